@@ -1,0 +1,404 @@
+"""Seeded synthetic workloads for the shape-gradient path.
+
+This module only *generates inputs*: grid node coordinates, scene
+descriptions (primitive records, the parameter map, the op tree and the two
+material levels), design vectors p and complex field planes.  It holds none of
+the method's arithmetic: no sigma_k, no fill fractions, no composition, no
+sensitivities.  Both the GPU path and the CPU oracle read what it produces,
+and nothing else is shared between them.
+
+Scene description (plain Python data, consumed by the C-ABI marshalling in
+``paper_2311_05646_amd._lib`` and, independently, by ``oracle.scene``):
+
+    {
+      "name": str,
+      "dim": 2 | 3,
+      "nodes": [X, Y, Z],        # float64 node coordinates (um), len N_a + 1;
+                                 # dim 2 uses Z = [0, 1] (one cell, unused)
+      "components": ("z",) | ("x", "y", "z"),   # E-field components sampled
+      "eps_bg": float, "eps_fg": float,         # background / shape material
+      "n_params": int,
+      "prims": [prim, ...],
+      "tree": {"op": "union"|"intersection"|"difference",
+               "children": [prim index | tree, ...]},
+    }
+
+    prim = {"type": "box"|"ellipse"|"poly"|"gcart",
+            "fields": [(a, b, idx), ...],   # value = a + b * p[idx]; idx < 0: a
+            "consts": [float, ...],         # gcart vertex x's; ellipse aspect
+            "nvert": int,
+            "bounded": [bx, by, bz],        # box: per axis; others: z only
+            "sigma": [(kind, kmode, k), x3]}
+
+Field order per type (paper Tab. ``autodiffgeo``):
+    box     : x0 x1 y0 y1 z0 z1                    sigma: x, y, z
+    ellipse : x0 y0 r z0 z1   consts (ax, ay)      sigma: boundary, -, z
+    poly    : x_1..x_N y_1..y_N z0 z1 (CCW)        sigma: boundary, -, z
+    gcart   : xs xe y+_1..y+_M y-_1..y-_M z0 z1    sigma: x-range, y, z
+              consts: vertex x_1 < ... < x_M
+
+sigma kinds: sigmoid, erf, sin, linear, quadratic (paper Tab.
+``nonlinearfunctions``); kmode "local" means k = k_r / (sample width along the
+argument's axis), "fixed" means k is used as given (1/um).
+
+Random numbers: numpy PCG64.  The geometry stream (seed + 1000) is drawn
+before the field stream (seed).  Fields are drawn component by component in
+the order E_re, E_im, A_re, A_im, each of shape (Nz, Ny, Nx).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+BASE_SEED = 231105646
+
+EPS_SIO2 = 1.444 ** 2
+EPS_SI = 3.4757 ** 2
+
+LIN = ("linear", "local", 1.0)
+
+
+def P(i, b=1.0, a=0.0):
+    """Field bound to design parameter i: a + b * p[i]."""
+    return (float(a), float(b), int(i))
+
+
+def K(v):
+    """Constant field."""
+    return (float(v), 0.0, -1)
+
+
+_NOF = (0.0, 0.0, -1)
+
+
+# ----------------------------------------------------------------- primitives
+def box(x=None, y=None, z=None, sig=(LIN, LIN, LIN)):
+    """Cuboid / Rect2D / Rect1D.  Each of x, y, z is a (lo, hi) pair of fields
+    or None for an axis along which the box is unbounded."""
+    fields, bounded = [], []
+    for iv in (x, y, z):
+        if iv is None:
+            fields += [_NOF, _NOF]
+            bounded.append(False)
+        else:
+            fields += [iv[0], iv[1]]
+            bounded.append(True)
+    return {"type": "box", "fields": fields, "consts": [], "nvert": 0,
+            "bounded": bounded, "sigma": [tuple(s) for s in sig]}
+
+
+def ellipse(x0, y0, r, aspect=(1.0, 1.0), z=None, sig=("sigmoid", "fixed", 50.0), sig_z=LIN):
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "ellipse", "fields": [x0, y0, r] + zf, "consts": [float(aspect[0]), float(aspect[1])],
+            "nvert": 0, "bounded": [True, True, z is not None],
+            "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
+
+
+def poly(xs, ys, z=None, sig=("sin", "fixed", 50.0), sig_z=LIN):
+    assert len(xs) == len(ys) and len(xs) >= 3
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "poly", "fields": list(xs) + list(ys) + zf, "consts": [], "nvert": len(xs),
+            "bounded": [True, True, z is not None], "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
+
+
+def gcart(xs, xe, xv, yp, ym, z=None, sig_x=LIN, sig_y=LIN, sig_z=LIN):
+    assert len(xv) == len(yp) == len(ym) and len(xv) >= 2
+    assert all(xv[i] < xv[i + 1] for i in range(len(xv) - 1))
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "gcart", "fields": [xs, xe] + list(yp) + list(ym) + zf,
+            "consts": [float(v) for v in xv], "nvert": len(xv),
+            "bounded": [True, True, z is not None], "sigma": [tuple(sig_x), tuple(sig_y), tuple(sig_z)]}
+
+
+# ----------------------------------------------------------------- grids
+def uniform_nodes(n, d, x0=0.0):
+    return x0 + d * np.arange(n + 1, dtype=np.float64)
+
+
+def graded_nodes(widths_nm, x0=0.0):
+    w = np.asarray(widths_nm, dtype=np.float64) * 1e-3
+    return x0 + np.concatenate([[0.0], np.cumsum(w)])
+
+
+def raised_cosine_widths(n, lo_nm, hi_nm, coarse_at_ends=True):
+    """Cell widths that vary smoothly between lo and hi over n cells:
+    coarse at the ends and fine in the middle (or the reverse)."""
+    i = np.arange(n, dtype=np.float64)
+    bump = 0.5 * (1.0 - np.cos(2.0 * np.pi * (i + 0.5) / n))
+    if coarse_at_ends:
+        return hi_nm - (hi_nm - lo_nm) * bump
+    return lo_nm + (hi_nm - lo_nm) * bump
+
+
+def safe_point(nodes, x, rng, window=(0.2, 0.3)):
+    """Move x inside the cell that holds it to a random spot a fraction
+    window (or 1 - window) of the cell width past its left node.  Keeps
+    parameters at least ~0.2 cell from every node and every cell midpoint, so
+    that central differences with small steps never straddle a kink of a
+    piecewise sigma on the lattice (input conditioning only)."""
+    i = int(np.clip(np.searchsorted(nodes, x, side="right") - 1, 0, len(nodes) - 2))
+    w = nodes[i + 1] - nodes[i]
+    f = rng.uniform(*window)
+    if rng.uniform() < 0.5:
+        f = 1.0 - f
+    return float(nodes[i] + f * w)
+
+
+# ----------------------------------------------------------------- fields
+def make_fields(scene, seed, dtype=np.complex64):
+    """E_fwd and E_adj as (C, Nz, Ny, Nx) complex arrays, re/im i.i.d. N(0,1)."""
+    X, Y, Z = scene["nodes"]
+    shape = (len(Z) - 1, len(Y) - 1, len(X) - 1)
+    C = len(scene["components"])
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rdt = np.float32 if dtype == np.complex64 else np.float64
+    E = np.empty((C,) + shape, dtype=dtype)
+    A = np.empty((C,) + shape, dtype=dtype)
+    for c in range(C):
+        E.real[c] = rng.standard_normal(shape, dtype=rdt)
+        E.imag[c] = rng.standard_normal(shape, dtype=rdt)
+        A.real[c] = rng.standard_normal(shape, dtype=rdt)
+        A.imag[c] = rng.standard_normal(shape, dtype=rdt)
+    return E, A
+
+
+def make_geps(scene, seed):
+    """An upstream dF/d(eps) plane set (C, Nz, Ny, Nx) float32, N(0,1)."""
+    X, Y, Z = scene["nodes"]
+    shape = (len(scene["components"]), len(Z) - 1, len(Y) - 1, len(X) - 1)
+    rng = np.random.Generator(np.random.PCG64(seed + 77))
+    return rng.standard_normal(shape, dtype=np.float32)
+
+
+# ----------------------------------------------------------------- configs
+def _wl_omega(lam_um):
+    return 2.0 * math.pi / lam_um
+
+
+def make_c1(seed=BASE_SEED + 0):
+    """2D plain method: 160x80 uniform 20 nm, Ez only; 8 union teeth on
+    cladding with x0/x1 of each tooth as parameters (16)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    X = uniform_nodes(160, 0.02)
+    Y = uniform_nodes(80, 0.02)
+    Z = np.array([0.0, 1.0])
+    prims, p = [], []
+    for t in range(8):
+        x0 = safe_point(X, 0.4 * t + rng.uniform(0.04, 0.16), rng)
+        x1 = safe_point(X, 0.4 * t + rng.uniform(0.24, 0.36), rng)
+        prims.append(box(x=(P(2 * t), P(2 * t + 1)), y=(K(0.6), K(1.0))))
+        p += [x0, x1]
+    scene = {"name": "c1", "dim": 2, "nodes": [X, Y, Z], "components": ("z",),
+             "eps_bg": 2.1, "eps_fg": 12.25, "n_params": 16, "prims": prims,
+             "tree": {"op": "union", "children": list(range(8))}}
+    E, A = make_fields(scene, seed, dtype=np.complex128)
+    return {"scene": scene, "p": np.array(p), "E": E, "A": A,
+            "omega": _wl_omega(1.55), "h": 1e-4}
+
+
+def c2_scene(rng, nx=4000, ny=600, n_periods=50, x_start=5.0, period=1.2):
+    X = graded_nodes(raised_cosine_widths(nx, 10.0, 25.0, coarse_at_ends=False))
+    Y = uniform_nodes(ny, 0.01)
+    Z = np.array([0.0, 1.0])
+    ym = Y[ny // 2]
+    ys0, ys1 = ym - 0.1063, ym + 0.1137
+    prims = [box(x=(K(1.0), K(X[-1] - 1.0)), y=(K(ys0), K(ys1)))]
+    etches, p = [], []
+    for q in range(n_periods):
+        xf0 = x_start + period * q + rng.uniform(0.0, 0.05)
+        xf1 = xf0 + rng.uniform(0.10, 0.30)
+        xs0 = xf1 + rng.uniform(0.05, 0.15)
+        xs1 = xs0 + rng.uniform(0.15, 0.40)
+        vals = [safe_point(X, v, rng) for v in (xf0, xf1, xs0, xs1)]
+        k = len(p)
+        etches.append(box(x=(P(k), P(k + 1)), y=(K(ys0), K(ys1))))
+        etches.append(box(x=(P(k + 2), P(k + 3)), y=(K(ym + 0.0437), K(ys1))))
+        p += vals
+    prims += etches
+    scene = {"name": "c2", "dim": 2, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "difference",
+                      "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}}
+    return scene, np.array(p)
+
+
+def make_c2(seed=BASE_SEED + 1, with_fields=True, **kw):
+    """2D multi-etch blazed grating: 4000x600, dx graded 10-25 nm, dy 10 nm,
+    slab minus union of 50 full and 50 shallow etches (200 edge params)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = c2_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.55), "h": 1e-5}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+def c3_scene(rng, nx=600, ny=240, nz=100, nvert=96, w_in=0.5, w_out=8.0,
+             x_a=1.013, x_b=22.013, y_m=4.807, noise=0.15):
+    X = uniform_nodes(nx, 0.04)
+    Y = uniform_nodes(ny, 0.04)
+    Z = graded_nodes(raised_cosine_widths(nz, 10.0, 40.0, coarse_at_ends=True))
+    zc = Z[nz // 2]
+    zr = (K(zc - 0.108), K(zc + 0.112))
+    xin = box(x=(K(-0.5), K(x_a)), y=(K(y_m - w_in / 2), K(y_m + w_in / 2)), z=zr)
+    xout = box(x=(K(x_b), K(X[-1] + 0.5)), y=(K(y_m - w_out / 2), K(y_m + w_out / 2)), z=zr)
+    xv = [x_a + (x_b - x_a) * i / (nvert - 1) for i in range(nvert)]
+    yp, ym, pu, pl = [], [], [], []
+    for i, x in enumerate(xv):
+        w = w_in + (w_out - w_in) * (x - x_a) / (x_b - x_a)
+        pu.append(y_m + w / 2 + rng.uniform(-noise, noise))
+        pl.append(y_m - w / 2 + rng.uniform(-noise, noise))
+        yp.append(P(i))
+        ym.append(P(nvert + i))
+    taper = gcart(K(x_a), K(x_b), xv, yp, ym, z=zr)
+    scene = {"name": "c3", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": 2 * nvert, "prims": [xin, taper, xout],
+             "tree": {"op": "union", "children": [0, 1, 2]}}
+    return scene, np.array(pu + pl)
+
+
+def make_c3(seed=BASE_SEED + 2, with_fields=True, **kw):
+    """3D non-adiabatic taper: 600x240x100, dz graded 10-40 nm; x-monotone
+    two-sided taper through 96 vertices per side (192 params) unioned with
+    input and output waveguide cuboids, extruded over a 220 nm slab."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = c3_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.31), "h": 1e-8}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+def c4_scene(rng, nside=40, nx=None, ny=None, nz=80, pitch=0.25, r_lo=0.06, r_hi=0.14,
+             jitter=0.02, aspect=1.15, dx=0.025, kr=4.0 * math.sqrt(2.0)):
+    nx = nside * int(round(pitch / dx)) if nx is None else nx
+    ny = nside * int(round(pitch / dx)) if ny is None else ny
+    X = uniform_nodes(nx, dx)
+    Y = uniform_nodes(ny, dx)
+    Z = uniform_nodes(nz, 0.025)
+    zc = Z[nz // 2]
+    zr = (K(zc - 0.1095), K(zc + 0.1105))
+    k = kr / dx
+    prims = [box(x=None, y=None, z=zr)]
+    p = []
+    for i in range(nside):
+        for j in range(nside):
+            cx = pitch / 2 + pitch * i + rng.uniform(-jitter, jitter)
+            cy = pitch / 2 + pitch * j + rng.uniform(-jitter, jitter)
+            r = rng.uniform(r_lo, r_hi)
+            q = len(p)
+            prims.append(ellipse(P(q), P(q + 1), P(q + 2), aspect=(aspect, 1.0 / aspect), z=zr,
+                                 sig=("sigmoid", "fixed", k)))
+            p += [cx, cy, r]
+    scene = {"name": "c4", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "difference",
+                      "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}}
+    return scene, np.array(p)
+
+
+def make_c4(seed=BASE_SEED + 3, with_fields=True, **kw):
+    """3D polarization-splitting grating: 400x400x80 at 25 nm; slab minus a
+    40x40 lattice of elliptical holes, (x, y, r) per hole (4800 params)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = c4_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.31), "h": 1e-7}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+# small variants of the same structure (several tiles, ragged tails)
+def make_c2_small(seed=BASE_SEED + 11):
+    return make_c2(seed, nx=300, ny=64, n_periods=3, x_start=1.2, period=1.0)
+
+
+def make_c3_small(seed=BASE_SEED + 12):
+    return make_c3(seed, nx=70, ny=30, nz=10, nvert=12, w_in=0.2, w_out=0.7,
+                   x_a=0.213, x_b=2.413, y_m=0.607, noise=0.03)
+
+
+def make_c4_small(seed=BASE_SEED + 13):
+    return make_c4(seed, nside=4, nx=45, ny=43, nz=12)
+
+
+def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
+    """A mixed scene that exercises every primitive type, every sigma kind,
+    both k modes, intersection and difference, shared and scaled parameter
+    references and extrusion parameters.  Not one of the paper's devices."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    X = graded_nodes(raised_cosine_widths(52, 18.0, 30.0))
+    Y = uniform_nodes(37, 0.025)
+    if dim == 3:
+        Z = graded_nodes(raised_cosine_widths(11, 15.0, 30.0))
+        zc = Z[5]
+    else:
+        Z = np.array([0.0, 1.0])
+        zc = None
+    u = lambda a, b: float(rng.uniform(a, b))
+    p, prims = [], []
+
+    def par(v, b=1.0):
+        p.append(v / b)
+        return P(len(p) - 1, b)
+
+    zr = None
+    if dim == 3:
+        zr = (par(zc - 0.09 + u(-0.004, 0.004)), K(zc + 0.1))
+    # convex pentagon, sin sigma
+    cx, cy, R = 0.35, 0.30, 0.17
+    xs, ys = [], []
+    for i in range(5):
+        th = 2 * math.pi * i / 5 + 0.3
+        xs.append(par(cx + R * math.cos(th) + u(-0.01, 0.01)))
+        ys.append(par(cy + R * math.sin(th) + u(-0.01, 0.01)))
+    prims.append(poly(xs, ys, z=zr, sig=("sin", "fixed", 45.0)))
+    # ellipse, erf sigma, radius through a scaled reference
+    prims.append(ellipse(par(0.95 + u(-.02, .02)), par(0.62 + u(-.02, .02)), par(0.14, b=-0.5),
+                         aspect=(1.3, 0.8), z=zr, sig=("erf", "fixed", 30.0)))
+    # box, quadratic local sigma
+    bx0 = par(0.62 + u(-.02, .02))
+    prims.append(box(x=(bx0, par(0.88 + u(-.02, .02))), y=(par(0.10 + u(-.01, .01)), K(0.31)),
+                     z=None if dim == 2 else (K(zc - 0.12), par(zc + 0.11)),
+                     sig=(("quadratic", "local", 1.0), ("quadratic", "local", 1.0), LIN)))
+    # gcart, linear y / sigmoid x-range
+    nv = 6
+    xv = [0.15 + 0.5 * i / (nv - 1) for i in range(nv)]
+    yp = [par(0.72 + u(-0.03, 0.03)) for _ in range(nv)]
+    ym = [par(0.58 + u(-0.03, 0.03)) for _ in range(nv)]
+    prims.append(gcart(par(0.17), K(0.63), xv, yp, ym, z=zr,
+                       sig_x=("sigmoid", "fixed", 60.0), sig_y=("linear", "local", 1.0)))
+    # two boxes for an intersection; one shares bx0 with the quadratic box
+    prims.append(box(x=(bx0, K(1.10)), y=(K(0.38), par(0.80 + u(-.02, .02))),
+                     z=None if dim == 2 else (K(zc - 0.08), K(zc + 0.08)),
+                     sig=(("sigmoid", "local", 3.0), ("erf", "local", 1.5), LIN)))
+    prims.append(box(x=(par(0.80 + u(-.02, .02)), K(1.25)), y=(K(0.20), K(0.70)),
+                     z=None if dim == 2 else (K(zc - 0.1), K(zc + 0.1)),
+                     sig=(("linear", "local", 1.0), ("sin", "local", 1.2), LIN)))
+    if root == "union":
+        tree = {"op": "union", "children": [{"op": "union", "children": [0, 1, 2, 3]},
+                                            {"op": "intersection", "children": [4, 5]}]}
+    elif root == "difference":
+        tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4]},
+                                                 {"op": "union", "children": [1, 5]}]}
+    else:
+        tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5]},
+                                                   {"op": "union", "children": [4]}]}
+    scene = {"name": f"zoo{dim}d_{root}", "dim": dim, "nodes": [X, Y, Z],
+             "components": ("x", "y", "z"), "eps_bg": 2.25, "eps_fg": 11.7,
+             "n_params": len(p), "prims": prims, "tree": tree}
+    out = {"scene": scene, "p": np.array(p), "omega": 2 * math.pi / 1.4, "h": 1e-7}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+CONFIGS = {
+    "c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4,
+    "c2_small": make_c2_small, "c3_small": make_c3_small, "c4_small": make_c4_small,
+}
+
+
+def n_samples(scene):
+    X, Y, Z = scene["nodes"]
+    return len(scene["components"]) * (len(X) - 1) * (len(Y) - 1) * (len(Z) - 1)
