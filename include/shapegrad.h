@@ -1,0 +1,189 @@
+/*
+ * shapegrad.h -- C ABI of the MI355X shape-parameter gradient library.
+ *
+ * The library implements steps 2 and 5 of the adjoint inverse-design loop
+ * (Sec. "Background on photonic inverse design and the adjoint method"):
+ *   step 2: design vector v (here p, n FP64 values) -> permittivity eps(p) on a
+ *           rectilinear grid, built from AutoDiffGeo primitives (Sec.
+ *           "AutoDiffGeo", Tab. autodiffgeo) rasterized to fill fractions with
+ *           sigma_k (Tab. nonlinearfunctions), combined by eq:union,
+ *           eq:intersection and difference, and scaled to two materials;
+ *   step 5: the adjoint gradient of eq:1 (epsilon term),
+ *           grad_k = sum over components c and samples j of
+ *                    Re(c0 * E_cj * Eadj_cj) * d eps_cj / d p_k,  c0 = -2i*omega,
+ *           computed in reverse mode (eq:AD, eq:jaceps) without forming the
+ *           Jacobian, or by finite differences (the paper's baseline).
+ * The fields E and E_adj are given inputs (Sec. "Background": the simulators
+ * are out of scope).
+ *
+ * Conventions shared by every call
+ *   - Every function returns sg_status: SG_OK (0), SG_EAGAIN (1, serving only)
+ *     or a negative error.  Nothing throws across the ABI and nothing exits.
+ *     sg_last_error() returns a thread-local message for the last failure on
+ *     the calling thread (valid until that thread's next call).
+ *   - Planes are FP32 (eps, dF/deps) or complex64 (interleaved re, im) arrays
+ *     of shape [Nz][Ny][Nx], x fastest; a component set is C planes.  All plane
+ *     pointers are device memory owned by the caller.
+ *   - Component c of a set is the field component along axis comp_axis[c];
+ *     it samples the material at the cell center along its own axis and at the
+ *     cell's lower node along the other axes (staggered Yee positions).
+ *   - p: n_params FP64, on the host (p_on_device = 0, copied before the call
+ *     returns) or on the device (1, read by the call's stream work).
+ *   - grad: n_params FP64, overwritten.  On the host (grad_on_device = 0) the
+ *     call blocks until the result is there; on the device it is asynchronous.
+ *   - stream: a hipStream_t (NULL = the default stream).  Device work is
+ *     ordered on it.  Calls on one scene must be ordered on one stream (a
+ *     scene owns its staging buffers); use one scene per concurrent stream.
+ *   - Invalid input (null pointer, size or index out of range, NaN in p,
+ *     unknown type) is rejected on the host before any launch (SG_E_INVALID).
+ *     HIP failures return SG_E_DEVICE on this call or the next.
+ */
+#ifndef SHAPEGRAD_H
+#define SHAPEGRAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sg_status;
+enum {
+    SG_OK = 0,
+    SG_EAGAIN = 1,
+    SG_E_INVALID = -1,
+    SG_E_NOMEM = -2,
+    SG_E_TOO_LARGE = -3,
+    SG_E_DEVICE = -4,
+    SG_E_CANCELLED = -5,
+    SG_E_TIMEOUT = -6,
+    SG_E_UNSUPPORTED = -7
+};
+
+/* Primitive types (Tab. autodiffgeo).  Field order per type:
+ *   SG_PRIM_BOX     x0 x1 y0 y1 z0 z1           RectdD = product of Rect1D per bounded axis
+ *                                               sigma[0..2] = x, y, z
+ *   SG_PRIM_ELLIPSE x0 y0 r z0 z1               Circ2D with aspect transform:
+ *                                               sigma_k(r - rho), rho = |((x-x0)/ax, (y-y0)/ay)|
+ *                                               consts: ax ay; sigma[0] boundary (FIXED k), sigma[2] z
+ *   SG_PRIM_POLY    x_1..x_N y_1..y_N z0 z1     Poly2D: product of Step2D over the edges of a
+ *                                               convex counter-clockwise polygon (inward normals)
+ *                                               sigma[0] boundary (FIXED k), sigma[2] z
+ *   SG_PRIM_GCART   xs xe y+_1..y+_M y-_1..y-_M z0 z1
+ *                                               two-sided GeneralCartesian2D:
+ *                                               Rect1D(x; xs, xe) sigma_k(f+(x) - y) sigma_k(y - f-(x))
+ *                                               with f+- piecewise linear through (x_j, y+-_j),
+ *                                               constant beyond the end vertices;
+ *                                               consts: x_1 < ... < x_M; sigma[0] x-range,
+ *                                               sigma[1] y boundary, sigma[2] z
+ * z0 z1 are the extrusion along z (Rect1D in z), used when bounded[2] != 0.
+ * In 2D scenes (dim = 2) nothing may be bounded along z. */
+enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3 };
+
+/* sigma_k kinds (Tab. nonlinearfunctions).  sigmoid and erf are taken as exactly
+ * 0 / 1 beyond |k x| = 24 / 6 (tails below 4e-11 / 2e-17). */
+enum { SG_SIGMA_SIGMOID = 0, SG_SIGMA_ERF = 1, SG_SIGMA_SIN = 2, SG_SIGMA_LINEAR = 3, SG_SIGMA_QUADRATIC = 4 };
+/* k modes: LOCAL k = k / (sample width along the argument's axis); FIXED k as given (1/um). */
+enum { SG_K_LOCAL = 0, SG_K_FIXED = 1 };
+/* op-tree nodes: union min{1, sum} (eq:union), intersection max{N-1, sum} - (N-1)
+ * (eq:intersection), difference max{0, a - b} (exactly two operands). */
+enum { SG_OP_UNION = 0, SG_OP_INTERSECTION = 1, SG_OP_DIFFERENCE = 2 };
+/* finite-difference schemes for eps_grad_fd */
+enum { SG_FD_CENTRAL = 0, SG_FD_FORWARD = 1 };
+
+typedef struct sg_field { double a; double b; int64_t idx; } sg_field;   /* a + b * p[idx]; idx < 0: a */
+typedef struct sg_sigma { int32_t kind; int32_t kmode; double k; } sg_sigma;
+
+typedef struct sg_prim_desc {
+    int32_t type;
+    int32_t nvert;        /* POLY: N (>= 3); GCART: M (>= 2); else 0 */
+    int32_t field_off;    /* first field in sg_scene_desc.fields */
+    int32_t nfield;       /* BOX 6, ELLIPSE 5, POLY 2N+2, GCART 2M+4 */
+    int32_t const_off;    /* first constant in sg_scene_desc.consts */
+    int32_t nconst;       /* ELLIPSE 2, GCART M, else 0 */
+    int32_t bounded[3];   /* BOX: per axis; others: [2] = extruded along z */
+    int32_t pad;
+    sg_sigma sigma[3];
+} sg_prim_desc;
+
+typedef struct sg_node_desc {
+    int32_t op;
+    int32_t nchild;
+    int32_t child_off;    /* into sg_scene_desc.children */
+    int32_t pad;
+} sg_node_desc;
+
+typedef struct sg_scene_desc {
+    int32_t dim;              /* 2 or 3 */
+    int32_t ncomp;            /* 1..3 */
+    int32_t comp_axis[3];     /* 0 = x, 1 = y, 2 = z */
+    int32_t pad0;
+    int64_t n[3];             /* Nx, Ny, Nz cells (Nz = 1 when dim = 2) */
+    const double* nodes[3];   /* node coordinates in um, n[a] + 1 each, increasing */
+    double eps_bg;            /* background permittivity */
+    double eps_fg;            /* shape permittivity */
+    int64_t n_params;
+    int32_t nprim, nfield, nconst, nnode, nchild, pad1;
+    const sg_prim_desc* prims;
+    const sg_field* fields;
+    const double* consts;
+    const sg_node_desc* nodes_op;   /* postfix order, root last */
+    const int32_t* children;        /* >= 0: primitive; < 0: node -(c + 1), earlier in the list */
+} sg_scene_desc;
+
+typedef struct sg_ctx sg_ctx;
+typedef struct sg_scene sg_scene;
+
+/* Context on one HIP device.  Thread-safe for distinct scenes. */
+sg_status sg_ctx_create(int hip_device, sg_ctx** out);
+void sg_ctx_destroy(sg_ctx* ctx);
+const char* sg_last_error(void);
+
+/* Compile a scene description (copied; the caller's arrays may be freed after
+ * the call) into device tables.  Trees may nest one level below the root:
+ * root = op(children), each child a primitive or a node whose children are all
+ * primitives; at most 4 such groups and 8 distinct extrusion classes.
+ * Deeper trees return SG_E_UNSUPPORTED. */
+sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* desc, sg_scene** out);
+void sg_scene_destroy(sg_scene* scene);
+sg_status sg_scene_info(const sg_scene* scene, int64_t* n_params, int32_t* ncomp, int64_t dims[3]);
+/* Launch shape override: block width in x (16, 32, 64, 128 or 256 samples; the
+ * block holds 256 samples) and the number of segments each sample column is
+ * split into (>= 1).  0 keeps the library's choice. */
+sg_status sg_scene_set_launch(sg_scene* scene, int32_t block_x, int32_t col_segments);
+
+/* Step 2 (Sec. "Background"; eq:eps): eps[C][Nz][Ny][Nx] FP32 = eps_bg +
+ * (eps_fg - eps_bg) * s(p), with s composed in FP64 and rounded once. */
+sg_status eps_build(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                    float* eps, void* stream);
+
+/* Step 5, fused (eq:1, eq:AD): e_fwd and e_adj are arrays of C device pointers
+ * to complex64 planes.  grad_k = sum_c sum_j 2*omega*Im(E_cj Eadj_cj) d eps_cj/d p_k
+ * (no conjugation). */
+sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                       const void* const* e_fwd, const void* const* e_adj, double omega,
+                       double* grad, int grad_on_device, void* stream);
+
+/* Reverse mode with an upstream dF/deps: grad_eps is C FP32 planes stored
+ * contiguously ([C][Nz][Ny][Nx]); grad_k = sum grad_eps * d eps / d p_k. */
+sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                            const float* grad_eps, double* grad, int grad_on_device, void* stream);
+
+/* Finite-difference baseline (Sec. "Background", Sec. "Automatic differentiation
+ * based acceleration"): for every k, re-rasterize the whole grid at p +- h e_k
+ * (SG_FD_CENTRAL, 2n rasterizations) or at p + h e_k against p (SG_FD_FORWARD,
+ * the paper's n + 1 form), write the difference plane (FP64 difference, stored
+ * FP32), then reduce sum_j g_j * diff_j / (2h or h) with g = 2*omega*Im(E Eadj).
+ * h in um (> 0).  Uses 2 C-plane FP32 work buffers owned by the scene. */
+sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                      const void* const* e_fwd, const void* const* e_adj, double omega,
+                      double h, int scheme, double* grad, int grad_on_device, void* stream);
+
+/* Plain device-to-device copy (bytes a multiple of 16) on `stream`; a
+ * reference kernel of known traffic for calibrating HBM byte counters. */
+sg_status sg_util_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHAPEGRAD_H */

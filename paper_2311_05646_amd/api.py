@@ -1,0 +1,173 @@
+"""Python binding of the C-ABI (argument marshalling only; every step of the
+path runs in the HIP kernels of libshapegrad.so).  PyTorch supplies device
+memory and the current HIP stream.
+
+    scene = Scene(desc)                     # desc: see paper_2311_05646_amd.workloads
+    eps = eps_build(scene, p)               # (C, Nz, Ny, Nx) float32 on the GPU
+    g = eps_grad_vjp(scene, p, E, A, omega) # eq:1 / eq:AD fused adjoint gradient
+    g = eps_grad_vjp_geps(scene, p, dFdeps) # reverse mode with an upstream dF/deps
+    g = eps_grad_fd(scene, p, E, A, omega, h)  # finite-difference baseline
+    eps = EpsBuild.apply(p_tensor, scene)   # autograd; backward = eps_grad_vjp_geps
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+_CTX = {}
+
+
+def context(device=0):
+    if device not in _CTX:
+        h = C.c_void_p()
+        check(lib().sg_ctx_create(int(device), C.byref(h)))
+        _CTX[device] = h
+    return _CTX[device]
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Scene:
+    """A compiled scene (device tables) on one GPU."""
+
+    def __init__(self, desc, device=0):
+        self.desc = desc
+        self.device = device
+        self.ctx = context(device)
+        sd, keep = _lib.marshal_scene(desc)
+        h = C.c_void_p()
+        check(lib().sg_scene_create(self.ctx, C.byref(sd), C.byref(h)))
+        self.handle = h
+        n = C.c_int64()
+        nc = C.c_int32()
+        dims = (C.c_int64 * 3)()
+        check(lib().sg_scene_info(h, C.byref(n), C.byref(nc), dims))
+        self.n_params = n.value
+        self.ncomp = nc.value
+        self.dims = tuple(dims)                       # (Nx, Ny, Nz)
+        self.shape = (self.ncomp, dims[2], dims[1], dims[0])
+
+    def set_launch(self, block_x=0, col_segments=0):
+        check(lib().sg_scene_set_launch(self.handle, int(block_x), int(col_segments)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sg_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _p_arg(scene, p):
+    """(pointer, on_device, keepalive) for p (numpy/list on host, or a CUDA
+    float64 tensor)."""
+    if isinstance(p, torch.Tensor) and p.is_cuda:
+        if p.dtype != torch.float64 or not p.is_contiguous() or p.numel() != scene.n_params:
+            raise ValueError("device p must be a contiguous float64 tensor of n_params")
+        return C.c_void_p(p.data_ptr()), 1, p
+    a = np.ascontiguousarray(np.asarray(p.detach().cpu() if isinstance(p, torch.Tensor) else p, dtype=np.float64))
+    if a.size != scene.n_params:
+        raise ValueError(f"p has {a.size} values, the scene has {scene.n_params} parameters")
+    return C.c_void_p(a.ctypes.data), 0, a
+
+
+def _plane_ptrs(scene, F):
+    if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.complex64 and F.is_contiguous()):
+        raise ValueError("fields must be contiguous complex64 CUDA tensors")
+    if tuple(F.shape) != scene.shape:
+        raise ValueError(f"field shape {tuple(F.shape)} != {scene.shape}")
+    step = F[0].numel() * 8
+    base = F.data_ptr()
+    return (C.c_void_p * 3)(*[base + c * step for c in range(scene.ncomp)] + [0] * (3 - scene.ncomp))
+
+
+def _grad_out(scene, p_dev, grad, device):
+    if grad is not None:
+        if not (grad.is_cuda and grad.dtype == torch.float64 and grad.numel() == scene.n_params):
+            raise ValueError("grad must be a float64 CUDA tensor of n_params")
+        return grad, C.c_void_p(grad.data_ptr()), 1
+    if p_dev:
+        g = torch.empty(scene.n_params, dtype=torch.float64, device=device)
+        return g, C.c_void_p(g.data_ptr()), 1
+    g = np.empty(scene.n_params, dtype=np.float64)
+    return g, C.c_void_p(g.ctypes.data), 0
+
+
+def eps_build(scene, p, out=None, stream=None):
+    dev = torch.device("cuda", scene.device)
+    if out is None:
+        out = torch.empty(scene.shape, dtype=torch.float32, device=dev)
+    elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and tuple(out.shape) == scene.shape):
+        raise ValueError("out must be a contiguous float32 CUDA tensor of the scene's plane shape")
+    pp, pdev, keep = _p_arg(scene, p)
+    check(lib().eps_build(scene.ctx, scene.handle, pp, pdev, C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def eps_grad_vjp(scene, p, E, A, omega, grad=None, stream=None):
+    dev = torch.device("cuda", scene.device)
+    pp, pdev, keep = _p_arg(scene, p)
+    fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_vjp(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), gp, gdev, _stream(stream)))
+    return g
+
+
+def eps_grad_vjp_geps(scene, p, geps, grad=None, stream=None):
+    dev = torch.device("cuda", scene.device)
+    if not (geps.is_cuda and geps.dtype == torch.float32 and geps.is_contiguous() and tuple(geps.shape) == scene.shape):
+        raise ValueError("grad_eps must be a contiguous float32 CUDA tensor of the scene's plane shape")
+    pp, pdev, keep = _p_arg(scene, p)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_vjp_geps(scene.ctx, scene.handle, pp, pdev, C.c_void_p(geps.data_ptr()), gp, gdev,
+                                  _stream(stream)))
+    return g
+
+
+def eps_grad_fd(scene, p, E, A, omega, h, scheme="central", grad=None, stream=None):
+    dev = torch.device("cuda", scene.device)
+    pp, pdev, keep = _p_arg(scene, p)
+    fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_fd(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), float(h),
+                            _lib.FD_SCHEME[scheme], gp, gdev, _stream(stream)))
+    return g
+
+
+def util_copy(dst, src, stream=None):
+    n = src.numel() * src.element_size()
+    check(lib().sg_util_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n, _stream(stream)))
+
+
+class EpsBuild(torch.autograd.Function):
+    """eps(p) as a differentiable op: forward = eps_build, backward = the
+    fused reverse-mode kernel (eps_grad_vjp_geps) that recomputes
+    d eps / d p in registers instead of forming the Jacobian (eq:AD)."""
+
+    @staticmethod
+    def forward(ctx, p, scene):
+        pd = p.detach()
+        if not pd.is_cuda:
+            pd = pd.to(device=torch.device("cuda", scene.device))
+        pd = pd.to(torch.float64).contiguous()
+        ctx.scene = scene
+        ctx.save_for_backward(pd)
+        ctx.p_device = p.device
+        return eps_build(scene, pd)
+
+    @staticmethod
+    def backward(ctx, grad_eps):
+        (pd,) = ctx.saved_tensors
+        g = eps_grad_vjp_geps(ctx.scene, pd, grad_eps.to(torch.float32).contiguous())
+        return g.to(ctx.p_device), None

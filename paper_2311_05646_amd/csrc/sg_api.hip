@@ -1,0 +1,783 @@
+// Host runtime of the C ABI declared in include/shapegrad.h: error state,
+// contexts, the scene compiler (description -> device tables), staging of p
+// and the entry points that enqueue the kernels of sg_kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "sg_device.h"
+#include "sg_internal.h"
+
+using namespace sg;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static sg_status fail(sg_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(SG_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char* sg_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ context
+struct sg_ctx {
+    int device;
+};
+
+extern "C" sg_status sg_ctx_create(int hip_device, sg_ctx** out) {
+    if (!out) return fail(SG_E_INVALID, "sg_ctx_create: out is NULL");
+    int n = 0;
+    HIP_OK(hipGetDeviceCount(&n));
+    if (hip_device < 0 || hip_device >= n) return fail(SG_E_INVALID, "sg_ctx_create: device %d of %d", hip_device, n);
+    auto* c = new (std::nothrow) sg_ctx;
+    if (!c) return fail(SG_E_NOMEM, "sg_ctx_create: out of host memory");
+    c->device = hip_device;
+    *out = c;
+    return SG_OK;
+}
+
+extern "C" void sg_ctx_destroy(sg_ctx* ctx) { delete ctx; }
+
+// ------------------------------------------------------------------ scene
+struct sg_scene {
+    sg_ctx* ctx = nullptr;
+    int dim = 0, ncomp = 0, comp_axis[3] = {0, 0, 0};
+    int64_t n[3] = {0, 0, 0};
+    int64_t n_params = 0;
+    int64_t nfield = 0;
+    double eps_bg = 0, eps_fg = 0;
+    int col = 2;                      // column axis: 1 (y) or 2 (z)
+    int axis_v = 1;
+    int nu = 0, nv = 0, nw = 0;
+    int64_t sv = 0, sw = 0, plane = 0;
+    int nprim = 0, nclass = 0, ncls_pad = 1;
+    int ngroup = 0, root_op = ROOT_NONE;
+    int group_op[kMaxGroups] = {0, 0, 0, 0};
+    double group_nm1[kMaxGroups] = {0, 0, 0, 0};
+    double root_nm1 = 0;
+    std::vector<DevClass> classes;
+    std::vector<sg_field> fields;
+    int block_x = 0, nseg = 0;        // 0: automatic
+    // device tables
+    double* d_lat = nullptr;          // per component: uc uw vc vw wc ww
+    int64_t lat_off[kMaxComp][6] = {};
+    sg_field* d_fref = nullptr;
+    DevPrim* d_prims = nullptr;
+    DevClass* d_cls = nullptr;
+    double* d_consts = nullptr;
+    double* d_p = nullptr;
+    double* d_fval[2] = {nullptr, nullptr};
+    double4* d_bbox[2] = {nullptr, nullptr};
+    double* d_ztab[2] = {nullptr, nullptr};
+    double* d_grad = nullptr;
+    float* d_work[2] = {nullptr, nullptr};
+    double* h_p = nullptr;            // pinned staging
+    double* h_grad = nullptr;
+    hipEvent_t p_evt = nullptr;
+    bool p_evt_pending = false;
+    std::mutex mu;
+};
+
+static void axis_samples(const double* A, int64_t N, bool cell, std::vector<double>& c, std::vector<double>& w) {
+    c.resize(N);
+    w.resize(N);
+    for (int64_t i = 0; i < N; ++i) {
+        const double wi = A[i + 1] - A[i];
+        if (cell) {
+            c[i] = 0.5 * (A[i] + A[i + 1]);
+            w[i] = wi;
+        } else {
+            const double wl = (i == 0) ? wi : (A[i] - A[i - 1]);
+            c[i] = A[i];
+            w[i] = 0.5 * (wl + wi);
+        }
+    }
+}
+
+static void free_scene(sg_scene* s) {
+    if (!s) return;
+    hipFree(s->d_lat);
+    hipFree(s->d_fref);
+    hipFree(s->d_prims);
+    hipFree(s->d_cls);
+    hipFree(s->d_consts);
+    hipFree(s->d_p);
+    for (int i = 0; i < 2; ++i) {
+        hipFree(s->d_fval[i]);
+        hipFree(s->d_bbox[i]);
+        hipFree(s->d_ztab[i]);
+        hipFree(s->d_work[i]);
+    }
+    hipFree(s->d_grad);
+    if (s->h_p) hipHostFree(s->h_p);
+    if (s->h_grad) hipHostFree(s->h_grad);
+    if (s->p_evt) hipEventDestroy(s->p_evt);
+    delete s;
+}
+
+extern "C" void sg_scene_destroy(sg_scene* s) {
+    if (!s) return;
+    hipSetDevice(s->ctx->device);
+    hipDeviceSynchronize();
+    free_scene(s);
+}
+
+static bool valid_sigma(const sg_sigma& s) {
+    return s.kind >= SG_SIGMA_SIGMOID && s.kind <= SG_SIGMA_QUADRATIC && (s.kmode == SG_K_LOCAL || s.kmode == SG_K_FIXED) &&
+           std::isfinite(s.k) && s.k > 0.0;
+}
+
+static int expected_nfield(const sg_prim_desc& p) {
+    switch (p.type) {
+        case SG_PRIM_BOX: return 6;
+        case SG_PRIM_ELLIPSE: return 5;
+        case SG_PRIM_POLY: return 2 * p.nvert + 2;
+        case SG_PRIM_GCART: return 2 * p.nvert + 4;
+        default: return -1;
+    }
+}
+
+// Field index (relative to the primitive) of the z extrusion bounds.
+static int zfield(const sg_prim_desc& p) {
+    switch (p.type) {
+        case SG_PRIM_BOX: return 4;
+        case SG_PRIM_ELLIPSE: return 3;
+        case SG_PRIM_POLY: return 2 * p.nvert;
+        default: return 2 * p.nvert + 2;
+    }
+}
+
+struct ColSpec {
+    int bounded;
+    sg_field lo, hi;
+    int kind, kmode;
+    double k;
+    bool operator==(const ColSpec& o) const {
+        if (bounded != o.bounded) return false;
+        if (!bounded) return true;
+        return lo.a == o.lo.a && lo.b == o.lo.b && lo.idx == o.lo.idx && hi.a == o.hi.a && hi.b == o.hi.b &&
+               hi.idx == o.hi.idx && kind == o.kind && kmode == o.kmode && k == o.k;
+    }
+};
+
+extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_scene** out) {
+    if (!ctx || !d || !out) return fail(SG_E_INVALID, "sg_scene_create: NULL argument");
+    *out = nullptr;
+    if (d->dim != 2 && d->dim != 3) return fail(SG_E_INVALID, "dim must be 2 or 3");
+    if (d->ncomp < 1 || d->ncomp > 3) return fail(SG_E_INVALID, "ncomp must be 1..3");
+    for (int c = 0; c < d->ncomp; ++c)
+        if (d->comp_axis[c] < 0 || d->comp_axis[c] > 2) return fail(SG_E_INVALID, "comp_axis out of range");
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1 || d->n[a] > (1 << 24)) return fail(SG_E_INVALID, "n[%d] out of range", a);
+        if (!d->nodes[a]) return fail(SG_E_INVALID, "nodes[%d] is NULL", a);
+        for (int64_t i = 0; i < d->n[a]; ++i)
+            if (!(d->nodes[a][i + 1] > d->nodes[a][i])) return fail(SG_E_INVALID, "nodes[%d] not increasing", a);
+    }
+    if (d->dim == 2 && d->n[2] != 1) return fail(SG_E_INVALID, "2D scenes have n[2] = 1");
+    const int64_t plane = d->n[0] * d->n[1] * d->n[2];
+    if (plane > ((int64_t)1 << 31)) return fail(SG_E_TOO_LARGE, "grid too large");
+    if (d->n_params < 0) return fail(SG_E_INVALID, "n_params < 0");
+    if (d->nprim < 1 || !d->prims) return fail(SG_E_INVALID, "no primitives");
+    if (d->nfield < 0 || (d->nfield > 0 && !d->fields)) return fail(SG_E_INVALID, "fields");
+    if (d->nconst < 0 || (d->nconst > 0 && !d->consts)) return fail(SG_E_INVALID, "consts");
+    if (d->nnode < 1 || !d->nodes_op) return fail(SG_E_INVALID, "no op nodes");
+    if (d->nchild < 1 || !d->children) return fail(SG_E_INVALID, "no children");
+    for (int f = 0; f < d->nfield; ++f) {
+        const sg_field& r = d->fields[f];
+        if (r.idx >= d->n_params) return fail(SG_E_INVALID, "field %d references p[%lld] of %lld", f, (long long)r.idx,
+                                              (long long)d->n_params);
+        if (!std::isfinite(r.a) || !std::isfinite(r.b)) return fail(SG_E_INVALID, "field %d not finite", f);
+    }
+    // primitives
+    for (int i = 0; i < d->nprim; ++i) {
+        const sg_prim_desc& p = d->prims[i];
+        const int nf = expected_nfield(p);
+        if (nf < 0) return fail(SG_E_INVALID, "primitive %d: unknown type %d", i, p.type);
+        if (p.type == SG_PRIM_POLY && (p.nvert < 3 || p.nvert > 64)) return fail(SG_E_INVALID, "poly %d: nvert", i);
+        if (p.type == SG_PRIM_GCART && (p.nvert < 2 || p.nvert > 100000)) return fail(SG_E_INVALID, "gcart %d: nvert", i);
+        if (p.nfield != nf) return fail(SG_E_INVALID, "primitive %d: nfield %d, expected %d", i, p.nfield, nf);
+        if (p.field_off < 0 || p.field_off + nf > d->nfield) return fail(SG_E_INVALID, "primitive %d: fields", i);
+        const int nc = p.type == SG_PRIM_ELLIPSE ? 2 : (p.type == SG_PRIM_GCART ? p.nvert : 0);
+        if (p.nconst != nc || p.const_off < 0 || p.const_off + nc > d->nconst)
+            return fail(SG_E_INVALID, "primitive %d: consts", i);
+        const int nsig = p.type == SG_PRIM_BOX || p.type == SG_PRIM_GCART ? 3 : 1;
+        for (int a = 0; a < 3; ++a) {
+            const bool used = (a < nsig) || (a == 2);
+            const bool bnd = p.type == SG_PRIM_BOX ? p.bounded[a] != 0 : (a < 2 || p.bounded[2] != 0);
+            if (used && bnd && !valid_sigma(p.sigma[a])) return fail(SG_E_INVALID, "primitive %d: sigma[%d]", i, a);
+        }
+        if (d->dim == 2 && p.bounded[2]) return fail(SG_E_INVALID, "primitive %d: bounded along z in a 2D scene", i);
+        if ((p.type == SG_PRIM_ELLIPSE || p.type == SG_PRIM_POLY) && p.sigma[0].kmode != SG_K_FIXED)
+            return fail(SG_E_INVALID, "primitive %d: radial/oblique boundary needs a FIXED k", i);
+        if (p.type == SG_PRIM_ELLIPSE) {
+            const double ax = d->consts[p.const_off], ay = d->consts[p.const_off + 1];
+            if (!(ax > 0) || !(ay > 0)) return fail(SG_E_INVALID, "ellipse %d: aspect must be > 0", i);
+        }
+        if (p.type == SG_PRIM_GCART)
+            for (int j = 0; j + 1 < p.nvert; ++j)
+                if (!(d->consts[p.const_off + j + 1] > d->consts[p.const_off + j]))
+                    return fail(SG_E_INVALID, "gcart %d: vertex x not increasing", i);
+    }
+    // tree -> groups
+    struct Group { int op; std::vector<int> prims; int nmember; };
+    std::vector<Group> groups;
+    const sg_node_desc& root = d->nodes_op[d->nnode - 1];
+    auto child = [&](const sg_node_desc& nd, int c) -> int { return d->children[nd.child_off + c]; };
+    for (int k = 0; k < d->nnode; ++k) {
+        const sg_node_desc& nd = d->nodes_op[k];
+        if (nd.op < SG_OP_UNION || nd.op > SG_OP_DIFFERENCE) return fail(SG_E_INVALID, "node %d: op", k);
+        if (nd.nchild < 1 || nd.child_off < 0 || nd.child_off + nd.nchild > d->nchild)
+            return fail(SG_E_INVALID, "node %d: children", k);
+        if (nd.op == SG_OP_DIFFERENCE && nd.nchild != 2) return fail(SG_E_INVALID, "node %d: difference takes 2", k);
+        for (int c = 0; c < nd.nchild; ++c) {
+            const int ch = child(nd, c);
+            if (ch >= d->nprim) return fail(SG_E_INVALID, "node %d: primitive %d out of range", k, ch);
+            if (ch < 0 && -(ch + 1) >= k) return fail(SG_E_INVALID, "node %d: child node must come earlier", k);
+        }
+    }
+    std::vector<int> used(d->nprim, 0);
+    auto leaf_group = [&](int nodeidx, Group& g) -> sg_status {
+        const sg_node_desc& nd = d->nodes_op[nodeidx];
+        if (nd.op == SG_OP_DIFFERENCE)
+            return fail(SG_E_UNSUPPORTED, "a difference below the root is not supported by the GPU path");
+        g.op = nd.op;
+        g.nmember = nd.nchild;
+        for (int c = 0; c < nd.nchild; ++c) {
+            const int ch = child(nd, c);
+            if (ch < 0) return fail(SG_E_UNSUPPORTED, "op trees deeper than root -> node -> primitive");
+            g.prims.push_back(ch);
+        }
+        return SG_OK;
+    };
+    int root_op;
+    if (root.op == SG_OP_DIFFERENCE) {
+        root_op = SG_OP_DIFFERENCE;
+        for (int c = 0; c < 2; ++c) {
+            Group g;
+            const int ch = child(root, c);
+            if (ch >= 0) {
+                g.op = SG_OP_UNION;
+                g.nmember = 1;
+                g.prims.push_back(ch);
+            } else {
+                sg_status st = leaf_group(-(ch + 1), g);
+                if (st != SG_OK) return st;
+            }
+            groups.push_back(g);
+        }
+    } else {
+        Group direct;
+        direct.op = root.op;
+        direct.nmember = 0;
+        std::vector<Group> nodes;
+        for (int c = 0; c < root.nchild; ++c) {
+            const int ch = child(root, c);
+            if (ch >= 0) {
+                direct.prims.push_back(ch);
+                direct.nmember++;
+            } else {
+                Group g;
+                sg_status st = leaf_group(-(ch + 1), g);
+                if (st != SG_OK) return st;
+                nodes.push_back(g);
+            }
+        }
+        // primitives directly under a union / intersection root form one group
+        // with the root's op: min{1, min{1, a} + X} = min{1, a + X} and the
+        // clamped-sum intersection nests the same way.
+        if (!direct.prims.empty()) groups.push_back(direct);
+        for (auto& g : nodes) groups.push_back(g);
+        root_op = groups.size() == 1 ? ROOT_NONE : root.op;
+    }
+    if ((int)groups.size() > kMaxGroups) return fail(SG_E_UNSUPPORTED, "more than %d groups under the root", kMaxGroups);
+    for (auto& g : groups)
+        for (int pi : g.prims) {
+            if (used[pi]) return fail(SG_E_INVALID, "primitive %d appears twice in the tree", pi);
+            used[pi] = 1;
+        }
+
+    // column axis: y for 2D scenes made only of boxes, else z
+    bool all_box = true;
+    for (int i = 0; i < d->nprim; ++i)
+        if (used[i] && d->prims[i].type != SG_PRIM_BOX) all_box = false;
+    const int col = (d->dim == 2 && all_box) ? 1 : 2;
+    const int axis_v = col == 2 ? 1 : 2;
+
+    auto* s = new (std::nothrow) sg_scene;
+    if (!s) return fail(SG_E_NOMEM, "host memory");
+    s->ctx = ctx;
+    s->dim = d->dim;
+    s->ncomp = d->ncomp;
+    for (int c = 0; c < 3; ++c) s->comp_axis[c] = d->comp_axis[c];
+    for (int a = 0; a < 3; ++a) s->n[a] = d->n[a];
+    s->n_params = d->n_params;
+    s->nfield = d->nfield;
+    s->eps_bg = d->eps_bg;
+    s->eps_fg = d->eps_fg;
+    s->col = col;
+    s->axis_v = axis_v;
+    s->nu = (int)d->n[0];
+    s->nv = (int)d->n[axis_v];
+    s->nw = (int)d->n[col];
+    const int64_t stride[3] = {1, d->n[0], d->n[0] * d->n[1]};
+    s->sv = stride[axis_v];
+    s->sw = stride[col];
+    s->plane = plane;
+    s->fields.assign(d->fields, d->fields + d->nfield);
+
+    // extrusion classes
+    auto colspec = [&](int pi) {
+        const sg_prim_desc& p = d->prims[pi];
+        ColSpec cs{};
+        int fz, sa;
+        if (p.type == SG_PRIM_BOX) {
+            fz = 2 * col;
+            sa = col;
+            cs.bounded = p.bounded[col] != 0;
+        } else {
+            fz = zfield(p);
+            sa = 2;
+            cs.bounded = p.bounded[2] != 0;
+        }
+        if (cs.bounded) {
+            cs.lo = d->fields[p.field_off + fz];
+            cs.hi = d->fields[p.field_off + fz + 1];
+            cs.kind = p.sigma[sa].kind;
+            cs.kmode = p.sigma[sa].kmode;
+            cs.k = p.sigma[sa].k;
+        }
+        return std::make_tuple(cs, p.field_off + fz);
+    };
+    std::vector<int> prim_cls(d->nprim, -1);
+    std::vector<ColSpec> specs;
+    std::vector<int> spec_group;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+        for (int pi : groups[gi].prims) {
+            auto [cs, fz] = colspec(pi);
+            int found = -1;
+            for (int c = 0; c < (int)specs.size(); ++c)
+                if (spec_group[c] == gi && specs[c] == cs) found = c;
+            if (found < 0) {
+                if ((int)specs.size() == kMaxClasses) {
+                    free_scene(s);
+                    return fail(SG_E_UNSUPPORTED, "more than %d extrusion classes", kMaxClasses);
+                }
+                found = (int)specs.size();
+                specs.push_back(cs);
+                spec_group.push_back(gi);
+                DevClass dc{};
+                dc.group = gi;
+                dc.bounded = cs.bounded;
+                dc.flo = cs.bounded ? fz : -1;
+                dc.fhi = cs.bounded ? fz + 1 : -1;
+                dc.skind = cs.kind;
+                dc.smode = cs.kmode;
+                dc.k = cs.bounded ? cs.k : 1.0;
+                s->classes.push_back(dc);
+            }
+            prim_cls[pi] = found;
+        }
+    }
+    s->nclass = (int)s->classes.size();
+    s->ncls_pad = s->nclass <= 1 ? 1 : s->nclass <= 2 ? 2 : s->nclass <= 4 ? 4 : 8;
+    s->ngroup = (int)groups.size();
+    s->root_op = root_op;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        s->group_op[g] = g < s->ngroup ? groups[g].op : SG_OP_UNION;
+        s->group_nm1[g] = g < s->ngroup ? (double)(groups[g].nmember - 1) : 0.0;
+    }
+    s->root_nm1 = (double)(s->ngroup - 1);
+
+    // lattices and the largest sample width per in-plane axis
+    std::vector<double> lat;
+    double wmax[3] = {0, 0, 0};
+    for (int c = 0; c < d->ncomp; ++c) {
+        const int axes[3] = {0, axis_v, col};
+        for (int q = 0; q < 3; ++q) {
+            const int a = axes[q];
+            std::vector<double> cc, ww;
+            axis_samples(d->nodes[a], d->n[a], a == d->comp_axis[c], cc, ww);
+            for (double w : ww) wmax[a] = std::max(wmax[a], w);
+            s->lat_off[c][2 * q] = (int64_t)lat.size();
+            lat.insert(lat.end(), cc.begin(), cc.end());
+            s->lat_off[c][2 * q + 1] = (int64_t)lat.size();
+            lat.insert(lat.end(), ww.begin(), ww.end());
+        }
+    }
+    // device primitive records (primitives of the tree only, in index order)
+    std::vector<DevPrim> prims;
+    for (int i = 0; i < d->nprim; ++i) {
+        if (!used[i]) continue;
+        const sg_prim_desc& p = d->prims[i];
+        DevPrim r{};
+        r.type = p.type;
+        r.cls = prim_cls[i];
+        r.f0 = p.field_off;
+        r.nvert = p.nvert;
+        r.c0 = p.const_off;
+        auto reach = [&](const sg_sigma& sgm, int axis) {
+            const double k = sgm.kmode == SG_K_LOCAL ? sgm.k / wmax[axis] : sgm.k;
+            return sigma_cut(sgm.kind) / k;
+        };
+        if (p.type == SG_PRIM_BOX) {
+            r.ubnd = p.bounded[0] != 0;
+            r.vbnd = p.bounded[axis_v] != 0;
+            r.fu0 = p.field_off + 0;
+            r.fu1 = p.field_off + 1;
+            r.fv0 = p.field_off + 2 * axis_v;
+            r.fv1 = p.field_off + 2 * axis_v + 1;
+            r.sk0 = p.sigma[0].kind;
+            r.sm0 = p.sigma[0].kmode;
+            r.k0 = p.sigma[0].k;
+            r.sk1 = p.sigma[axis_v].kind;
+            r.sm1 = p.sigma[axis_v].kmode;
+            r.k1 = p.sigma[axis_v].k;
+            r.reach0 = r.ubnd ? reach(p.sigma[0], 0) : 0.0;
+            r.reach1 = r.vbnd ? reach(p.sigma[axis_v], axis_v) : 0.0;
+        } else {
+            r.ubnd = r.vbnd = 1;
+            r.sk0 = p.sigma[0].kind;
+            r.sm0 = p.sigma[0].kmode;
+            r.k0 = p.sigma[0].k;
+            r.reach0 = reach(p.sigma[0], 0);
+            if (p.type == SG_PRIM_GCART) {
+                r.sk1 = p.sigma[1].kind;
+                r.sm1 = p.sigma[1].kmode;
+                r.k1 = p.sigma[1].k;
+                r.reach1 = reach(p.sigma[1], 1);
+            }
+            if (p.type == SG_PRIM_ELLIPSE) {
+                r.ax = d->consts[p.const_off];
+                r.ay = d->consts[p.const_off + 1];
+            }
+        }
+        prims.push_back(r);
+    }
+    s->nprim = (int)prims.size();
+
+    // device allocations
+    hipError_t e = hipSetDevice(ctx->device);
+    auto alloc = [&](void** ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+    };
+    alloc((void**)&s->d_lat, lat.size() * sizeof(double));
+    alloc((void**)&s->d_fref, std::max<int64_t>(1, d->nfield) * sizeof(sg_field));
+    alloc((void**)&s->d_prims, prims.size() * sizeof(DevPrim));
+    alloc((void**)&s->d_cls, s->classes.size() * sizeof(DevClass));
+    alloc((void**)&s->d_consts, std::max(1, d->nconst) * sizeof(double));
+    alloc((void**)&s->d_p, std::max<int64_t>(1, d->n_params) * sizeof(double));
+    alloc((void**)&s->d_grad, std::max<int64_t>(1, d->n_params) * sizeof(double));
+    for (int v = 0; v < 2; ++v) {
+        alloc((void**)&s->d_fval[v], std::max<int64_t>(1, d->nfield) * sizeof(double));
+        alloc((void**)&s->d_bbox[v], prims.size() * sizeof(double4));
+        alloc((void**)&s->d_ztab[v], (size_t)d->ncomp * s->nclass * s->nw * 3 * sizeof(double));
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_p, std::max<int64_t>(1, d->n_params) * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_grad, std::max<int64_t>(1, d->n_params) * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->p_evt, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpy(s->d_lat, lat.data(), lat.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && d->nfield)
+        e = hipMemcpy(s->d_fref, d->fields, d->nfield * sizeof(sg_field), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->d_prims, prims.data(), prims.size() * sizeof(DevPrim), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->d_cls, s->classes.data(), s->classes.size() * sizeof(DevClass), hipMemcpyHostToDevice);
+    if (e == hipSuccess && d->nconst)
+        e = hipMemcpy(s->d_consts, d->consts, d->nconst * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_scene(s);
+        return fail(e == hipErrorOutOfMemory ? SG_E_NOMEM : SG_E_DEVICE, "sg_scene_create: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_scene_info(const sg_scene* s, int64_t* n_params, int32_t* ncomp, int64_t dims[3]) {
+    if (!s) return fail(SG_E_INVALID, "sg_scene_info: NULL scene");
+    if (n_params) *n_params = s->n_params;
+    if (ncomp) *ncomp = s->ncomp;
+    if (dims)
+        for (int a = 0; a < 3; ++a) dims[a] = s->n[a];
+    return SG_OK;
+}
+
+extern "C" sg_status sg_scene_set_launch(sg_scene* s, int32_t block_x, int32_t col_segments) {
+    if (!s) return fail(SG_E_INVALID, "NULL scene");
+    if (block_x != 0 && block_x != 16 && block_x != 32 && block_x != 64 && block_x != 128 && block_x != 256)
+        return fail(SG_E_INVALID, "block_x must be 0, 16, 32, 64, 128 or 256");
+    if (col_segments < 0) return fail(SG_E_INVALID, "col_segments < 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->block_x = block_x;
+    s->nseg = col_segments;
+    return SG_OK;
+}
+
+// ------------------------------------------------------------------ calls
+static sg_status stage_p(sg_scene* s, const double* p, int p_on_device, hipStream_t st, const double** dp) {
+    if (s->n_params == 0) {
+        *dp = s->d_p;
+        return SG_OK;
+    }
+    if (!p) return fail(SG_E_INVALID, "p is NULL");
+    if (p_on_device) {
+        *dp = p;
+        return SG_OK;
+    }
+    for (int64_t i = 0; i < s->n_params; ++i)
+        if (!std::isfinite(p[i])) return fail(SG_E_INVALID, "p[%lld] is not finite", (long long)i);
+    if (s->p_evt_pending) HIP_OK(hipEventSynchronize(s->p_evt));
+    std::memcpy(s->h_p, p, s->n_params * sizeof(double));
+    HIP_OK(hipMemcpyAsync(s->d_p, s->h_p, s->n_params * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_OK(hipEventRecord(s->p_evt, st));
+    s->p_evt_pending = true;
+    *dp = s->d_p;
+    return SG_OK;
+}
+
+static StageParams stage_params(sg_scene* s, const double* dp) {
+    StageParams sp{};
+    sp.nprim = s->nprim;
+    sp.nclass = s->nclass;
+    sp.ncomp = s->ncomp;
+    sp.nw = s->nw;
+    sp.n_params = s->n_params;
+    sp.fref = s->d_fref;
+    sp.prims = s->d_prims;
+    sp.cls = s->d_cls;
+    sp.consts = s->d_consts;
+    sp.p = dp;
+    sp.pert_idx = -1;
+    sp.delta[0] = sp.delta[1] = 0.0;
+    for (int v = 0; v < 2; ++v) {
+        sp.fval[v] = s->d_fval[v];
+        sp.bbox[v] = s->d_bbox[v];
+        sp.ztab[v] = s->d_ztab[v];
+    }
+    for (int c = 0; c < kMaxComp; ++c) {
+        const int cc = std::min(c, s->ncomp - 1);
+        sp.wc[c] = s->d_lat + s->lat_off[cc][4];
+        sp.ww[c] = s->d_lat + s->lat_off[cc][5];
+    }
+    sp.nfield = (int)s->nfield;
+    sp.zero_ptr = nullptr;
+    sp.zero_n = 0;
+    return sp;
+}
+
+static KParams column_params(sg_scene* s) {
+    KParams kp{};
+    kp.nu = s->nu;
+    kp.nv = s->nv;
+    kp.nw = s->nw;
+    kp.ncomp = s->ncomp;
+    kp.sv = s->sv;
+    kp.sw = s->sw;
+    kp.plane = s->plane;
+    int tu = s->block_x;
+    if (tu == 0) {
+        if (s->nv == 1) tu = 256;
+        else tu = s->nprim > 32 ? 16 : 64;
+    }
+    kp.tu = tu;
+    kp.tv = kBlock / tu;
+    kp.tiles_u = (s->nu + tu - 1) / tu;
+    kp.tiles_v = (s->nv + kp.tv - 1) / kp.tv;
+    int nseg = s->nseg;
+    if (nseg == 0) {
+        const int64_t base = (int64_t)s->ncomp * kp.tiles_u * kp.tiles_v;
+        const int64_t target = 2048;
+        nseg = (int)std::max<int64_t>(1, std::min<int64_t>((target + base - 1) / base, (s->nw + 15) / 16));
+    }
+    nseg = std::min(nseg, s->nw);
+    kp.seglen = (s->nw + nseg - 1) / nseg;
+    kp.nseg = (s->nw + kp.seglen - 1) / kp.seglen;
+    kp.nprim = s->nprim;
+    kp.nclass = s->nclass;
+    for (int c = 0; c < kMaxClasses; ++c) {
+        kp.cls_group[c] = c < s->nclass ? s->classes[c].group : 0;
+        int wp = 0;
+        if (c < s->nclass && s->classes[c].bounded) {
+            wp = s->fields[s->classes[c].flo].idx >= 0 || s->fields[s->classes[c].fhi].idx >= 0;
+        }
+        kp.cls_wparam[c] = wp;
+    }
+    kp.ngroup = s->ngroup;
+    kp.root_op = s->root_op;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        kp.group_op[g] = s->group_op[g];
+        kp.group_nm1[g] = s->group_nm1[g];
+    }
+    kp.root_nm1 = s->root_nm1;
+    kp.eps_bg = s->eps_bg;
+    kp.deps = s->eps_fg - s->eps_bg;
+    for (int c = 0; c < kMaxComp; ++c) {
+        const int cc = std::min(c, s->ncomp - 1);
+        kp.uc[c] = s->d_lat + s->lat_off[cc][0];
+        kp.uw[c] = s->d_lat + s->lat_off[cc][1];
+        kp.vc[c] = s->d_lat + s->lat_off[cc][2];
+        kp.vw[c] = s->d_lat + s->lat_off[cc][3];
+    }
+    kp.prims = s->d_prims;
+    kp.cls = s->d_cls;
+    kp.fref = s->d_fref;
+    kp.consts = s->d_consts;
+    kp.fval = s->d_fval[0];
+    kp.bbox = s->d_bbox[0];
+    kp.ztab = s->d_ztab[0];
+    kp.fval2 = s->d_fval[1];
+    kp.bbox2 = s->d_bbox[1];
+    kp.ztab2 = s->d_ztab[1];
+    return kp;
+}
+
+static sg_status check_call(sg_ctx* ctx, sg_scene* s) {
+    if (!ctx || !s) return fail(SG_E_INVALID, "NULL ctx or scene");
+    if (s->ctx->device != ctx->device) return fail(SG_E_INVALID, "scene belongs to another device");
+    HIP_OK(hipSetDevice(ctx->device));
+    return SG_OK;
+}
+
+static sg_status finish_grad(sg_scene* s, double* grad, int grad_on_device, hipStream_t st) {
+    if (grad_on_device || s->n_params == 0) return SG_OK;
+    HIP_OK(hipMemcpyAsync(s->h_grad, s->d_grad, s->n_params * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    std::memcpy(grad, s->h_grad, s->n_params * sizeof(double));
+    return SG_OK;
+}
+
+extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, float* eps, void* stream) {
+    sg_status rc = check_call(ctx, s);
+    if (rc != SG_OK) return rc;
+    if (!eps) return fail(SG_E_INVALID, "eps is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const double* dp;
+    if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
+    StageParams sp = stage_params(s, dp);
+    HIP_OK(launch_stage(sp, 1, st));
+    KParams kp = column_params(s);
+    kp.out = eps;
+    HIP_OK(launch_column(MODE_EPS, s->ncls_pad, kp, st));
+    return SG_OK;
+}
+
+static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, int mode,
+                            const void* const* e_fwd, const void* const* e_adj, double omega, const float* geps,
+                            double* grad, int grad_on_device, void* stream) {
+    sg_status rc = check_call(ctx, s);
+    if (rc != SG_OK) return rc;
+    if (!grad && s->n_params > 0) return fail(SG_E_INVALID, "grad is NULL");
+    if (mode == MODE_VJP_FIELDS) {
+        if (!e_fwd || !e_adj) return fail(SG_E_INVALID, "field pointer arrays are NULL");
+        for (int c = 0; c < s->ncomp; ++c)
+            if (!e_fwd[c] || !e_adj[c]) return fail(SG_E_INVALID, "field plane %d is NULL", c);
+        if (!std::isfinite(omega)) return fail(SG_E_INVALID, "omega not finite");
+    } else if (!geps) {
+        return fail(SG_E_INVALID, "grad_eps is NULL");
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const double* dp;
+    if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
+    double* g = grad_on_device ? grad : s->d_grad;
+    StageParams sp = stage_params(s, dp);
+    sp.zero_ptr = g;
+    sp.zero_n = s->n_params;
+    HIP_OK(launch_stage(sp, 1, st));
+    KParams kp = column_params(s);
+    kp.grad = g;
+    if (mode == MODE_VJP_FIELDS) {
+        for (int c = 0; c < kMaxComp; ++c) {
+            const int cc = std::min(c, s->ncomp - 1);
+            kp.ef[c] = (const float2*)e_fwd[cc];
+            kp.ea[c] = (const float2*)e_adj[cc];
+        }
+        kp.two_omega = (float)(2.0 * omega);
+    } else {
+        kp.geps = geps;
+    }
+    HIP_OK(launch_column(mode, s->ncls_pad, kp, st));
+    return finish_grad(s, grad, grad_on_device, st);
+}
+
+extern "C" sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,
+                                  const void* const* e_adj, double omega, double* grad, int grad_on_device,
+                                  void* stream) {
+    return vjp_common(ctx, s, p, p_on_device, MODE_VJP_FIELDS, e_fwd, e_adj, omega, nullptr, grad, grad_on_device,
+                      stream);
+}
+
+extern "C" sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,
+                                       const float* grad_eps, double* grad, int grad_on_device, void* stream) {
+    return vjp_common(ctx, s, p, p_on_device, MODE_VJP_GEPS, nullptr, nullptr, 0.0, grad_eps, grad, grad_on_device,
+                      stream);
+}
+
+extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,
+                                 const void* const* e_adj, double omega, double h, int scheme, double* grad,
+                                 int grad_on_device, void* stream) {
+    sg_status rc = check_call(ctx, s);
+    if (rc != SG_OK) return rc;
+    if (!grad && s->n_params > 0) return fail(SG_E_INVALID, "grad is NULL");
+    if (!e_fwd || !e_adj) return fail(SG_E_INVALID, "field pointer arrays are NULL");
+    for (int c = 0; c < s->ncomp; ++c)
+        if (!e_fwd[c] || !e_adj[c]) return fail(SG_E_INVALID, "field plane %d is NULL", c);
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(SG_E_INVALID, "h must be > 0");
+    if (scheme != SG_FD_CENTRAL && scheme != SG_FD_FORWARD) return fail(SG_E_INVALID, "unknown FD scheme");
+    std::lock_guard<std::mutex> lk(s->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t total = (int64_t)s->ncomp * s->plane;
+    for (int v = 0; v < 2; ++v)
+        if (!s->d_work[v]) HIP_OK(hipMalloc((void**)&s->d_work[v], total * sizeof(float) + 64));
+    const double* dp;
+    if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
+    double* g = grad_on_device ? grad : s->d_grad;
+    HIP_OK(launch_fill(g, 0.0, std::max<int64_t>(1, s->n_params), st));
+    const float2* ef[3];
+    const float2* ea[3];
+    for (int c = 0; c < 3; ++c) {
+        const int cc = std::min(c, s->ncomp - 1);
+        ef[c] = (const float2*)e_fwd[cc];
+        ea[c] = (const float2*)e_adj[cc];
+    }
+    HIP_OK(launch_gplane(ef, ea, s->ncomp, s->plane, (float)(2.0 * omega), s->d_work[0], st));
+    KParams kp = column_params(s);
+    kp.out = s->d_work[1];
+    const double scale = scheme == SG_FD_CENTRAL ? 1.0 / (2.0 * h) : 1.0 / h;
+    for (int64_t k = 0; k < s->n_params; ++k) {
+        StageParams sp = stage_params(s, dp);
+        sp.pert_idx = k;
+        sp.delta[0] = h;
+        sp.delta[1] = scheme == SG_FD_CENTRAL ? -h : 0.0;
+        HIP_OK(launch_stage(sp, 2, st));
+        HIP_OK(launch_column(MODE_FD, s->ncls_pad, kp, st));
+        HIP_OK(launch_dot(s->d_work[0], s->d_work[1], total, scale, g + k, st));
+    }
+    return finish_grad(s, grad, grad_on_device, st);
+}
+
+// ------------------------------------------------------------------ utilities
+extern "C" sg_status sg_util_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+    if (!dst || !src || bytes < 0 || (bytes % 16) != 0) return fail(SG_E_INVALID, "sg_util_copy: bad arguments");
+    HIP_OK(launch_copy(dst, src, bytes, (hipStream_t)stream));
+    return SG_OK;
+}

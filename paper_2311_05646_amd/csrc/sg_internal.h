@@ -1,0 +1,117 @@
+// Internal tables shared by the host scene compiler and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/shapegrad.h"
+
+namespace sg {
+
+constexpr int kMaxComp = 3;
+constexpr int kMaxGroups = 4;
+constexpr int kMaxClasses = 8;
+constexpr int kBlock = 256;        // threads (= in-plane samples) per block
+constexpr int kCandCap = 1024;     // candidate primitives staged in LDS per pass
+
+enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3 };
+enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
+
+// One primitive as the column kernel sees it.  The kernel works in (u, v, w)
+// sample coordinates: u = x (lanes, contiguous in memory), v = the other
+// in-plane axis and w = the column axis each thread walks.  Everything a
+// primitive does along w is folded into its extrusion class.
+struct DevPrim {
+    int32_t type;          // SG_PRIM_*
+    int32_t cls;           // extrusion class
+    int32_t f0;            // first field of the primitive (flat field array)
+    int32_t nvert;         // POLY / GCART vertices
+    int32_t c0;            // first constant
+    int32_t ubnd, vbnd;    // BOX: bounded along u / v
+    int32_t fu0, fu1;      // BOX: fields of the u bounds
+    int32_t fv0, fv1;      // BOX: fields of the v bounds
+    int32_t sk0, sm0;      // sigma kind / k mode of argument 0 (u bound, boundary, x-range)
+    int32_t sk1, sm1;      // sigma kind / k mode of argument 1 (v bound, GCART y boundary)
+    int32_t pad;
+    double k0, k1;         // k_r (LOCAL) or k (FIXED)
+    double reach0, reach1; // support half-width of each argument (um), for the support boxes
+    double ax, ay;         // ELLIPSE aspect
+};
+
+// An extrusion class: primitives of one group that share the same factor
+// along the column axis (a Rect1D in w, or 1).
+struct DevClass {
+    int32_t group;
+    int32_t bounded;
+    int32_t flo, fhi;      // fields of the w bounds
+    int32_t skind, smode;
+    double k;
+};
+
+struct StageParams {
+    int32_t nprim, nclass, ncomp, nw;
+    int64_t n_params;
+    const sg_field* fref;
+    const DevPrim* prims;
+    const DevClass* cls;
+    const double* consts;
+    const double* p;
+    int64_t pert_idx;            // parameter perturbed by +delta[variant] (-1: none)
+    double delta[2];
+    double* fval[2];
+    double4* bbox[2];            // (u_lo, u_hi, v_lo, v_hi) of the support, per primitive
+    double* ztab[2];             // [comp][class][w][3] = Z, dZ/dlo, dZ/dhi
+    const double* wc[kMaxComp];  // column-axis sample centers / widths per component
+    const double* ww[kMaxComp];
+    int32_t nfield;
+    int32_t pad;
+    double* zero_ptr;            // zeroed by variant 0 (gradient accumulator)
+    int64_t zero_n;
+};
+
+struct KParams {
+    int32_t nu, nv, nw, ncomp;
+    int64_t sv, sw, plane;       // element strides of v and w, elements per component plane
+    int32_t tu, tv, tiles_u, tiles_v;
+    int32_t nseg, seglen;
+    int32_t nprim, nclass;
+    int32_t cls_group[kMaxClasses];
+    int32_t cls_wparam[kMaxClasses];
+    int32_t ngroup, root_op;
+    int32_t group_op[kMaxGroups];
+    double group_nm1[kMaxGroups];
+    double root_nm1;
+    double eps_bg, deps;
+    const double* uc[kMaxComp];
+    const double* uw[kMaxComp];
+    const double* vc[kMaxComp];
+    const double* vw[kMaxComp];
+    const DevPrim* prims;
+    const DevClass* cls;
+    const sg_field* fref;
+    const double* consts;
+    const double* fval;
+    const double4* bbox;
+    const double* ztab;
+    const double* fval2;         // FD: the second evaluation point
+    const double4* bbox2;
+    const double* ztab2;
+    float* out;                  // eps (MODE_EPS) or difference plane (MODE_FD)
+    const float2* ef[kMaxComp];
+    const float2* ea[kMaxComp];
+    float two_omega;
+    int32_t pad;
+    const float* geps;
+    double* grad;
+};
+
+// kernel launchers (sg_kernels.hip)
+hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st);
+hipError_t launch_column(int mode, int nclass_padded, const KParams& kp, hipStream_t st);
+hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int ncomp, int64_t plane,
+                         float two_omega, float* g, hipStream_t st);
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
+hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t st);
+
+}  // namespace sg

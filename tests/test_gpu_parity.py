@@ -1,0 +1,148 @@
+"""GPU path (through the C-ABI) against the FP64 oracle on seeded inputs at
+sizes the oracle finishes in seconds, spanning several tiles with ragged
+tails: eps within 1e-6 absolute, gradients within 1e-4 relative L2 (the
+tolerances FP32 output against FP64 reference are held to)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import scene as S
+from tests.gpu_util import api, config, fields_c64, rel, scene_for, to_dev
+from paper_2311_05646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
+         "zoo2_intersection", "zoo3_intersection", "zoo2_difference"]
+EPS_TOL = 1e-6
+GRAD_TOL = 1e-4
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_eps(name):
+    cfg = config(name)
+    print(f"[eps] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    got = api().eps_build(sc, cfg["p"]).cpu().numpy()
+    ref = S.eps(cfg["scene"], cfg["p"])
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= EPS_TOL
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_vjp_fields(name):
+    cfg = config(name)
+    print(f"[vjp] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    got = api().eps_grad_vjp(sc, cfg["p"], to_dev(E), to_dev(A), cfg["omega"])
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], S.sensitivity(E, A, cfg["omega"]))
+    assert rel(got, ref) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_vjp_geps(name):
+    cfg = config(name)
+    print(f"[geps] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    ge = W.make_geps(cfg["scene"], 5)
+    got = api().eps_grad_vjp_geps(sc, cfg["p"], to_dev(ge))
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], ge.astype(np.float64))
+    assert rel(got, ref) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small", "c3_small", "c4_small", "zoo3_union", "zoo2_difference"])
+@pytest.mark.parametrize("scheme", ["central", "forward"])
+def test_fd(name, scheme):
+    cfg = config(name)
+    print(f"[fd-{scheme}] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    h = cfg["h"] if scheme == "central" else min(cfg["h"], 1e-7)
+    got = api().eps_grad_fd(sc, cfg["p"], to_dev(E), to_dev(A), cfg["omega"], h, scheme=scheme)
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], S.sensitivity(E, A, cfg["omega"]))
+    assert rel(got, ref) <= GRAD_TOL
+
+
+def test_c1_matches_the_standard_method():
+    """c1 is the paper's plain method: volume-averaged eps and its central FD
+    gradient.  For cuboids with linear sigma the GPU AutoDiffGeo gradient is the
+    same quantity."""
+    from oracle import volavg as V
+    cfg = config("c1")
+    sc = scene_for("c1", cfg)
+    E, A = fields_c64(cfg)
+    g = S.sensitivity(E, A, cfg["omega"])
+    d, p, h = cfg["scene"], cfg["p"], cfg["h"]
+    fd = np.array([np.sum(g * (V.eps_boxes(d, p + h * np.eye(16)[k]) - V.eps_boxes(d, p - h * np.eye(16)[k]))) / (2 * h)
+                   for k in range(16)])
+    got = api().eps_grad_vjp(sc, p, to_dev(E), to_dev(A), cfg["omega"])
+    assert rel(got, fd) <= GRAD_TOL
+    assert np.max(np.abs(api().eps_build(sc, p).cpu().numpy() - V.eps_boxes(d, p))) <= EPS_TOL
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c4_small"])
+def test_device_p_and_grad(name):
+    cfg = config(name)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    Ed, Ad = to_dev(E), to_dev(A)
+    host = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    pd = torch.tensor(cfg["p"], dtype=torch.float64, device="cuda")
+    dev = api().eps_grad_vjp(sc, pd, Ed, Ad, cfg["omega"])
+    assert isinstance(dev, torch.Tensor) and dev.is_cuda
+    assert rel(dev.cpu().numpy(), host) <= 1e-12
+    e1 = api().eps_build(sc, pd)
+    e2 = api().eps_build(sc, cfg["p"])
+    assert torch.equal(e1, e2)
+
+
+@pytest.mark.parametrize("name", ["c4_small", "zoo3_union", "c2_small"])
+def test_launch_shape_independence(name):
+    """eps does not depend on the tiling (bitwise); gradients only through the
+    order of atomic additions."""
+    cfg = config(name)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    Ed, Ad = to_dev(E), to_dev(A)
+    base_e = api().eps_build(sc, cfg["p"]).cpu()
+    base_g = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    for bx in (16, 32, 64, 128, 256):
+        for seg in (1, 3):
+            sc.set_launch(bx, seg)
+            assert torch.equal(api().eps_build(sc, cfg["p"]).cpu(), base_e), (bx, seg)
+            assert rel(api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"]), base_g) <= 1e-6, (bx, seg)
+    sc.set_launch(0, 0)
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c4_small", "zoo3_difference"])
+def test_autograd_epsbuild(name):
+    cfg = config(name)
+    sc = scene_for(name, cfg)
+    p = torch.tensor(cfg["p"], dtype=torch.float64, device="cuda", requires_grad=True)
+    eps = api().EpsBuild.apply(p, sc)
+    wgt = W.make_geps(cfg["scene"], 9)
+    loss = (eps.double() * to_dev(wgt).double()).sum()
+    loss.backward()
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], wgt.astype(np.float64))
+    assert rel(p.grad.cpu().numpy(), ref) <= GRAD_TOL
+    # the same gradient by central differences of the FP64 map
+    ks = list(range(0, cfg["scene"]["n_params"], max(1, cfg["scene"]["n_params"] // 8)))
+    fd = S.grad_fd(cfg["scene"], cfg["p"], wgt.astype(np.float64), 1e-6, ks)
+    assert rel(p.grad.cpu().numpy()[ks], fd[ks]) <= GRAD_TOL
+
+
+def test_invalid_inputs_raise():
+    from paper_2311_05646_amd._lib import SGError
+    cfg = config("c1")
+    sc = scene_for("c1", cfg)
+    bad = cfg["p"].copy()
+    bad[3] = np.nan
+    with pytest.raises(SGError):
+        api().eps_build(sc, bad)
+    with pytest.raises(ValueError):
+        api().eps_build(sc, cfg["p"][:5])
+    d = dict(cfg["scene"])
+    d["tree"] = {"op": "union", "children": [{"op": "union", "children": [{"op": "union", "children": [0]}]}, 1]}
+    with pytest.raises(SGError):
+        api().Scene(d)
