@@ -1,0 +1,287 @@
+#!/usr/bin/env python3
+"""Shape-gradient throughput on one MI355X.
+
+A step is one pass of the whole gradient path on the 2D multi-etch blazed
+grating workload (4000 x 600 rectilinear grid, dx graded 10-25 nm, dy 10 nm,
+3 complex64 field components, 101 primitives, n = 200 edge parameters):
+staging of p, eps_build (step 2 of the adjoint loop) and the fused adjoint
+gradient eps_grad_vjp (step 5, eq:1 / eq:AD), with p, fields and outputs
+resident in HBM.  Four field sets are rotated so the 115 MB per set cannot
+be served from the 256 MB Infinity Cache.
+
+Printed JSON line: value = gradient evaluations per second; roofline of the
+dominant kernel (the fused VJP column kernel, timed with HIP events on its
+own stream inside the library); the GPU finite-difference Jacobian baseline
+at matched accuracy; the 3D workloads' kernel bandwidth; and the CPU oracle
+timed on a bounded slice of the same workload on this host's cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import ctypes as C
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_2311_05646_amd/csrc/sg_kernels.hip", "paper_2311_05646_amd/csrc/sg_device.h",
+                  "paper_2311_05646_amd/csrc/sg_internal.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_src_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name):
+    """HBM bytes per launch of the named kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on other kernel sources."""
+    path = os.path.join(PROFILE_DIR, f"pmc_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Fast:
+    """Pre-marshalled C-ABI calls for the timed loop (no per-call Python
+    argument checks; the checked wrappers in api are used everywhere else)."""
+
+    def __init__(self, api, scene, p_dev, eps_out, grad_out, sets, omega, stream):
+        from paper_2311_05646_amd._lib import lib
+        self.L = lib()
+        self.ctx, self.sc = scene.ctx, scene.handle
+        self.p = C.c_void_p(p_dev.data_ptr())
+        self.eps = C.c_void_p(eps_out.data_ptr())
+        self.grad = C.c_void_p(grad_out.data_ptr())
+        self.sets = [(api._plane_ptrs(scene, E), api._plane_ptrs(scene, A)) for E, A in sets]
+        self.omega = float(omega)
+        self.st = C.c_void_p(stream.cuda_stream)
+
+    def step(self, i):
+        fe, fa = self.sets[i % len(self.sets)]
+        r1 = self.L.eps_build(self.ctx, self.sc, self.p, 1, self.eps, self.st)
+        r2 = self.L.eps_grad_vjp(self.ctx, self.sc, self.p, 1, fe, fa, self.omega, self.grad, 1, self.st)
+        if r1 or r2:
+            raise RuntimeError(self.L.sg_last_error().decode())
+
+
+def cpu_baseline(W, cfg, fields0, seconds_budget):
+    """The oracle (FP64 NumPy, single thread) on a contiguous x-slice of the
+    same workload: eps + reverse-mode gradient; scaled to a whole evaluation."""
+    import numpy as np
+    from oracle import scene as S
+    d, p = cfg["scene"], cfg["p"]
+    X, Y, Z = d["nodes"]
+    i0, w = 1000, 600
+    d2 = dict(d)
+    d2["nodes"] = [X[i0:i0 + w + 1], Y, Z]
+    E, A = fields0
+    E2 = np.ascontiguousarray(E[:, :, :, i0:i0 + w])
+    A2 = np.ascontiguousarray(A[:, :, :, i0:i0 + w])
+    t = time.perf_counter()
+    S.eps(d2, p)
+    S.grad_analytic(d2, p, S.sensitivity(E2, A2, cfg["omega"]))
+    dt = time.perf_counter() - t
+    n_slice = E2.size
+    n_full = W.n_samples(d)
+    sec_per_eval = dt * n_full / n_slice
+    return {"value": 1.0 / sec_per_eval, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"x-slice [{i0}, {i0 + w}) of 4000 columns ({n_slice} of {n_full} samples, all 101 "
+                      f"primitives, eps + reverse-mode gradient), {dt:.1f} s, scaled by {n_full / n_slice:.2f}",
+            "seconds_per_eval": sec_per_eval}
+
+
+def time_kernels(api, scene, p_dev, E, A, omega, reps):
+    import torch
+    g = torch.empty(scene.n_params, dtype=torch.float64, device="cuda")
+    e = torch.empty(scene.shape, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        api.eps_build(scene, p_dev, out=e)
+        api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
+    torch.cuda.synchronize()
+    scene.set_timing(True)
+    for _ in range(reps):
+        api.eps_build(scene, p_dev, out=e)
+        api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
+    torch.cuda.synchronize()
+    ve, ne = scene.kernel_time("eps")
+    vv, nv = scene.kernel_time("vjp")
+    scene.set_timing(False)
+    m = scene.shape[0] * scene.shape[1] * scene.shape[2] * scene.shape[3]
+    return {"vjp_us": 1e3 * vv / nv, "vjp_GBps": 16.0 * m / (vv / nv * 1e-3) / 1e9,
+            "eps_us": 1e3 * ve / ne, "eps_GBps": 4.0 * m / (ve / ne * 1e-3) / 1e9, "samples": m}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--quick", action="store_true", help="timed loop only (for profiler runs)")
+    ap.add_argument("--calib-copy", action="store_true", help="also run the reference copy kernel (1 GiB)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path shards by grid slab "
+              "with one n-vector all-reduce; that multi-GPU path is not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2311_05646_amd import _lib, workloads as W
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2311_05646_amd import build
+        build.build()
+    from paper_2311_05646_amd import api
+
+    log("[bench] generating c2 inputs")
+    cfg = W.make_c2()
+    scene = api.Scene(cfg["scene"])
+    dev = torch.device("cuda", 0)
+    E0 = torch.from_numpy(cfg["E"]).to(dev)
+    A0 = torch.from_numpy(cfg["A"]).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(W.BASE_SEED)
+    sets = [(E0, A0)]
+    for _ in range(3):
+        sets.append(tuple(torch.complex(torch.randn(scene.shape, device=dev, generator=gen),
+                                        torch.randn(scene.shape, device=dev, generator=gen)) for _ in range(2)))
+    p_dev = torch.tensor(cfg["p"], dtype=torch.float64, device=dev)
+    eps_out = torch.empty(scene.shape, dtype=torch.float32, device=dev)
+    grad_out = torch.empty(scene.n_params, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    fast = Fast(api, scene, p_dev, eps_out, grad_out, sets, cfg["omega"], stream)
+
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        api.util_copy(dst, src)
+        torch.cuda.synchronize()
+        log("[bench] reference copy of 1 GiB done")
+
+    log(f"[bench] warmup {args.warmup}")
+    scene.set_timing(True)          # also fills the event pool the timed loop reuses
+    for i in range(max(args.warmup, args.steps)):
+        fast.step(i)
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    scene.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        fast.step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vjp_ms, nv = scene.kernel_time("vjp")
+    eps_ms, ne = scene.kernel_time("eps")
+    scene.set_timing(False)
+    sec = t1 - t0
+    m = W.n_samples(cfg["scene"])
+    vjp_avg_s = vjp_ms / nv * 1e-3
+    alg_bytes = 16.0 * m + 16.0 * scene.n_params
+    achieved = alg_bytes / vjp_avg_s / 1e9
+    traffic = read_traffic("vjp_c2")
+    out = {
+        "metric": "shape-gradient evals/s (eps_build + fused VJP); HBM GB/s of the VJP kernel vs the GPU "
+                  "FD-Jacobian; serve p50/p99",
+        "value": args.steps / sec,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 geometry + f32 fields",
+        "data": "synthetic (seeded; fields i.i.d. N(0,1) complex64, 4 rotated sets)",
+        "config": {"workload": "c2 2D multi-etch blazed grating: 4000x600 rectilinear (dx 10-25 nm graded, "
+                               "dy 10 nm), Ex/Ey/Ez complex64, slab minus union of 50 full + 50 shallow etches, "
+                               "n=200, linear sigma", "samples": m, "n_params": scene.n_params},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_column<MODE_VJP_FIELDS> (eps_grad_vjp)",
+                     "kernel_us": vjp_avg_s * 1e6, "algorithmic_bytes_per_launch": alg_bytes},
+        "eps_build_kernel": {"us": eps_ms / ne * 1e3, "GBps": 4.0 * m / (eps_ms / ne * 1e-3) / 1e9},
+    }
+    if args.quick:
+        print(json.dumps(out), flush=True)
+        return
+
+    # ---- GPU finite-difference Jacobian baseline at matched accuracy
+    log("[bench] FD baseline")
+    gfd = torch.empty(scene.n_params, dtype=torch.float64, device=dev)
+    gvjp = api.eps_grad_vjp(scene, p_dev, E0, A0, cfg["omega"])
+    api.eps_grad_fd(scene, p_dev, E0, A0, cfg["omega"], cfg["h"], grad=gfd)
+    torch.cuda.synchronize()
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        api.eps_grad_fd(scene, p_dev, E0, A0, cfg["omega"], cfg["h"], grad=gfd)
+    torch.cuda.synchronize()
+    fd_s = (time.perf_counter() - t) / reps
+    rel = float(torch.linalg.norm(gfd - gvjp) / torch.linalg.norm(gvjp))
+    vjp_only = time_kernels(api, scene, p_dev, E0, A0, cfg["omega"], 50)
+    out["fd"] = {"evals_per_s": 1.0 / fd_s, "seconds_per_eval": fd_s, "scheme": "central", "h_um": cfg["h"],
+                 "rel_l2_vs_vjp": rel,
+                 "vjp_kernel_speedup": fd_s / (vjp_only["vjp_us"] * 1e-6),
+                 "step_speedup": fd_s / (sec / args.steps),
+                 "fd_alg_GBps": (20.0 * m + scene.n_params * 12.0 * m) / fd_s / 1e9}
+
+    # ---- 3D workloads: kernel bandwidth (not the bench line's workload)
+    also = {}
+    for name, mk in (("c3", W.make_c3), ("c4", W.make_c4)):
+        log(f"[bench] {name} kernels")
+        c = mk(with_fields=False)
+        sc = api.Scene(c["scene"])
+        E = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
+        A = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
+        pd = torch.tensor(c["p"], dtype=torch.float64, device=dev)
+        r = time_kernels(api, sc, pd, E, A, c["omega"], 20)
+        r["vjp_frac_of_peak"] = r["vjp_GBps"] / HBM_PEAK_GBS
+        r["n_params"] = sc.n_params
+        also[name] = r
+        del E, A, sc
+        torch.cuda.empty_cache()
+    out["3d"] = also
+
+    # ---- serving (continuous batching) -- filled in by the serving runtime when present
+    out["serve"] = None
+    try:
+        from paper_2311_05646_amd import serving
+        log("[bench] serving")
+        out["serve"] = serving.bench_serving(api, W)
+    except ImportError:
+        pass
+
+    # ---- CPU oracle on this host
+    log("[bench] cpu baseline (oracle)")
+    out["cpu_baseline"] = cpu_baseline(W, cfg, (cfg["E"], cfg["A"]), 20)
+    out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

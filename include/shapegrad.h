@@ -179,6 +179,15 @@ sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_de
                       const void* const* e_fwd, const void* const* e_adj, double omega,
                       double h, int scheme, double* grad, int grad_on_device, void* stream);
 
+/* Kernel tracing.  With timing enabled the scene records a pair of HIP events
+ * on the call's stream around every launch of its main column kernel.
+ * sg_scene_set_timing(scene, 1) enables and clears the records, 0 disables.
+ * sg_scene_kernel_time() waits for the recorded launches of one kind (mode:
+ * 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps, 3 eps_grad_fd rasterization)
+ * and returns their summed duration (ms) and count. */
+sg_status sg_scene_set_timing(sg_scene* scene, int enable);
+sg_status sg_scene_kernel_time(sg_scene* scene, int mode, double* total_ms, int64_t* launches);
+
 /* Plain device-to-device copy (bytes a multiple of 16) on `stream`; a
  * reference kernel of known traffic for calibrating HBM byte counters. */
 sg_status sg_util_copy(void* dst, const void* src, int64_t bytes, void* stream);

@@ -57,6 +57,19 @@ class Scene:
     def set_launch(self, block_x=0, col_segments=0):
         check(lib().sg_scene_set_launch(self.handle, int(block_x), int(col_segments)))
 
+    def set_timing(self, enable=True):
+        """Trace the main column kernel of every later call (HIP events on the
+        call's stream); enabling clears earlier records."""
+        check(lib().sg_scene_set_timing(self.handle, int(bool(enable))))
+
+    def kernel_time(self, mode):
+        """(summed ms, launches) of the traced column kernels of one kind:
+        'eps', 'vjp', 'geps' or 'fd'."""
+        t = C.c_double()
+        n = C.c_int64()
+        check(lib().sg_scene_kernel_time(self.handle, _lib.MODE[mode], C.byref(t), C.byref(n)))
+        return t.value, n.value
+
     def close(self):
         if getattr(self, "handle", None):
             lib().sg_scene_destroy(self.handle)

@@ -71,6 +71,7 @@ struct sg_scene {
     int nu = 0, nv = 0, nw = 0;
     int64_t sv = 0, sw = 0, plane = 0;
     int nprim = 0, nclass = 0, ncls_pad = 1;
+    int variant = VAR_ALL;
     int ngroup = 0, root_op = ROOT_NONE;
     int group_op[kMaxGroups] = {0, 0, 0, 0};
     double group_nm1[kMaxGroups] = {0, 0, 0, 0};
@@ -95,6 +96,11 @@ struct sg_scene {
     double* h_grad = nullptr;
     hipEvent_t p_evt = nullptr;
     bool p_evt_pending = false;
+    // tracing: events around the main column-kernel launches
+    bool timing = false;
+    struct Rec { int mode; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> evpool;
     std::mutex mu;
 };
 
@@ -132,6 +138,11 @@ static void free_scene(sg_scene* s) {
     if (s->h_p) hipHostFree(s->h_p);
     if (s->h_grad) hipHostFree(s->h_grad);
     if (s->p_evt) hipEventDestroy(s->p_evt);
+    for (auto& r : s->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : s->evpool) hipEventDestroy(e);
     delete s;
 }
 
@@ -474,6 +485,27 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         prims.push_back(r);
     }
     s->nprim = (int)prims.size();
+    // smallest kernel variant covering the primitive types and in-plane sigma kinds
+    {
+        int tmask = 0, smask = 0;
+        for (int i = 0; i < d->nprim; ++i) {
+            if (!used[i]) continue;
+            const sg_prim_desc& p = d->prims[i];
+            tmask |= 1 << p.type;
+            if (p.type == SG_PRIM_BOX) {
+                if (p.bounded[0]) smask |= sigma_bit(p.sigma[0].kind);
+                if (p.bounded[axis_v]) smask |= sigma_bit(p.sigma[axis_v].kind);
+            } else {
+                smask |= sigma_bit(p.sigma[0].kind);
+                if (p.type == SG_PRIM_GCART) smask |= sigma_bit(p.sigma[1].kind);
+            }
+        }
+        const int vt[3] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL};
+        const int vs[3] = {S_LIN, S_LIN, S_LIN | S_SIGMOID};
+        s->variant = VAR_ALL;
+        for (int v = 0; v < 3; ++v)
+            if ((tmask & ~vt[v]) == 0 && (smask & ~vs[v]) == 0) { s->variant = v; break; }
+    }
 
     // device allocations
     hipError_t e = hipSetDevice(ctx->device);
@@ -664,6 +696,64 @@ static sg_status finish_grad(sg_scene* s, double* grad, int grad_on_device, hipS
     return SG_OK;
 }
 
+static hipError_t take_event(sg_scene* s, hipEvent_t* e) {
+    if (!s->evpool.empty()) {
+        *e = s->evpool.back();
+        s->evpool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Launches the column kernel, bracketed by events when tracing is on.
+static sg_status run_column(sg_scene* s, int mode, const KParams& kp, hipStream_t st) {
+    if (!s->timing) {
+        HIP_OK(launch_column(mode, s->ncls_pad, s->variant, kp, st));
+        return SG_OK;
+    }
+    sg_scene::Rec r{mode, nullptr, nullptr};
+    HIP_OK(take_event(s, &r.a));
+    HIP_OK(take_event(s, &r.b));
+    HIP_OK(hipEventRecord(r.a, st));
+    HIP_OK(launch_column(mode, s->ncls_pad, s->variant, kp, st));
+    HIP_OK(hipEventRecord(r.b, st));
+    s->recs.push_back(r);
+    return SG_OK;
+}
+
+extern "C" sg_status sg_scene_set_timing(sg_scene* s, int enable) {
+    if (!s) return fail(SG_E_INVALID, "NULL scene");
+    std::lock_guard<std::mutex> lk(s->mu);
+    HIP_OK(hipSetDevice(s->ctx->device));
+    for (auto& r : s->recs) {
+        HIP_OK(hipEventSynchronize(r.b));
+        s->evpool.push_back(r.a);
+        s->evpool.push_back(r.b);
+    }
+    s->recs.clear();
+    s->timing = enable != 0;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_scene_kernel_time(sg_scene* s, int mode, double* total_ms, int64_t* launches) {
+    if (!s || !total_ms || !launches) return fail(SG_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    HIP_OK(hipSetDevice(s->ctx->device));
+    double t = 0.0;
+    int64_t n = 0;
+    for (auto& r : s->recs) {
+        if (r.mode != mode) continue;
+        HIP_OK(hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+        t += ms;
+        ++n;
+    }
+    *total_ms = t;
+    *launches = n;
+    return SG_OK;
+}
+
 extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, float* eps, void* stream) {
     sg_status rc = check_call(ctx, s);
     if (rc != SG_OK) return rc;
@@ -676,8 +766,7 @@ extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_
     HIP_OK(launch_stage(sp, 1, st));
     KParams kp = column_params(s);
     kp.out = eps;
-    HIP_OK(launch_column(MODE_EPS, s->ncls_pad, kp, st));
-    return SG_OK;
+    return run_column(s, MODE_EPS, kp, st);
 }
 
 static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, int mode,
@@ -715,7 +804,7 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     } else {
         kp.geps = geps;
     }
-    HIP_OK(launch_column(mode, s->ncls_pad, kp, st));
+    if ((rc = run_column(s, mode, kp, st)) != SG_OK) return rc;
     return finish_grad(s, grad, grad_on_device, st);
 }
 
@@ -769,7 +858,7 @@ extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int 
         sp.delta[0] = h;
         sp.delta[1] = scheme == SG_FD_CENTRAL ? -h : 0.0;
         HIP_OK(launch_stage(sp, 2, st));
-        HIP_OK(launch_column(MODE_FD, s->ncls_pad, kp, st));
+        if ((rc = run_column(s, MODE_FD, kp, st)) != SG_OK) return rc;
         HIP_OK(launch_dot(s->d_work[0], s->d_work[1], total, scale, g + k, st));
     }
     return finish_grad(s, grad, grad_on_device, st);

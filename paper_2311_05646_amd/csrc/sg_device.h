@@ -26,90 +26,135 @@ __host__ __device__ inline double sigma_cut(int kind) {
     }
 }
 
-// sigma(t)
+// Compile-time feature sets: which primitive types and which in-plane sigma
+// kinds a kernel instantiation handles.  Scenes are dispatched to the smallest
+// instantiation that covers them, so the common kernels carry no code for
+// primitives or transcendental functions they never see.
+enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_ALL = 15 };
+enum : int { S_SIGMOID = 1, S_ERF = 2, S_SIN = 4, S_LIN = 8, S_QUAD = 16, S_ALL = 31 };
+
+// ---- one function per kind: value, and value + d/dt
+__device__ __forceinline__ double sigm_v(double t) {
+    if (t <= -kSigmoidCut) return 0.0;
+    if (t >= kSigmoidCut) return 1.0;
+    return 1.0 / (1.0 + exp(-t));
+}
+__device__ __forceinline__ void sigm_vd(double t, double& s, double& ds) {
+    if (t <= -kSigmoidCut) { s = 0.0; ds = 0.0; return; }
+    if (t >= kSigmoidCut) { s = 1.0; ds = 0.0; return; }
+    s = 1.0 / (1.0 + exp(-t));
+    ds = s * (1.0 - s);
+}
+__device__ __forceinline__ double erf_v(double t) {
+    if (t <= -kErfCut) return 0.0;
+    if (t >= kErfCut) return 1.0;
+    return 0.5 * (1.0 + erf(t));
+}
+__device__ __forceinline__ void erf_vd(double t, double& s, double& ds) {
+    if (t <= -kErfCut) { s = 0.0; ds = 0.0; return; }
+    if (t >= kErfCut) { s = 1.0; ds = 0.0; return; }
+    s = 0.5 * (1.0 + erf(t));
+    ds = exp(-t * t) * kInvSqrtPi;
+}
+__device__ __forceinline__ double sin_v(double t) {
+    if (t < -kPiHalf) return 0.0;
+    if (t > kPiHalf) return 1.0;
+    return 0.5 * (1.0 + sin(t));
+}
+__device__ __forceinline__ void sin_vd(double t, double& s, double& ds) {
+    if (t < -kPiHalf) { s = 0.0; ds = 0.0; return; }
+    if (t > kPiHalf) { s = 1.0; ds = 0.0; return; }
+    double sn, cs;
+    sincos(t, &sn, &cs);
+    s = 0.5 * (1.0 + sn);
+    ds = (t > -kPiHalf && t < kPiHalf) ? 0.5 * cs : 0.0;
+}
+__device__ __forceinline__ double lin_v(double t) { return fmax(0.0, fmin(1.0, t + 0.5)); }
+__device__ __forceinline__ void lin_vd(double t, double& s, double& ds) {
+    s = fmax(0.0, fmin(1.0, t + 0.5));
+    ds = (t > -0.5 && t < 0.5) ? 1.0 : 0.0;
+}
+__device__ __forceinline__ double quad_v(double t) {
+    if (t < -kInvSqrt2) return 0.0;
+    if (t < 0.0) { const double a = kInvSqrt2 + t; return a * a; }
+    if (t <= kInvSqrt2) { const double a = kInvSqrt2 - t; return 1.0 - a * a; }
+    return 1.0;
+}
+__device__ __forceinline__ void quad_vd(double t, double& s, double& ds) {
+    if (t < -kInvSqrt2) { s = 0.0; ds = 0.0; return; }
+    if (t < 0.0) { const double a = kInvSqrt2 + t; s = a * a; ds = 2.0 * a; return; }
+    if (t <= kInvSqrt2) {
+        const double a = kInvSqrt2 - t;
+        s = 1.0 - a * a;
+        ds = (t < kInvSqrt2) ? 2.0 * a : 0.0;
+        return;
+    }
+    s = 1.0;
+    ds = 0.0;
+}
+// out-of-line copies of the transcendental kinds for the catch-all kernels
+static __device__ __noinline__ double sigm_v_call(double t) { return sigm_v(t); }
+static __device__ __noinline__ void sigm_vd_call(double t, double& s, double& ds) { sigm_vd(t, s, ds); }
+static __device__ __noinline__ double erf_v_call(double t) { return erf_v(t); }
+static __device__ __noinline__ void erf_vd_call(double t, double& s, double& ds) { erf_vd(t, s, ds); }
+static __device__ __noinline__ double sin_v_call(double t) { return sin_v(t); }
+static __device__ __noinline__ void sin_vd_call(double t, double& s, double& ds) { sin_vd(t, s, ds); }
+
+// sigma(t) for a kind drawn from SIGS
+template <int SIGS>
 __device__ __forceinline__ double sig_v(int kind, double t) {
-    switch (kind) {
-        case SG_SIGMA_SIGMOID:
-            if (t <= -kSigmoidCut) return 0.0;
-            if (t >= kSigmoidCut) return 1.0;
-            return 1.0 / (1.0 + exp(-t));
-        case SG_SIGMA_ERF:
-            if (t <= -kErfCut) return 0.0;
-            if (t >= kErfCut) return 1.0;
-            return 0.5 * (1.0 + erf(t));
-        case SG_SIGMA_SIN:
-            if (t < -kPiHalf) return 0.0;
-            if (t > kPiHalf) return 1.0;
-            return 0.5 * (1.0 + sin(t));
-        case SG_SIGMA_LINEAR:
-            return fmax(0.0, fmin(1.0, t + 0.5));
-        default: {  // quadratic
-            if (t < -kInvSqrt2) return 0.0;
-            if (t < 0.0) { const double a = kInvSqrt2 + t; return a * a; }
-            if (t <= kInvSqrt2) { const double a = kInvSqrt2 - t; return 1.0 - a * a; }
-            return 1.0;
-        }
+    constexpr bool inl = __builtin_popcount(SIGS) <= 2;
+    if constexpr (SIGS == S_LIN) return lin_v(t);
+    else if constexpr (SIGS == S_SIGMOID) return sigm_v(t);
+    else {
+        if constexpr ((SIGS & S_LIN) != 0) if (kind == SG_SIGMA_LINEAR) return lin_v(t);
+        if constexpr ((SIGS & S_QUAD) != 0) if (kind == SG_SIGMA_QUADRATIC) return quad_v(t);
+        if constexpr ((SIGS & S_SIGMOID) != 0) if (kind == SG_SIGMA_SIGMOID) return inl ? sigm_v(t) : sigm_v_call(t);
+        if constexpr ((SIGS & S_ERF) != 0) if (kind == SG_SIGMA_ERF) return inl ? erf_v(t) : erf_v_call(t);
+        if constexpr ((SIGS & S_SIN) != 0) if (kind == SG_SIGMA_SIN) return inl ? sin_v(t) : sin_v_call(t);
+        return 0.0;
     }
 }
 
 // sigma(t) and d sigma / d t (derivative of the open piece holding t, 0 outside)
+template <int SIGS>
 __device__ __forceinline__ void sig_vd(int kind, double t, double& s, double& ds) {
-    switch (kind) {
-        case SG_SIGMA_SIGMOID:
-            if (t <= -kSigmoidCut) { s = 0.0; ds = 0.0; return; }
-            if (t >= kSigmoidCut) { s = 1.0; ds = 0.0; return; }
-            s = 1.0 / (1.0 + exp(-t));
-            ds = s * (1.0 - s);
-            return;
-        case SG_SIGMA_ERF:
-            if (t <= -kErfCut) { s = 0.0; ds = 0.0; return; }
-            if (t >= kErfCut) { s = 1.0; ds = 0.0; return; }
-            s = 0.5 * (1.0 + erf(t));
-            ds = exp(-t * t) * kInvSqrtPi;
-            return;
-        case SG_SIGMA_SIN:
-            if (t < -kPiHalf) { s = 0.0; ds = 0.0; return; }
-            if (t > kPiHalf) { s = 1.0; ds = 0.0; return; }
-            {
-                double sn, cs;
-                sincos(t, &sn, &cs);
-                s = 0.5 * (1.0 + sn);
-                ds = (t > -kPiHalf && t < kPiHalf) ? 0.5 * cs : 0.0;
-            }
-            return;
-        case SG_SIGMA_LINEAR:
-            s = fmax(0.0, fmin(1.0, t + 0.5));
-            ds = (t > -0.5 && t < 0.5) ? 1.0 : 0.0;
-            return;
-        default:
-            if (t < -kInvSqrt2) { s = 0.0; ds = 0.0; return; }
-            if (t < 0.0) { const double a = kInvSqrt2 + t; s = a * a; ds = 2.0 * a; return; }
-            if (t <= kInvSqrt2) {
-                const double a = kInvSqrt2 - t;
-                s = 1.0 - a * a;
-                ds = (t < kInvSqrt2) ? 2.0 * a : 0.0;
-                return;
-            }
-            s = 1.0;
-            ds = 0.0;
-            return;
+    constexpr bool inl = __builtin_popcount(SIGS) <= 2;
+    if constexpr (SIGS == S_LIN) { lin_vd(t, s, ds); return; }
+    else if constexpr (SIGS == S_SIGMOID) { sigm_vd(t, s, ds); return; }
+    else {
+        if constexpr ((SIGS & S_LIN) != 0) if (kind == SG_SIGMA_LINEAR) { lin_vd(t, s, ds); return; }
+        if constexpr ((SIGS & S_QUAD) != 0) if (kind == SG_SIGMA_QUADRATIC) { quad_vd(t, s, ds); return; }
+        if constexpr ((SIGS & S_SIGMOID) != 0)
+            if (kind == SG_SIGMA_SIGMOID) { if (inl) sigm_vd(t, s, ds); else sigm_vd_call(t, s, ds); return; }
+        if constexpr ((SIGS & S_ERF) != 0)
+            if (kind == SG_SIGMA_ERF) { if (inl) erf_vd(t, s, ds); else erf_vd_call(t, s, ds); return; }
+        if constexpr ((SIGS & S_SIN) != 0)
+            if (kind == SG_SIGMA_SIN) { if (inl) sin_vd(t, s, ds); else sin_vd_call(t, s, ds); return; }
+        s = 0.0;
+        ds = 0.0;
     }
 }
+
+// host + device: kind -> bit
+__host__ __device__ inline int sigma_bit(int kind) { return 1 << kind; }
 
 __device__ __forceinline__ double kval(int kmode, double k, double width) {
     return kmode == SG_K_LOCAL ? k / width : k;
 }
 
 // Rect1D(c; lo, hi) = sigma_k(c - lo) sigma_k(hi - c)
+template <int SIGS>
 __device__ __forceinline__ double rect_v(int kind, double k, double c, double lo, double hi) {
-    return sig_v(kind, k * (c - lo)) * sig_v(kind, k * (hi - c));
+    return sig_v<SIGS>(kind, k * (c - lo)) * sig_v<SIGS>(kind, k * (hi - c));
 }
 
+template <int SIGS>
 __device__ __forceinline__ void rect_vd(int kind, double k, double c, double lo, double hi,
                                         double& v, double& dlo, double& dhi) {
     double sa, dsa, sb, dsb;
-    sig_vd(kind, k * (c - lo), sa, dsa);
-    sig_vd(kind, k * (hi - c), sb, dsb);
+    sig_vd<SIGS>(kind, k * (c - lo), sa, dsa);
+    sig_vd<SIGS>(kind, k * (hi - c), sb, dsb);
     v = sa * sb;
     dlo = -k * dsa * sb;
     dhi = k * sa * dsb;
@@ -137,22 +182,27 @@ __device__ __forceinline__ void gcart_segment(const double* __restrict__ xv, int
 }
 
 // In-plane factor F(u, v) of a primitive (value only).
+template <int TYPES, int SIGS>
 __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __restrict__ fv,
                                              const double* __restrict__ cst,
                                              double uc, double uw, double vc, double vw) {
-    switch (pr.type) {
-        case SG_PRIM_BOX: {
+    if constexpr ((TYPES & T_BOX) != 0) {
+        if (TYPES == T_BOX || pr.type == SG_PRIM_BOX) {
             double f = 1.0;
-            if (pr.ubnd) f = rect_v(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.fu0], fv[pr.fu1]);
-            if (pr.vbnd) f *= rect_v(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, fv[pr.fv0], fv[pr.fv1]);
+            if (pr.ubnd) f = rect_v<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.fu0], fv[pr.fu1]);
+            if (pr.vbnd) f *= rect_v<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, fv[pr.fv0], fv[pr.fv1]);
             return f;
         }
-        case SG_PRIM_ELLIPSE: {
+    }
+    if constexpr ((TYPES & T_ELL) != 0) {
+        if (pr.type == SG_PRIM_ELLIPSE) {
             const double dx = (uc - fv[pr.f0]) / pr.ax, dy = (vc - fv[pr.f0 + 1]) / pr.ay;
             const double rho = sqrt(dx * dx + dy * dy);
-            return sig_v(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho));
+            return sig_v<SIGS>(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho));
         }
-        case SG_PRIM_POLY: {
+    }
+    if constexpr ((TYPES & T_POLY) != 0) {
+        if (pr.type == SG_PRIM_POLY) {
             const int N = pr.nvert;
             const double* xs = fv + pr.f0;
             const double* ys = xs + N;
@@ -162,13 +212,15 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
                 const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
                 const double L = sqrt(ex * ex + ey * ey);
                 const double d = (ex * (vc - ys[i]) - ey * (uc - xs[i])) / L;
-                f *= sig_v(pr.sk0, pr.k0 * d);
+                f *= sig_v<SIGS>(pr.sk0, pr.k0 * d);
             }
             return f;
         }
-        default: {  // GCART
+    }
+    if constexpr ((TYPES & T_GCART) != 0) {
+        if (pr.type == SG_PRIM_GCART) {
             const int M = pr.nvert;
-            const double rx = rect_v(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1]);
+            const double rx = rect_v<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1]);
             if (rx == 0.0) return 0.0;
             int j;
             double t;
@@ -178,9 +230,10 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
             const double fp = (1.0 - t) * yp[j] + t * yp[j + 1];
             const double fm = (1.0 - t) * ym[j] + t * ym[j + 1];
             const double ky = kval(pr.sm1, pr.k1, vw);
-            return rx * sig_v(pr.sk1, ky * (fp - vc)) * sig_v(pr.sk1, ky * (vc - fm));
+            return rx * sig_v<SIGS>(pr.sk1, ky * (fp - vc)) * sig_v<SIGS>(pr.sk1, ky * (vc - fm));
         }
     }
+    return 0.0;
 }
 
 }  // namespace sg

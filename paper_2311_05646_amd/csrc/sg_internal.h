@@ -16,6 +16,8 @@ constexpr int kCandCap = 1024;     // candidate primitives staged in LDS per pas
 
 enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3 };
 enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
+// kernel feature variants (primitive types x in-plane sigma kinds), smallest first
+enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_ALL = 3 };
 
 // One primitive as the column kernel sees it.  The kernel works in (u, v, w)
 // sample coordinates: u = x (lanes, contiguous in memory), v = the other
@@ -107,7 +109,7 @@ struct KParams {
 
 // kernel launchers (sg_kernels.hip)
 hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st);
-hipError_t launch_column(int mode, int nclass_padded, const KParams& kp, hipStream_t st);
+hipError_t launch_column(int mode, int nclass_padded, int variant, const KParams& kp, hipStream_t st);
 hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int ncomp, int64_t plane,
                          float two_omega, float* g, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st);

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         if (cl.bounded) {
             const double wc = sp.wc[comp][w], wwid = sp.ww[comp][w];
             const double k = kval(cl.smode, cl.k, wwid);
-            rect_vd(cl.skind, k, wc, resolve(cl.flo), resolve(cl.fhi), z, dlo, dhi);
+            rect_vd<S_ALL>(cl.skind, k, wc, resolve(cl.flo), resolve(cl.fhi), z, dlo, dhi);
         }
         double* zt = sp.ztab[var] + 3 * t;
         zt[0] = z;
@@ -132,6 +132,11 @@ __device__ __forceinline__ void emit(const KParams& P, int field, float v) {
     if (__ballot(v != 0.0f) == 0) return;
     const float s = wave_sum(v);
     if ((threadIdx.x & 63) == 0) atomicAdd(P.grad + r.idx, r.b * (double)s);
+}
+
+__device__ __forceinline__ void add_field(const KParams& P, int field, float v) {
+    const sg_field r = P.fref[field];
+    if (r.idx >= 0 && v != 0.0f) atomicAdd(P.grad + r.idx, r.b * (double)v);
 }
 
 // Appends (in primitive order) every primitive whose support box meets the
@@ -185,7 +190,7 @@ __device__ __forceinline__ void add_to_class(double (&F)[NC], int cls, double v)
 }
 
 // Sum of F_h over the candidates, per class, at (uc, vc).
-template <int NC>
+template <int NC, int TYPES, int SIGS>
 __device__ void inplane_sums(const KParams& P, const double4* __restrict__ bbox, const double* __restrict__ fval,
                              const Tile& T, double uc, double uw, double vc, double vw, int* s_cand, int* s_cnt,
                              double (&F)[NC], int& nlist, bool& complete) {
@@ -203,71 +208,81 @@ __device__ void inplane_sums(const KParams& P, const double4* __restrict__ bbox,
             const int pi = uniform_int(s_cand[j]);
             if (!wave_meets(T, bbox[pi])) continue;
             const DevPrim pr = P.prims[pi];
-            const double f = prim_value(pr, fval, P.consts, uc, uw, vc, vw);
+            const double f = prim_value<TYPES, SIGS>(pr, fval, P.consts, uc, uw, vc, vw);
             add_to_class(F, pr.cls, f);
         }
     }
 }
 
-// Group sums -> root value s and, per group, d s / d (group sum) in {0, +-1}.
+// Composition at one column step: root value s and, per group g, the
+// derivative r_g = d s / d (group sum g) in {0, +1, -1}.
+struct Comp {
+    double s;
+    double r0, r1, r2, r3;
+};
+
+__device__ __forceinline__ void group_op(const KParams& P, int g, double S, double& val, double& msk) {
+    if (P.group_op[g] == SG_OP_INTERSECTION) {
+        const double nm1 = P.group_nm1[g];
+        val = fmax(nm1, S) - nm1;
+        msk = (S > nm1) ? 1.0 : 0.0;
+    } else {
+        val = fmin(1.0, S);
+        msk = (S < 1.0) ? 1.0 : 0.0;
+    }
+}
+
 template <int NC>
-__device__ __forceinline__ double compose(const KParams& P, const double (&F)[NC], const double* __restrict__ zt,
-                                          double (&rc)[kMaxGroups], double (&Z)[NC]) {
-    double S[kMaxGroups] = {0.0, 0.0, 0.0, 0.0};
+__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[NC], const double* __restrict__ zt,
+                                        double (&Z)[NC]) {
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (c < P.nclass) {
             Z[c] = zt[3 * c * P.nw];
             const double t = F[c] * Z[c];
             const int g = P.cls_group[c];
-            if (g == 0) S[0] += t;
-            else if (g == 1) S[1] += t;
-            else if (g == 2) S[2] += t;
-            else S[3] += t;
+            if (g == 0) S0 += t;
+            else if (g == 1) S1 += t;
+            else if (g == 2) S2 += t;
+            else S3 += t;
         } else {
             Z[c] = 0.0;
         }
     }
-    double val[kMaxGroups], msk[kMaxGroups];
-#pragma unroll
-    for (int g = 0; g < kMaxGroups; ++g) {
-        if (P.group_op[g] == SG_OP_INTERSECTION) {
-            val[g] = fmax(P.group_nm1[g], S[g]) - P.group_nm1[g];
-            msk[g] = (S[g] > P.group_nm1[g]) ? 1.0 : 0.0;
-        } else {
-            val[g] = fmin(1.0, S[g]);
-            msk[g] = (S[g] < 1.0) ? 1.0 : 0.0;
-        }
-    }
-    double s;
+    double v0, v1 = 0.0, v2 = 0.0, v3 = 0.0, m0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    group_op(P, 0, S0, v0, m0);
+    if (P.ngroup > 1) group_op(P, 1, S1, v1, m1);
+    if (P.ngroup > 2) group_op(P, 2, S2, v2, m2);
+    if (P.ngroup > 3) group_op(P, 3, S3, v3, m3);
+    Comp o;
     if (P.root_op == ROOT_NONE) {
-        s = val[0];
-        rc[0] = msk[0];
-        rc[1] = rc[2] = rc[3] = 0.0;
+        o.s = v0;
+        o.r0 = m0;
+        o.r1 = o.r2 = o.r3 = 0.0;
     } else if (P.root_op == SG_OP_DIFFERENCE) {
-        const double d = val[0] - val[1];
-        s = fmax(0.0, d);
+        const double d = v0 - v1;
+        o.s = fmax(0.0, d);
         const double m = d > 0.0 ? 1.0 : 0.0;
-        rc[0] = m * msk[0];
-        rc[1] = -m * msk[1];
-        rc[2] = rc[3] = 0.0;
+        o.r0 = m * m0;
+        o.r1 = -m * m1;
+        o.r2 = o.r3 = 0.0;
     } else {
-        double tot = 0.0;
-#pragma unroll
-        for (int g = 0; g < kMaxGroups; ++g)
-            if (g < P.ngroup) tot += val[g];
+        const double tot = v0 + v1 + v2 + v3;
         double m;
         if (P.root_op == SG_OP_UNION) {
-            s = fmin(1.0, tot);
+            o.s = fmin(1.0, tot);
             m = tot < 1.0 ? 1.0 : 0.0;
         } else {
-            s = fmax(P.root_nm1, tot) - P.root_nm1;
+            o.s = fmax(P.root_nm1, tot) - P.root_nm1;
             m = tot > P.root_nm1 ? 1.0 : 0.0;
         }
-#pragma unroll
-        for (int g = 0; g < kMaxGroups; ++g) rc[g] = (g < P.ngroup) ? m * msk[g] : 0.0;
+        o.r0 = m * m0;
+        o.r1 = m * m1;
+        o.r2 = m * m2;
+        o.r3 = m * m3;
     }
-    return s;
+    return o;
 }
 
 template <int NC>
@@ -281,15 +296,18 @@ __device__ __forceinline__ float class_pick(const float (&A)[NC], int cls) {
 
 // In-plane partials of one primitive times its class column sum a, reduced
 // over the wavefront and added to the gradient.
+template <int TYPES, int SIGS>
 __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float a, double uc, double uw,
                               double vc, double vw) {
     const double* fv = P.fval;
     const double ad = (double)a;
-    switch (pr.type) {
+    const int type = (TYPES == T_BOX) ? SG_PRIM_BOX : pr.type;
+    switch (type) {
         case SG_PRIM_BOX: {
+            if constexpr ((TYPES & T_BOX) == 0) break;
             double ru = 1.0, du0 = 0.0, du1 = 0.0, rv = 1.0, dv0 = 0.0, dv1 = 0.0;
-            if (pr.ubnd) rect_vd(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.fu0], fv[pr.fu1], ru, du0, du1);
-            if (pr.vbnd) rect_vd(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, fv[pr.fv0], fv[pr.fv1], rv, dv0, dv1);
+            if (pr.ubnd) rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.fu0], fv[pr.fu1], ru, du0, du1);
+            if (pr.vbnd) rect_vd<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, fv[pr.fv0], fv[pr.fv1], rv, dv0, dv1);
             if (pr.ubnd) {
                 emit(P, pr.fu0, (float)(ad * du0 * rv));
                 emit(P, pr.fu1, (float)(ad * du1 * rv));
@@ -301,11 +319,12 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
             break;
         }
         case SG_PRIM_ELLIPSE: {
+            if constexpr ((TYPES & T_ELL) == 0) break;
             const double dx = uc - fv[pr.f0], dy = vc - fv[pr.f0 + 1];
             const double qx = dx / pr.ax, qy = dy / pr.ay;
             const double rho = sqrt(qx * qx + qy * qy);
             double s, ds;
-            sig_vd(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho), s, ds);
+            sig_vd<SIGS>(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho), s, ds);
             const double g = ad * pr.k0 * ds;  // a * dF / d(r - rho)
             const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
             emit(P, pr.f0, (float)(g * qx * inv / pr.ax));       // -drho/dx0 = dx / (ax^2 rho)
@@ -314,6 +333,7 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
             break;
         }
         case SG_PRIM_POLY: {
+            if constexpr ((TYPES & T_POLY) == 0) break;
             const int N = pr.nvert;
             const double* xs = fv + pr.f0;
             const double* ys = xs + N;
@@ -323,7 +343,7 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
                 const int j = (i + 1 == N) ? 0 : i + 1;
                 const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
                 const double L = sqrt(ex * ex + ey * ey);
-                const double sv = sig_v(pr.sk0, pr.k0 * (ex * (vc - ys[i]) - ey * (uc - xs[i])) / L);
+                const double sv = sig_v<SIGS>(pr.sk0, pr.k0 * (ex * (vc - ys[i]) - ey * (uc - xs[i])) / L);
                 if (sv == 0.0) { ++nzero; zidx = i; } else { pnz *= sv; }
             }
             for (int i = 0; i < N; ++i) {
@@ -333,7 +353,7 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
                 const double wx = uc - xs[i], wy = vc - ys[i];
                 const double d = (ex * wy - ey * wx) / L;
                 double s, ds;
-                sig_vd(pr.sk0, pr.k0 * d, s, ds);
+                sig_vd<SIGS>(pr.sk0, pr.k0 * d, s, ds);
                 double other;
                 if (nzero == 0) other = pnz / s;
                 else if (nzero == 1 && zidx == i) other = pnz;
@@ -348,9 +368,10 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
             break;
         }
         default: {  // GCART
+            if constexpr ((TYPES & T_GCART) == 0) break;
             const int M = pr.nvert;
             double rx, drx0, drx1;
-            rect_vd(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1], rx, drx0, drx1);
+            rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1], rx, drx0, drx1);
             int j;
             double t;
             gcart_segment(P.consts + pr.c0, M, uc, j, t);
@@ -360,8 +381,8 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
             const double fm = (1.0 - t) * ym[j] + t * ym[j + 1];
             const double ky = kval(pr.sm1, pr.k1, vw);
             double sp, dsp, sm, dsm;
-            sig_vd(pr.sk1, ky * (fp - vc), sp, dsp);
-            sig_vd(pr.sk1, ky * (vc - fm), sm, dsm);
+            sig_vd<SIGS>(pr.sk1, ky * (fp - vc), sp, dsp);
+            sig_vd<SIGS>(pr.sk1, ky * (vc - fm), sm, dsm);
             const double fy = sp * sm;
             emit(P, pr.f0, (float)(ad * drx0 * fy));
             emit(P, pr.f0 + 1, (float)(ad * drx1 * fy));
@@ -378,12 +399,10 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
                 const float s0 = wave_sum(mine ? c0 : 0.0f), s1 = wave_sum(mine ? c1 : 0.0f);
                 const float s2 = wave_sum(mine ? c2 : 0.0f), s3 = wave_sum(mine ? c3 : 0.0f);
                 if ((threadIdx.x & 63) == 0) {
-                    const int fi[4] = {pr.f0 + 2 + j0, pr.f0 + 3 + j0, pr.f0 + 2 + M + j0, pr.f0 + 3 + M + j0};
-                    const float sv[4] = {s0, s1, s2, s3};
-                    for (int q = 0; q < 4; ++q) {
-                        const sg_field r = P.fref[fi[q]];
-                        if (r.idx >= 0 && sv[q] != 0.0f) atomicAdd(P.grad + r.idx, r.b * (double)sv[q]);
-                    }
+                    add_field(P, pr.f0 + 2 + j0, s0);
+                    add_field(P, pr.f0 + 3 + j0, s1);
+                    add_field(P, pr.f0 + 2 + M + j0, s2);
+                    add_field(P, pr.f0 + 3 + M + j0, s3);
                 }
                 pend &= ~__ballot(mine);
             }
@@ -393,7 +412,7 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
 }
 
 // ------------------------------------------------------------------ column kernel
-template <int MODE, int NC>
+template <int MODE, int NC, int TYPES, int SIGS>
 __global__ __launch_bounds__(256) void k_column(const KParams P) {
     __shared__ int s_cand[kCandCap];
     __shared__ int s_cnt[kBlock / 64];
@@ -446,18 +465,18 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
     double F[NC];
     int nlist;
     bool complete;
-    inplane_sums<NC>(P, P.bbox, P.fval, T, uc, uw, vc, vw, s_cand, s_cnt, F, nlist, complete);
+    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.fval, T, uc, uw, vc, vw, s_cand, s_cnt, F, nlist, complete);
     double F2[NC];
     if constexpr (MODE == MODE_FD) {
         int nl2;
         bool c2;
         __syncthreads();
-        inplane_sums<NC>(P, P.bbox2, P.fval2, T, uc, uw, vc, vw, s_cand, s_cnt, F2, nl2, c2);
+        inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.fval2, T, uc, uw, vc, vw, s_cand, s_cnt, F2, nl2, c2);
     }
 
     const int w0 = seg * P.seglen;
     const int w1 = min(w0 + P.seglen, P.nw);
-    const int64_t base = (int64_t)comp * P.plane + (int64_t)uu + (int64_t)vv * P.sv;
+    const int64_t b0 = (int64_t)uu + (int64_t)vv * P.sv;     // offset within a component plane
     const double* __restrict__ zt0 = P.ztab + (int64_t)comp * P.nclass * P.nw * 3;
 
     float A[NC], Blo[NC], Bhi[NC];
@@ -466,49 +485,62 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
 
     if constexpr (MODE == MODE_EPS || MODE == MODE_FD) {
         const double* __restrict__ zt2 = (MODE == MODE_FD) ? P.ztab2 + (int64_t)comp * P.nclass * P.nw * 3 : nullptr;
+        float* __restrict__ outp = P.out + (int64_t)comp * P.plane + b0;
 #pragma unroll 2
         for (int w = w0; w < w1; ++w) {
-            double rc[kMaxGroups], Z[NC];
-            const double s = compose<NC>(P, F, zt0 + 3 * w, rc, Z);
+            double Z[NC];
+            const double s = compose<NC>(P, F, zt0 + 3 * w, Z).s;
             float out;
             if constexpr (MODE == MODE_EPS) {
                 out = (float)(P.eps_bg + P.deps * s);
             } else {
-                const double s2 = compose<NC>(P, F2, zt2 + 3 * w, rc, Z);
+                const double s2 = compose<NC>(P, F2, zt2 + 3 * w, Z).s;
                 out = (float)(P.deps * (s - s2));
             }
-            if (act) P.out[base + (int64_t)w * P.sw] = out;
+            if (act) outp[(int64_t)w * P.sw] = out;
         }
         return;
     } else {
-#pragma unroll 2
-        for (int w = w0; w < w1; ++w) {
-            const int64_t idx = base + (int64_t)w * P.sw;
-            float gs = 0.0f;
-            if constexpr (MODE == MODE_VJP_FIELDS) {
-                if (act) {
-                    const float2 e = P.ef[comp][idx - (int64_t)comp * P.plane];
-                    const float2 a = P.ea[comp][idx - (int64_t)comp * P.plane];
-                    gs = P.two_omega * (e.x * a.y + e.y * a.x);   // 2 omega Im(E Eadj)
+        const float2* __restrict__ efp = P.ef[comp];
+        const float2* __restrict__ eap = P.ea[comp];
+        const float* __restrict__ gpl = P.geps + (int64_t)comp * P.plane;
+        // U column steps per iteration: every load of the group is issued before
+        // the first one is used, so each wavefront keeps 2U loads in flight.
+        constexpr int U = 4;
+        for (int w = w0; w < w1; w += U) {
+            float gs[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int wq = min(w + q, w1 - 1);
+                const int64_t i = b0 + (int64_t)wq * P.sw;
+                if constexpr (MODE == MODE_VJP_FIELDS) {
+                    const float2 e = efp[i], a = eap[i];
+                    gs[q] = P.two_omega * (e.x * a.y + e.y * a.x);   // 2 omega Im(E Eadj)
+                } else {
+                    gs[q] = gpl[i];
                 }
-            } else {
-                if (act) gs = P.geps[idx];
+                if (!act || w + q >= w1) gs[q] = 0.0f;
             }
-            double rc[kMaxGroups], Z[NC];
-            compose<NC>(P, F, zt0 + 3 * w, rc, Z);
-            float cg[kMaxGroups];
 #pragma unroll
-            for (int g = 0; g < kMaxGroups; ++g) cg[g] = gs * (float)(P.deps * rc[g]);
+            for (int q = 0; q < U; ++q) {
+                if (w + q < w1) {
+                    double Z[NC];
+                    const Comp o = compose<NC>(P, F, zt0 + 3 * (w + q), Z);
+                    const float gd = gs[q] * (float)P.deps;
+                    const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
+                    const float cg2 = gd * (float)o.r2, cg3 = gd * (float)o.r3;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c < P.nclass) {
-                    const int g = P.cls_group[c];
-                    const float cc = (g == 0) ? cg[0] : (g == 1) ? cg[1] : (g == 2) ? cg[2] : cg[3];
-                    A[c] += cc * (float)Z[c];
-                    if (P.cls_wparam[c]) {
-                        const double* z = zt0 + 3 * ((int64_t)c * P.nw + w);
-                        Blo[c] += cc * (float)z[1];
-                        Bhi[c] += cc * (float)z[2];
+                    for (int c = 0; c < NC; ++c) {
+                        if (c < P.nclass) {
+                            const int g = P.cls_group[c];
+                            const float cc = (g == 0) ? cg0 : (g == 1) ? cg1 : (g == 2) ? cg2 : cg3;
+                            A[c] += cc * (float)Z[c];
+                            if (P.cls_wparam[c]) {
+                                const double* z = zt0 + 3 * ((int64_t)c * P.nw + w + q);
+                                Blo[c] += cc * (float)z[1];
+                                Bhi[c] += cc * (float)z[2];
+                            }
+                        }
                     }
                 }
             }
@@ -549,7 +581,7 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
             const DevPrim pr = P.prims[pi];
             const float a = class_pick<NC>(A, pr.cls);
             if (__ballot(a != 0.0f) == 0) continue;
-            emit_partials(P, pr, pi, a, uc, uw, vc, vw);
+            emit_partials<TYPES, SIGS>(P, pr, pi, a, uc, uw, vc, vw);
         }
     }
 }
@@ -615,25 +647,35 @@ hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int MODE>
-static hipError_t launch_mode(int ncls, const KParams& kp, hipStream_t st) {
+template <int MODE, int TYPES, int SIGS>
+static hipError_t launch_variant(int ncls, const KParams& kp, hipStream_t st) {
     const int64_t blocks = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
     const dim3 grid((unsigned)blocks), blk(256);
     switch (ncls) {
-        case 1: hipLaunchKernelGGL((k_column<MODE, 1>), grid, blk, 0, st, kp); break;
-        case 2: hipLaunchKernelGGL((k_column<MODE, 2>), grid, blk, 0, st, kp); break;
-        case 4: hipLaunchKernelGGL((k_column<MODE, 4>), grid, blk, 0, st, kp); break;
-        default: hipLaunchKernelGGL((k_column<MODE, 8>), grid, blk, 0, st, kp); break;
+        case 1: hipLaunchKernelGGL((k_column<MODE, 1, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case 2: hipLaunchKernelGGL((k_column<MODE, 2, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case 4: hipLaunchKernelGGL((k_column<MODE, 4, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        default: hipLaunchKernelGGL((k_column<MODE, 8, TYPES, SIGS>), grid, blk, 0, st, kp); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_column(int mode, int ncls, const KParams& kp, hipStream_t st) {
+template <int MODE>
+static hipError_t launch_mode(int ncls, int variant, const KParams& kp, hipStream_t st) {
+    switch (variant) {
+        case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(ncls, kp, st);
+        case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(ncls, kp, st);
+        case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(ncls, kp, st);
+        default: return launch_variant<MODE, T_ALL, S_ALL>(ncls, kp, st);
+    }
+}
+
+hipError_t launch_column(int mode, int ncls, int variant, const KParams& kp, hipStream_t st) {
     switch (mode) {
-        case MODE_EPS: return launch_mode<MODE_EPS>(ncls, kp, st);
-        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(ncls, kp, st);
-        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(ncls, kp, st);
-        default: return launch_mode<MODE_FD>(ncls, kp, st);
+        case MODE_EPS: return launch_mode<MODE_EPS>(ncls, variant, kp, st);
+        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(ncls, variant, kp, st);
+        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(ncls, variant, kp, st);
+        default: return launch_mode<MODE_FD>(ncls, variant, kp, st);
     }
 }
 
