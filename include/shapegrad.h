@@ -179,6 +179,66 @@ sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_de
                       const void* const* e_fwd, const void* const* e_adj, double omega,
                       double h, int scheme, double* grad, int grad_on_device, void* stream);
 
+/* Synthetic fields: n complex64 values each of E_fwd and E_adj (device), from
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (i mod 2^32, i div 2^32, 0, 0)
+ * and key (seed mod 2^32, seed div 2^32); u_k = (x_k + 1/2) 2^-32 and two
+ * Box-Muller pairs: E = sqrt(-2 ln u0) e^{2 pi i u1}, E_adj = sqrt(-2 ln u2) e^{2 pi i u3}
+ * (FP32).  Used by the serving loop for requests that carry a field seed. */
+sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching loop for gradient requests from many
+ * concurrent optimizations (sessions) with different scenes, grid sizes and
+ * parameter counts.  A scheduler thread admits queued requests in arrival
+ * order while request slots and the HBM budget allow, gives each admitted
+ * request its own device buffers (seeded fields, staging, gradient; reused per
+ * session), groups admitted requests into batched launches (one kernel launch
+ * covers the tiles of every request of the same kernel specialization) and
+ * issues batches on several streams in turn, so requests that arrive while
+ * others run are admitted and overlap with them on the device.  Completion is
+ * tracked with events; results wait in host memory until polled.
+ * Each request computes eps_grad_vjp of its session's scene at its own p, with
+ * fields drawn by sg_fieldgen from its seed.
+ * ------------------------------------------------------------------------- */
+typedef struct sg_server sg_server;
+typedef struct sg_server_opts {
+    int64_t hbm_budget_bytes;   /* device bytes admitted requests may hold at once (> 0) */
+    int32_t max_slots;          /* requests admitted at once (>= 1) */
+    int32_t max_batch;          /* requests per batch (>= 1) */
+    int32_t n_streams;          /* batches in flight at once, one per stream (1..8) */
+    int32_t fake_executor;      /* 1: no device work (scheduling tests); the result of a
+                                   request is grad_k = 2 p_k + (seed mod 1000) after fake_us */
+    int64_t fake_us;
+} sg_server_opts;
+typedef struct sg_req_stats {
+    int64_t submit_ns, admit_ns, launch_ns, done_ns;   /* steady-clock times */
+    int32_t batch_size;                                /* requests in its batch */
+    int32_t pad;
+} sg_req_stats;
+
+/* ctx may be NULL only with fake_executor = 1. */
+sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* opts, sg_server** out);
+/* Cancels queued requests, waits for launched ones, frees everything. */
+sg_status sg_server_destroy(sg_server* server);
+/* A session runs its requests on `scene` (which must outlive the server). */
+sg_status serve_open_session(sg_server* server, sg_scene* scene, uint32_t* session);
+/* Fake-executor sessions (scheduling tests): n_params and bytes per request given directly. */
+sg_status serve_open_fake_session(sg_server* server, int64_t n_params, int64_t request_bytes, uint32_t* session);
+/* Queues a request (p: n_params FP64 on the host, copied).  Never blocks.
+ * SG_E_TOO_LARGE if the request can never fit the budget. */
+sg_status serve_submit(sg_server* server, uint32_t session, const double* p, uint64_t field_seed, double omega,
+                       uint64_t* ticket);
+/* Waits up to timeout_us (0: no wait, < 0: forever) for a request.  SG_OK: done,
+ * the gradient (n_params FP64) is copied to grad_out (host) and the ticket is
+ * retired; SG_EAGAIN: not done yet; SG_E_CANCELLED / SG_E_DEVICE: retired with
+ * that outcome.  stats may be NULL. */
+sg_status serve_poll(sg_server* server, uint64_t ticket, double* grad_out, int64_t timeout_us, sg_req_stats* stats);
+/* Cancels a request: queued requests never run; launched ones finish but their result is dropped. */
+sg_status serve_cancel(sg_server* server, uint64_t ticket);
+/* Counters: requests completed, batches launched, largest batch, bytes admitted now. */
+sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches, int64_t* max_batch_seen,
+                         int64_t* bytes_in_use);
+
 /* Kernel tracing.  With timing enabled the scene records a pair of HIP events
  * on the call's stream around every launch of its main column kernel.
  * sg_scene_set_timing(scene, 1) enables and clears the records, 0 disables.

@@ -51,6 +51,16 @@ class sg_scene_desc(C.Structure):
                 ("children", C.POINTER(C.c_int32))]
 
 
+class sg_server_opts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("max_batch", C.c_int32),
+                ("n_streams", C.c_int32), ("fake_executor", C.c_int32), ("fake_us", C.c_int64)]
+
+
+class sg_req_stats(C.Structure):
+    _fields_ = [("submit_ns", C.c_int64), ("admit_ns", C.c_int64), ("launch_ns", C.c_int64), ("done_ns", C.c_int64),
+                ("batch_size", C.c_int32), ("pad", C.c_int32)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -72,6 +82,16 @@ SIGNATURES = {
     "sg_scene_set_timing": (_S, [_P, _I]),
     "sg_scene_kernel_time": (_S, [_P, _I, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sg_util_copy": (_S, [_P, _P, C.c_int64, _P]),
+    "sg_fieldgen": (_S, [_P, _P, C.c_int64, C.c_uint64, _P]),
+    "sg_server_create": (_S, [_P, C.POINTER(sg_server_opts), C.POINTER(_P)]),
+    "sg_server_destroy": (_S, [_P]),
+    "serve_open_session": (_S, [_P, _P, C.POINTER(C.c_uint32)]),
+    "serve_open_fake_session": (_S, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_uint32)]),
+    "serve_submit": (_S, [_P, C.c_uint32, _P, C.c_uint64, _D, C.POINTER(C.c_uint64)]),
+    "serve_poll": (_S, [_P, C.c_uint64, _P, C.c_int64, C.POINTER(sg_req_stats)]),
+    "serve_cancel": (_S, [_P, C.c_uint64]),
+    "serve_counters": (_S, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                            C.POINTER(C.c_int64)]),
 }
 
 _lib = None

@@ -163,6 +163,88 @@ def util_copy(dst, src, stream=None):
     check(lib().sg_util_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n, _stream(stream)))
 
 
+def fieldgen(scene_or_shape, seed, stream=None):
+    """E_fwd, E_adj complex64 CUDA tensors drawn by the library's Philox
+    generator from `seed` (the fields a serving request with that seed uses)."""
+    shape = scene_or_shape.shape if isinstance(scene_or_shape, Scene) else tuple(scene_or_shape)
+    E = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    A = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    check(lib().sg_fieldgen(C.c_void_p(E.data_ptr()), C.c_void_p(A.data_ptr()), E.numel(), int(seed),
+                            _stream(stream)))
+    return E, A
+
+
+class Server:
+    """Continuous-batching gradient server (C++ scheduler thread in the
+    library).  submit() queues a request and returns a ticket; poll() waits for
+    its gradient."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_batch=16, n_streams=2, device=0,
+                 fake_executor=False, fake_us=0):
+        o = _lib.sg_server_opts(int(hbm_budget_bytes), int(max_slots), int(max_batch), int(n_streams),
+                                int(bool(fake_executor)), int(fake_us))
+        h = C.c_void_p()
+        ctx = None if fake_executor else context(device)
+        check(lib().sg_server_create(ctx, C.byref(o), C.byref(h)))
+        self.handle = h
+        self.n_params = {}
+        self._scenes = []
+
+    def open_session(self, scene):
+        sid = C.c_uint32()
+        check(lib().serve_open_session(self.handle, scene.handle, C.byref(sid)))
+        self.n_params[sid.value] = scene.n_params
+        self._scenes.append(scene)
+        return sid.value
+
+    def open_fake_session(self, n_params, request_bytes):
+        sid = C.c_uint32()
+        check(lib().serve_open_fake_session(self.handle, int(n_params), int(request_bytes), C.byref(sid)))
+        self.n_params[sid.value] = int(n_params)
+        return sid.value
+
+    def submit(self, session, p, seed, omega):
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        n = self.n_params.get(session)
+        if n is not None and a.size != n:
+            raise ValueError("p has the wrong size for this session")
+        t = C.c_uint64()
+        check(lib().serve_submit(self.handle, int(session), C.c_void_p(a.ctypes.data), int(seed), float(omega),
+                                 C.byref(t)))
+        return t.value
+
+    def poll(self, ticket, n_params, timeout_us=-1):
+        """(status, grad or None, stats dict).  status 'ok' | 'pending' (raises
+        on cancelled / failed)."""
+        g = np.empty(max(1, n_params), dtype=np.float64)
+        st = _lib.sg_req_stats()
+        r = lib().serve_poll(self.handle, int(ticket), C.c_void_p(g.ctypes.data), int(timeout_us), C.byref(st))
+        if r == _lib.SG_EAGAIN:
+            return "pending", None, None
+        check(r)
+        stats = {k: getattr(st, k) for k in ("submit_ns", "admit_ns", "launch_ns", "done_ns", "batch_size")}
+        return "ok", g[:n_params], stats
+
+    def cancel(self, ticket):
+        check(lib().serve_cancel(self.handle, int(ticket)))
+
+    def counters(self):
+        v = [C.c_int64() for _ in range(4)]
+        check(lib().serve_counters(self.handle, *[C.byref(x) for x in v]))
+        return dict(zip(("completed", "batches", "max_batch", "bytes_in_use"), [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(lib().sg_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class EpsBuild(torch.autograd.Function):
     """eps(p) as a differentiable op: forward = eps_build, backward = the
     fused reverse-mode kernel (eps_grad_vjp_geps) that recomputes

@@ -9,14 +9,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshapegrad.so")
-SOURCES = ["sg_api.hip", "sg_kernels.hip"]
+SOURCES = ["sg_api.hip", "sg_kernels.hip", "sg_serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
     # never let the compiler form packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-variable", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-variable", "-Wno-unused-function", "-pthread",
 ]
 
 

@@ -15,13 +15,14 @@
 
 #include "sg_device.h"
 #include "sg_internal.h"
+#include "sg_scene.h"
 
 using namespace sg;
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
-static sg_status fail(sg_status code, const char* fmt, ...) {
+sg_status sg::fail(sg_status code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -31,19 +32,9 @@ static sg_status fail(sg_status code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_OK(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess) return fail(SG_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
 extern "C" const char* sg_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------ context
-struct sg_ctx {
-    int device;
-};
-
 extern "C" sg_status sg_ctx_create(int hip_device, sg_ctx** out) {
     if (!out) return fail(SG_E_INVALID, "sg_ctx_create: out is NULL");
     int n = 0;
@@ -57,52 +48,6 @@ extern "C" sg_status sg_ctx_create(int hip_device, sg_ctx** out) {
 }
 
 extern "C" void sg_ctx_destroy(sg_ctx* ctx) { delete ctx; }
-
-// ------------------------------------------------------------------ scene
-struct sg_scene {
-    sg_ctx* ctx = nullptr;
-    int dim = 0, ncomp = 0, comp_axis[3] = {0, 0, 0};
-    int64_t n[3] = {0, 0, 0};
-    int64_t n_params = 0;
-    int64_t nfield = 0;
-    double eps_bg = 0, eps_fg = 0;
-    int col = 2;                      // column axis: 1 (y) or 2 (z)
-    int axis_v = 1;
-    int nu = 0, nv = 0, nw = 0;
-    int64_t sv = 0, sw = 0, plane = 0;
-    int nprim = 0, nclass = 0, ncls_pad = 1;
-    int variant = VAR_ALL;
-    int ngroup = 0, root_op = ROOT_NONE;
-    int group_op[kMaxGroups] = {0, 0, 0, 0};
-    double group_nm1[kMaxGroups] = {0, 0, 0, 0};
-    double root_nm1 = 0;
-    std::vector<DevClass> classes;
-    std::vector<sg_field> fields;
-    int block_x = 0, nseg = 0;        // 0: automatic
-    // device tables
-    double* d_lat = nullptr;          // per component: uc uw vc vw wc ww
-    int64_t lat_off[kMaxComp][6] = {};
-    sg_field* d_fref = nullptr;
-    DevPrim* d_prims = nullptr;
-    DevClass* d_cls = nullptr;
-    double* d_consts = nullptr;
-    double* d_p = nullptr;
-    double* d_fval[2] = {nullptr, nullptr};
-    double4* d_bbox[2] = {nullptr, nullptr};
-    double* d_ztab[2] = {nullptr, nullptr};
-    double* d_grad = nullptr;
-    float* d_work[2] = {nullptr, nullptr};
-    double* h_p = nullptr;            // pinned staging
-    double* h_grad = nullptr;
-    hipEvent_t p_evt = nullptr;
-    bool p_evt_pending = false;
-    // tracing: events around the main column-kernel launches
-    bool timing = false;
-    struct Rec { int mode; hipEvent_t a, b; };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> evpool;
-    std::mutex mu;
-};
 
 static void axis_samples(const double* A, int64_t N, bool cell, std::vector<double>& c, std::vector<double>& w) {
     c.resize(N);
@@ -480,6 +425,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             if (p.type == SG_PRIM_ELLIPSE) {
                 r.ax = d->consts[p.const_off];
                 r.ay = d->consts[p.const_off + 1];
+                r.iax = 1.0 / r.ax;
+                r.iay = 1.0 / r.ay;
             }
         }
         prims.push_back(r);
@@ -505,6 +452,20 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         s->variant = VAR_ALL;
         for (int v = 0; v < 3; ++v)
             if ((tmask & ~vt[v]) == 0 && (smask & ~vs[v]) == 0) { s->variant = v; break; }
+        // op-tree layout
+        auto plain_union = [&](int g) { return groups[g].op == SG_OP_UNION || groups[g].nmember == 1; };
+        int ncls_g[kMaxGroups] = {0, 0, 0, 0};
+        for (const DevClass& c : s->classes) ncls_g[c.group]++;
+        s->tree = s->nclass <= 4 ? TR_GEN4 : TR_GEN8;
+        if (s->ngroup == 1 && plain_union(0)) {
+            if (s->nclass == 1) s->tree = TR_U1;
+            else if (s->nclass == 2) s->tree = TR_U2;
+        } else if (s->ngroup == 2 && s->root_op == SG_OP_DIFFERENCE && plain_union(0) && plain_union(1) &&
+                   ncls_g[0] == 1) {
+            if (ncls_g[1] == 1) s->tree = TR_D11;
+            else if (ncls_g[1] == 2) s->tree = TR_D12;
+        }
+        if (s->tree == TR_GEN4 || s->tree == TR_GEN8) s->variant = VAR_ALL;
     }
 
     // device allocations
@@ -585,7 +546,7 @@ static sg_status stage_p(sg_scene* s, const double* p, int p_on_device, hipStrea
     return SG_OK;
 }
 
-static StageParams stage_params(sg_scene* s, const double* dp) {
+StageParams sg::stage_params(sg_scene* s, const double* dp) {
     StageParams sp{};
     sp.nprim = s->nprim;
     sp.nclass = s->nclass;
@@ -615,7 +576,7 @@ static StageParams stage_params(sg_scene* s, const double* dp) {
     return sp;
 }
 
-static KParams column_params(sg_scene* s) {
+KParams sg::column_params(sg_scene* s) {
     KParams kp{};
     kp.nu = s->nu;
     kp.nv = s->nv;
@@ -627,7 +588,7 @@ static KParams column_params(sg_scene* s) {
     int tu = s->block_x;
     if (tu == 0) {
         if (s->nv == 1) tu = 256;
-        else tu = s->nprim > 32 ? 16 : 64;
+        else tu = s->nprim > 32 ? 16 : 128;
     }
     kp.tu = tu;
     kp.tv = kBlock / tu;
@@ -636,7 +597,7 @@ static KParams column_params(sg_scene* s) {
     int nseg = s->nseg;
     if (nseg == 0) {
         const int64_t base = (int64_t)s->ncomp * kp.tiles_u * kp.tiles_v;
-        const int64_t target = 2048;
+        const int64_t target = 1024;
         nseg = (int)std::max<int64_t>(1, std::min<int64_t>((target + base - 1) / base, (s->nw + 15) / 16));
     }
     nseg = std::min(nseg, s->nw);
@@ -681,6 +642,11 @@ static KParams column_params(sg_scene* s) {
     return kp;
 }
 
+int64_t sg::staging_bytes(const sg_scene* s) {
+    return 8 * std::max<int64_t>(1, s->nfield) + 32 * (int64_t)s->nprim +
+           24 * (int64_t)s->ncomp * s->nclass * s->nw + 16 * std::max<int64_t>(1, s->n_params);
+}
+
 static sg_status check_call(sg_ctx* ctx, sg_scene* s) {
     if (!ctx || !s) return fail(SG_E_INVALID, "NULL ctx or scene");
     if (s->ctx->device != ctx->device) return fail(SG_E_INVALID, "scene belongs to another device");
@@ -708,14 +674,14 @@ static hipError_t take_event(sg_scene* s, hipEvent_t* e) {
 // Launches the column kernel, bracketed by events when tracing is on.
 static sg_status run_column(sg_scene* s, int mode, const KParams& kp, hipStream_t st) {
     if (!s->timing) {
-        HIP_OK(launch_column(mode, s->ncls_pad, s->variant, kp, st));
+        HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));
         return SG_OK;
     }
     sg_scene::Rec r{mode, nullptr, nullptr};
     HIP_OK(take_event(s, &r.a));
     HIP_OK(take_event(s, &r.b));
     HIP_OK(hipEventRecord(r.a, st));
-    HIP_OK(launch_column(mode, s->ncls_pad, s->variant, kp, st));
+    HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));
     HIP_OK(hipEventRecord(r.b, st));
     s->recs.push_back(r);
     return SG_OK;

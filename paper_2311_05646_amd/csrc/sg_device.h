@@ -136,6 +136,29 @@ __device__ __forceinline__ void sig_vd(int kind, double t, double& s, double& ds
     }
 }
 
+// d sigma / d t in FP32 (derivative-only uses; the sigma value stays FP64)
+__device__ __forceinline__ float sig_d32(int kind, float t) {
+    switch (kind) {
+        case SG_SIGMA_SIGMOID: {
+            if (t <= -(float)kSigmoidCut || t >= (float)kSigmoidCut) return 0.0f;
+            const float e = __expf(-fabsf(t));
+            const float s = 1.0f / (1.0f + e);
+            return s * (1.0f - s);
+        }
+        case SG_SIGMA_ERF:
+            if (t <= -(float)kErfCut || t >= (float)kErfCut) return 0.0f;
+            return __expf(-t * t) * (float)kInvSqrtPi;
+        case SG_SIGMA_SIN:
+            return (t > -(float)kPiHalf && t < (float)kPiHalf) ? 0.5f * __cosf(t) : 0.0f;
+        case SG_SIGMA_LINEAR:
+            return (t > -0.5f && t < 0.5f) ? 1.0f : 0.0f;
+        default:
+            if (t > -(float)kInvSqrt2 && t < 0.0f) return 2.0f * ((float)kInvSqrt2 + t);
+            if (t >= 0.0f && t < (float)kInvSqrt2) return 2.0f * ((float)kInvSqrt2 - t);
+            return 0.0f;
+    }
+}
+
 // host + device: kind -> bit
 __host__ __device__ inline int sigma_bit(int kind) { return 1 << kind; }
 
@@ -196,9 +219,13 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
     }
     if constexpr ((TYPES & T_ELL) != 0) {
         if (pr.type == SG_PRIM_ELLIPSE) {
-            const double dx = (uc - fv[pr.f0]) / pr.ax, dy = (vc - fv[pr.f0 + 1]) / pr.ay;
-            const double rho = sqrt(dx * dx + dy * dy);
-            return sig_v<SIGS>(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho));
+            const double dx = (uc - fv[pr.f0]) * pr.iax, dy = (vc - fv[pr.f0 + 1]) * pr.iay;
+            const double rho2 = dx * dx + dy * dy;
+            const double r = fv[pr.f0 + 2];
+            const double rhi = r + pr.reach0, rlo = r - pr.reach0;
+            if (rhi <= 0.0 || rho2 >= rhi * rhi) return 0.0;      // beyond the sigma support
+            if (rlo > 0.0 && rho2 <= rlo * rlo) return 1.0;
+            return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
     if constexpr ((TYPES & T_POLY) != 0) {

@@ -13,11 +13,23 @@ constexpr int kMaxGroups = 4;
 constexpr int kMaxClasses = 8;
 constexpr int kBlock = 256;        // threads (= in-plane samples) per block
 constexpr int kCandCap = 1024;     // candidate primitives staged in LDS per pass
+constexpr int kZStage = 512;       // extrusion-table entries staged in LDS per chunk
 
 enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3 };
 enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
 // kernel feature variants (primitive types x in-plane sigma kinds), smallest first
 enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_ALL = 3 };
+// op-tree layouts compiled into the column kernel: one union over 1 or 2
+// extrusion classes; the difference of two unions over (1, 1) or (1, 2)
+// classes; anything else through the generic composition (4 or 8 classes).
+enum Tree { TR_U1 = 0, TR_U2 = 1, TR_D11 = 2, TR_D12 = 3, TR_GEN4 = 4, TR_GEN8 = 5 };
+__host__ __device__ constexpr int tree_nc(int tr) {
+    return tr == TR_U1 ? 1 : tr == TR_U2 ? 2 : tr == TR_D11 ? 2 : tr == TR_D12 ? 3 : tr == TR_GEN4 ? 4 : 8;
+}
+// group of class c in the fixed layouts (-1: decided at run time)
+__host__ __device__ constexpr int tree_group(int tr, int c) {
+    return (tr == TR_U1 || tr == TR_U2) ? 0 : (tr == TR_D11 || tr == TR_D12) ? (c == 0 ? 0 : 1) : -1;
+}
 
 // One primitive as the column kernel sees it.  The kernel works in (u, v, w)
 // sample coordinates: u = x (lanes, contiguous in memory), v = the other
@@ -38,6 +50,7 @@ struct DevPrim {
     double k0, k1;         // k_r (LOCAL) or k (FIXED)
     double reach0, reach1; // support half-width of each argument (um), for the support boxes
     double ax, ay;         // ELLIPSE aspect
+    double iax, iay;       // 1 / aspect
 };
 
 // An extrusion class: primitives of one group that share the same factor
@@ -109,7 +122,13 @@ struct KParams {
 
 // kernel launchers (sg_kernels.hip)
 hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st);
-hipError_t launch_column(int mode, int nclass_padded, int variant, const KParams& kp, hipStream_t st);
+hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st);
+// fused VJP (E, Eadj fields) over several requests of one kernel specialization:
+// plist / first in device memory, blocks = first[nreq]
+hipError_t launch_column_batch(int tree, int variant, const KParams* plist, const int* first, int nreq,
+                               int64_t blocks, hipStream_t st);
+// Philox4x32-10 N(0,1) complex64 planes (see shapegrad.h: sg_fieldgen)
+hipError_t launch_fieldgen(float2* e, float2* a, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int ncomp, int64_t plane,
                          float two_omega, float* g, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st);

@@ -116,10 +116,22 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
 }
 
 // ------------------------------------------------------------------ helpers
+// Sum over the 64 lanes of a wavefront with DPP lane moves (no LDS traffic):
+// quad swaps, row rotations, then the two row broadcasts of wave64; lane 63
+// ends up with the total, which is returned to every lane.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+    return v + __int_as_float(moved);
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x124, 0xF>(v);   // row_ror:4
+    v = dpp_add<0x128, 0xF>(v);   // row_ror:8
+    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 -> rows 1, 3
+    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31 -> rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -232,165 +244,201 @@ __device__ __forceinline__ void group_op(const KParams& P, int g, double S, doub
     }
 }
 
-template <int NC>
-__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[NC], const double* __restrict__ zt,
-                                        double (&Z)[NC]) {
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (c < P.nclass) {
-            Z[c] = zt[3 * c * P.nw];
-            const double t = F[c] * Z[c];
-            const int g = P.cls_group[c];
-            if (g == 0) S0 += t;
-            else if (g == 1) S1 += t;
-            else if (g == 2) S2 += t;
-            else S3 += t;
-        } else {
-            Z[c] = 0.0;
-        }
-    }
-    double v0, v1 = 0.0, v2 = 0.0, v3 = 0.0, m0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
-    group_op(P, 0, S0, v0, m0);
-    if (P.ngroup > 1) group_op(P, 1, S1, v1, m1);
-    if (P.ngroup > 2) group_op(P, 2, S2, v2, m2);
-    if (P.ngroup > 3) group_op(P, 3, S3, v3, m3);
+// zs points at the class-0 entry of this column step; class c sits zstride further.
+template <int TREE>
+__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree_nc(TREE)], const double* zs,
+                                        int zstride, double (&Z)[tree_nc(TREE)]) {
+    constexpr int NC = tree_nc(TREE);
     Comp o;
-    if (P.root_op == ROOT_NONE) {
-        o.s = v0;
-        o.r0 = m0;
+    if constexpr (TREE == TR_U1 || TREE == TR_U2) {
+        double S = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            Z[c] = zs[c * zstride];
+            S += F[c] * Z[c];
+        }
+        o.s = fmin(1.0, S);
+        o.r0 = S < 1.0 ? 1.0 : 0.0;
         o.r1 = o.r2 = o.r3 = 0.0;
-    } else if (P.root_op == SG_OP_DIFFERENCE) {
+        return o;
+    } else if constexpr (TREE == TR_D11 || TREE == TR_D12) {
+        Z[0] = zs[0];
+        const double S0 = F[0] * Z[0];
+        double S1 = 0.0;
+#pragma unroll
+        for (int c = 1; c < NC; ++c) {
+            Z[c] = zs[c * zstride];
+            S1 += F[c] * Z[c];
+        }
+        const double v0 = fmin(1.0, S0), v1 = fmin(1.0, S1);
         const double d = v0 - v1;
         o.s = fmax(0.0, d);
-        const double m = d > 0.0 ? 1.0 : 0.0;
-        o.r0 = m * m0;
-        o.r1 = -m * m1;
+        const bool pass = d > 0.0;
+        o.r0 = (pass && S0 < 1.0) ? 1.0 : 0.0;
+        o.r1 = (pass && S1 < 1.0) ? -1.0 : 0.0;
         o.r2 = o.r3 = 0.0;
+        return o;
     } else {
-        const double tot = v0 + v1 + v2 + v3;
-        double m;
-        if (P.root_op == SG_OP_UNION) {
-            o.s = fmin(1.0, tot);
-            m = tot < 1.0 ? 1.0 : 0.0;
-        } else {
-            o.s = fmax(P.root_nm1, tot) - P.root_nm1;
-            m = tot > P.root_nm1 ? 1.0 : 0.0;
-        }
-        o.r0 = m * m0;
-        o.r1 = m * m1;
-        o.r2 = m * m2;
-        o.r3 = m * m3;
-    }
-    return o;
-}
-
-template <int NC>
-__device__ __forceinline__ float class_pick(const float (&A)[NC], int cls) {
-    float a = 0.0f;
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (c == cls) a = A[c];
-    return a;
+        for (int c = 0; c < NC; ++c) {
+            if (c < P.nclass) {
+                Z[c] = zs[c * zstride];
+                const double t = F[c] * Z[c];
+                const int g = P.cls_group[c];
+                if (g == 0) S0 += t;
+                else if (g == 1) S1 += t;
+                else if (g == 2) S2 += t;
+                else S3 += t;
+            } else {
+                Z[c] = 0.0;
+            }
+        }
+        double v0, v1 = 0.0, v2 = 0.0, v3 = 0.0, m0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+        group_op(P, 0, S0, v0, m0);
+        if (P.ngroup > 1) group_op(P, 1, S1, v1, m1);
+        if (P.ngroup > 2) group_op(P, 2, S2, v2, m2);
+        if (P.ngroup > 3) group_op(P, 3, S3, v3, m3);
+        if (P.root_op == ROOT_NONE) {
+            o.s = v0;
+            o.r0 = m0;
+            o.r1 = o.r2 = o.r3 = 0.0;
+        } else if (P.root_op == SG_OP_DIFFERENCE) {
+            const double d = v0 - v1;
+            o.s = fmax(0.0, d);
+            const double m = d > 0.0 ? 1.0 : 0.0;
+            o.r0 = m * m0;
+            o.r1 = -m * m1;
+            o.r2 = o.r3 = 0.0;
+        } else {
+            const double tot = v0 + v1 + v2 + v3;
+            double m;
+            if (P.root_op == SG_OP_UNION) {
+                o.s = fmin(1.0, tot);
+                m = tot < 1.0 ? 1.0 : 0.0;
+            } else {
+                o.s = fmax(P.root_nm1, tot) - P.root_nm1;
+                m = tot > P.root_nm1 ? 1.0 : 0.0;
+            }
+            o.r0 = m * m0;
+            o.r1 = m * m1;
+            o.r2 = m * m2;
+            o.r3 = m * m3;
+        }
+        return o;
+    }
 }
 
-// In-plane partials of one primitive times its class column sum a, reduced
-// over the wavefront and added to the gradient.
-template <int TYPES, int SIGS>
-__device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float a, double uc, double uw,
-                              double vc, double vw) {
+
+// Partials of a convex polygon at one sample, times a; one reduction per
+// vertex field and edge.
+template <int SIGS>
+__device__ void poly_partials(const KParams& P, const DevPrim& pr, double ad, double uc, double vc) {
     const double* fv = P.fval;
-    const double ad = (double)a;
-    const int type = (TYPES == T_BOX) ? SG_PRIM_BOX : pr.type;
-    switch (type) {
-        case SG_PRIM_BOX: {
-            if constexpr ((TYPES & T_BOX) == 0) break;
-            double ru = 1.0, du0 = 0.0, du1 = 0.0, rv = 1.0, dv0 = 0.0, dv1 = 0.0;
-            if (pr.ubnd) rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.fu0], fv[pr.fu1], ru, du0, du1);
-            if (pr.vbnd) rect_vd<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, fv[pr.fv0], fv[pr.fv1], rv, dv0, dv1);
-            if (pr.ubnd) {
-                emit(P, pr.fu0, (float)(ad * du0 * rv));
-                emit(P, pr.fu1, (float)(ad * du1 * rv));
-            }
-            if (pr.vbnd) {
-                emit(P, pr.fv0, (float)(ad * ru * dv0));
-                emit(P, pr.fv1, (float)(ad * ru * dv1));
-            }
-            break;
-        }
-        case SG_PRIM_ELLIPSE: {
-            if constexpr ((TYPES & T_ELL) == 0) break;
-            const double dx = uc - fv[pr.f0], dy = vc - fv[pr.f0 + 1];
-            const double qx = dx / pr.ax, qy = dy / pr.ay;
-            const double rho = sqrt(qx * qx + qy * qy);
-            double s, ds;
-            sig_vd<SIGS>(pr.sk0, pr.k0 * (fv[pr.f0 + 2] - rho), s, ds);
-            const double g = ad * pr.k0 * ds;  // a * dF / d(r - rho)
-            const double inv = rho > 0.0 ? 1.0 / rho : 0.0;
-            emit(P, pr.f0, (float)(g * qx * inv / pr.ax));       // -drho/dx0 = dx / (ax^2 rho)
-            emit(P, pr.f0 + 1, (float)(g * qy * inv / pr.ay));
-            emit(P, pr.f0 + 2, (float)g);
-            break;
-        }
-        case SG_PRIM_POLY: {
-            if constexpr ((TYPES & T_POLY) == 0) break;
-            const int N = pr.nvert;
-            const double* xs = fv + pr.f0;
-            const double* ys = xs + N;
-            double pnz = 1.0;
-            int nzero = 0, zidx = -1;
-            for (int i = 0; i < N; ++i) {
-                const int j = (i + 1 == N) ? 0 : i + 1;
-                const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
-                const double L = sqrt(ex * ex + ey * ey);
-                const double sv = sig_v<SIGS>(pr.sk0, pr.k0 * (ex * (vc - ys[i]) - ey * (uc - xs[i])) / L);
-                if (sv == 0.0) { ++nzero; zidx = i; } else { pnz *= sv; }
-            }
-            for (int i = 0; i < N; ++i) {
-                const int j = (i + 1 == N) ? 0 : i + 1;
-                const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
-                const double L = sqrt(ex * ex + ey * ey);
-                const double wx = uc - xs[i], wy = vc - ys[i];
-                const double d = (ex * wy - ey * wx) / L;
-                double s, ds;
-                sig_vd<SIGS>(pr.sk0, pr.k0 * d, s, ds);
-                double other;
-                if (nzero == 0) other = pnz / s;
-                else if (nzero == 1 && zidx == i) other = pnz;
-                else other = 0.0;
-                const double g = ad * pr.k0 * ds * other;   // a * dF / d d_i
-                const double iL = 1.0 / L, dL2 = d * iL * iL;
-                emit(P, pr.f0 + i, (float)(g * ((ey - wy) * iL + dL2 * ex)));
-                emit(P, pr.f0 + N + i, (float)(g * ((wx - ex) * iL + dL2 * ey)));
-                emit(P, pr.f0 + j, (float)(g * (wy * iL - dL2 * ex)));
-                emit(P, pr.f0 + N + j, (float)(g * (-wx * iL - dL2 * ey)));
-            }
-            break;
-        }
-        default: {  // GCART
-            if constexpr ((TYPES & T_GCART) == 0) break;
-            const int M = pr.nvert;
+    const int N = pr.nvert;
+    const double* xs = fv + pr.f0;
+    const double* ys = xs + N;
+    double pnz = 1.0;
+    int nzero = 0, zidx = -1;
+    for (int i = 0; i < N; ++i) {
+        const int j = (i + 1 == N) ? 0 : i + 1;
+        const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
+        const double L = sqrt(ex * ex + ey * ey);
+        const double sv = sig_v<SIGS>(pr.sk0, pr.k0 * (ex * (vc - ys[i]) - ey * (uc - xs[i])) / L);
+        if (sv == 0.0) { ++nzero; zidx = i; } else { pnz *= sv; }
+    }
+    for (int i = 0; i < N; ++i) {
+        const int j = (i + 1 == N) ? 0 : i + 1;
+        const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
+        const double L = sqrt(ex * ex + ey * ey);
+        const double wx = uc - xs[i], wy = vc - ys[i];
+        const double d = (ex * wy - ey * wx) / L;
+        double s, ds;
+        sig_vd<SIGS>(pr.sk0, pr.k0 * d, s, ds);
+        double other;
+        if (nzero == 0) other = pnz / s;
+        else if (nzero == 1 && zidx == i) other = pnz;
+        else other = 0.0;
+        const double g = ad * pr.k0 * ds * other;   // a * dF / d d_i
+        const double iL = 1.0 / L, dL2 = d * iL * iL;
+        emit(P, pr.f0 + i, (float)(g * ((ey - wy) * iL + dL2 * ex)));
+        emit(P, pr.f0 + N + i, (float)(g * ((wx - ex) * iL + dL2 * ey)));
+        emit(P, pr.f0 + j, (float)(g * (wy * iL - dL2 * ex)));
+        emit(P, pr.f0 + N + j, (float)(g * (-wx * iL - dL2 * ey)));
+    }
+}
+
+// Partials of a two-sided piecewise-linear boundary, times the column sums,
+// over the kBlock samples of the tile handled by this wavefront.  Each sample
+// touches the y+ and y- of its segment's two vertices; the contributions are
+// bucketed per vertex in this wavefront's LDS slice (ds_add_f32) and flushed
+// with one atomic per touched vertex field.  Tiles that span more than
+// kSegBucket vertices fall back to one reduction per distinct segment.
+constexpr int kSegBucket = 256;
+
+template <int SIGS>
+__device__ void gcart_partials(const KParams& P, const DevPrim& pr, const float* sAc, int u0, int v0, int comp,
+                               const Tile& T, float* sg) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int TU = P.tu;
+    const double* fv = P.fval;
+    const int M = pr.nvert;
+    const double* xv = P.consts + pr.c0;
+    const double* yp = fv + pr.f0 + 2;
+    const double* ym = yp + M;
+    int jlo, jhi;
+    double tdum;
+    gcart_segment(xv, M, T.ulo, jlo, tdum);
+    gcart_segment(xv, M, T.uhi, jhi, tdum);
+    const int nvx = jhi - jlo + 2;               // vertices jlo .. jhi + 1
+    const bool bucket = nvx <= kSegBucket;
+    if (bucket) {
+        for (int i = lane; i < 2 * nvx; i += 64) sg[i] = 0.0f;
+        __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0): the zeros are in LDS
+        __builtin_amdgcn_wave_barrier();
+    }
+    double sxs = 0.0, sxe = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        const int t = q * 64 + lane;
+        const float a = sAc[t];
+        if (__ballot(a != 0.0f) == 0) continue;
+        const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
+        const double uc = P.uc[comp][uq], uw = P.uw[comp][uq], vc = P.vc[comp][vq], vw = P.vw[comp][vq];
+        const double ad = (double)a;
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
+        int j = 0;
+        if (a != 0.0f) {
             double rx, drx0, drx1;
             rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1], rx, drx0, drx1);
-            int j;
-            double t;
-            gcart_segment(P.consts + pr.c0, M, uc, j, t);
-            const double* yp = fv + pr.f0 + 2;
-            const double* ym = yp + M;
-            const double fp = (1.0 - t) * yp[j] + t * yp[j + 1];
-            const double fm = (1.0 - t) * ym[j] + t * ym[j + 1];
+            double t01;
+            gcart_segment(xv, M, uc, j, t01);
+            const double fp = (1.0 - t01) * yp[j] + t01 * yp[j + 1];
+            const double fm = (1.0 - t01) * ym[j] + t01 * ym[j + 1];
             const double ky = kval(pr.sm1, pr.k1, vw);
             double sp, dsp, sm, dsm;
             sig_vd<SIGS>(pr.sk1, ky * (fp - vc), sp, dsp);
             sig_vd<SIGS>(pr.sk1, ky * (vc - fm), sm, dsm);
             const double fy = sp * sm;
-            emit(P, pr.f0, (float)(ad * drx0 * fy));
-            emit(P, pr.f0 + 1, (float)(ad * drx1 * fy));
+            sxs += ad * drx0 * fy;
+            sxe += ad * drx1 * fy;
             const double gp = ad * rx * ky * dsp * sm;    // a * dF / d f+
             const double gm = -ad * rx * sp * ky * dsm;   // a * dF / d f-
-            float c0 = (float)(gp * (1.0 - t)), c1 = (float)(gp * t);
-            float c2 = (float)(gm * (1.0 - t)), c3 = (float)(gm * t);
-            // lanes sit on different segments: reduce once per distinct segment
+            c0 = (float)(gp * (1.0 - t01));
+            c1 = (float)(gp * t01);
+            c2 = (float)(gm * (1.0 - t01));
+            c3 = (float)(gm * t01);
+        }
+        if (bucket) {
+            if (c0 != 0.0f || c1 != 0.0f || c2 != 0.0f || c3 != 0.0f) {
+                const int k = j - jlo;
+                atomicAdd(sg + k, c0);
+                atomicAdd(sg + k + 1, c1);
+                atomicAdd(sg + nvx + k, c2);
+                atomicAdd(sg + nvx + k + 1, c3);
+            }
+        } else {
             uint64_t pend = __ballot(c0 != 0.0f || c1 != 0.0f || c2 != 0.0f || c3 != 0.0f);
             while (pend) {
                 const int src = __ffsll((unsigned long long)pend) - 1;
@@ -398,7 +446,7 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
                 const bool mine = (j == j0);
                 const float s0 = wave_sum(mine ? c0 : 0.0f), s1 = wave_sum(mine ? c1 : 0.0f);
                 const float s2 = wave_sum(mine ? c2 : 0.0f), s3 = wave_sum(mine ? c3 : 0.0f);
-                if ((threadIdx.x & 63) == 0) {
+                if (lane == 0) {
                     add_field(P, pr.f0 + 2 + j0, s0);
                     add_field(P, pr.f0 + 3 + j0, s1);
                     add_field(P, pr.f0 + 2 + M + j0, s2);
@@ -406,19 +454,127 @@ __device__ void emit_partials(const KParams& P, const DevPrim& pr, int pi, float
                 }
                 pend &= ~__ballot(mine);
             }
-            break;
+        }
+    }
+    emit(P, pr.f0, (float)sxs);
+    emit(P, pr.f0 + 1, (float)sxe);
+    if (bucket) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < 2 * nvx; i += 64) {
+            const float v = sg[i];
+            if (v != 0.0f) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
+        }
+    }
+}
+
+// One candidate primitive, handled by one wavefront for all kBlock samples of
+// the block's tile (kBlock / 64 samples per lane): in-plane partials times the
+// class column sums sAc[sample], summed over the lane's samples, reduced over
+// the wavefront, and added with one atomic per parameter field.
+template <int TYPES, int SIGS>
+__device__ void block_partials(const KParams& P, const DevPrim& pr, const float* sAc, int u0, int v0, int comp,
+                               const Tile& T, float* sg) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int TU = P.tu;
+    const double* fv = P.fval;
+    const int type = (TYPES == T_BOX) ? SG_PRIM_BOX : pr.type;
+    if constexpr ((TYPES & T_BOX) != 0) {
+        if (type == SG_PRIM_BOX) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < Q; ++q) {
+                const int t = q * 64 + lane;
+                const float a = sAc[t];
+                if (a != 0.0f) {
+                    const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
+                    const double ad = (double)a;
+                    double ru = 1.0, du0 = 0.0, du1 = 0.0, rv = 1.0, dv0 = 0.0, dv1 = 0.0;
+                    if (pr.ubnd)
+                        rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, P.uw[comp][uq]), P.uc[comp][uq], fv[pr.fu0],
+                                      fv[pr.fu1], ru, du0, du1);
+                    if (pr.vbnd)
+                        rect_vd<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, P.vw[comp][vq]), P.vc[comp][vq], fv[pr.fv0],
+                                      fv[pr.fv1], rv, dv0, dv1);
+                    s0 += ad * du0 * rv;
+                    s1 += ad * du1 * rv;
+                    s2 += ad * ru * dv0;
+                    s3 += ad * ru * dv1;
+                }
+            }
+            if (pr.ubnd) {
+                emit(P, pr.fu0, (float)s0);
+                emit(P, pr.fu1, (float)s1);
+            }
+            if (pr.vbnd) {
+                emit(P, pr.fv0, (float)s2);
+                emit(P, pr.fv1, (float)s3);
+            }
+            return;
+        }
+    }
+    if constexpr ((TYPES & T_ELL) != 0) {
+        if (type == SG_PRIM_ELLIPSE) {
+            const double x0 = fv[pr.f0], y0 = fv[pr.f0 + 1], r = fv[pr.f0 + 2];
+            const double rhi = r + pr.reach0, rlo = r - pr.reach0;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < Q; ++q) {
+                const int t = q * 64 + lane;
+                const float a = sAc[t];
+                if (a != 0.0f) {
+                    const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
+                    const double qx = (P.uc[comp][uq] - x0) * pr.iax, qy = (P.vc[comp][vq] - y0) * pr.iay;
+                    const double rho2 = qx * qx + qy * qy;
+                    if (rhi > 0.0 && rho2 < rhi * rhi && !(rlo > 0.0 && rho2 <= rlo * rlo)) {
+                        // derivatives only: FP32 after the FP64 differences
+                        const float fqx = (float)qx, fqy = (float)qy;
+                        const float rho = sqrtf(fqx * fqx + fqy * fqy);
+                        const float ds = sig_d32(pr.sk0, (float)pr.k0 * ((float)r - rho));
+                        const float g = a * (float)pr.k0 * ds;     // a * dF / d(r - rho)
+                        const float inv = rho > 0.0f ? 1.0f / rho : 0.0f;
+                        s0 += (double)(g * fqx * inv * (float)pr.iax);   // -drho/dx0 = dx / (ax^2 rho)
+                        s1 += (double)(g * fqy * inv * (float)pr.iay);
+                        s2 += (double)g;
+                    }
+                }
+            }
+            emit(P, pr.f0, (float)s0);
+            emit(P, pr.f0 + 1, (float)s1);
+            emit(P, pr.f0 + 2, (float)s2);
+            return;
+        }
+    }
+    if constexpr ((TYPES & T_POLY) != 0) {
+        if (type == SG_PRIM_POLY) {
+#pragma unroll 1
+            for (int q = 0; q < Q; ++q) {
+                const int t = q * 64 + lane;
+                const float a = sAc[t];
+                if (__ballot(a != 0.0f) == 0) continue;
+                const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
+                poly_partials<SIGS>(P, pr, (double)a, P.uc[comp][uq], P.vc[comp][vq]);
+            }
+            return;
+        }
+    }
+    if constexpr ((TYPES & T_GCART) != 0) {
+        if (type == SG_PRIM_GCART) {
+            gcart_partials<SIGS>(P, pr, sAc, u0, v0, comp, T, sg);
+            return;
         }
     }
 }
 
 // ------------------------------------------------------------------ column kernel
-template <int MODE, int NC, int TYPES, int SIGS>
-__global__ __launch_bounds__(256) void k_column(const KParams P) {
+template <int MODE, int TREE, int TYPES, int SIGS>
+__device__ __forceinline__ void column_body(const KParams& P, int b) {
+    constexpr int NC = tree_nc(TREE);
     __shared__ int s_cand[kCandCap];
     __shared__ int s_cnt[kBlock / 64];
     const int tid = threadIdx.x, wave = tid >> 6;
 
-    int b = blockIdx.x;
     const int seg = b % P.nseg;
     b /= P.nseg;
     const int tvi = b % P.tiles_v;
@@ -462,6 +618,42 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
         T.wvhi = vcs[max(0, min(wv1, P.nv - 1))];
     }
 
+    // Column steps [w0, w1).  Field loads are double-buffered in two register
+    // sets of U steps each: while one group is being composed the next one is
+    // in flight.  The first group goes out before the in-plane pass.
+    const int w0 = seg * P.seglen;
+    const int w1 = min(w0 + P.seglen, P.nw);
+    const int64_t b0 = (int64_t)uu + (int64_t)vv * P.sv;     // offset within a component plane
+    constexpr bool VJP = (MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
+    constexpr int U = (MODE == MODE_VJP_GEPS) ? 8 : 4;
+    const float2* __restrict__ efp = nullptr;
+    const float2* __restrict__ eap = nullptr;
+    const float* __restrict__ gep = nullptr;
+    if constexpr (MODE == MODE_VJP_FIELDS) {
+        efp = P.ef[comp] + b0;
+        eap = P.ea[comp] + b0;
+    } else if constexpr (MODE == MODE_VJP_GEPS) {
+        gep = P.geps + (int64_t)comp * P.plane + b0;
+    }
+    struct Set {
+        float2 e[U], a[U];
+        float g[U];
+    };
+    Set sa, sb;
+    auto load_set = [&](Set& st, int w) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t off = (int64_t)min(w + q, w1 - 1) * P.sw;
+            if constexpr (MODE == MODE_VJP_FIELDS) {
+                st.e[q] = efp[off];
+                st.a[q] = eap[off];
+            } else if constexpr (MODE == MODE_VJP_GEPS) {
+                st.g[q] = gep[off];
+            }
+        }
+    };
+    if constexpr (VJP) load_set(sa, w0);
+
     double F[NC];
     int nlist;
     bool complete;
@@ -474,75 +666,99 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
         inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.fval2, T, uc, uw, vc, vw, s_cand, s_cnt, F2, nl2, c2);
     }
 
-    const int w0 = seg * P.seglen;
-    const int w1 = min(w0 + P.seglen, P.nw);
-    const int64_t b0 = (int64_t)uu + (int64_t)vv * P.sv;     // offset within a component plane
-    const double* __restrict__ zt0 = P.ztab + (int64_t)comp * P.nclass * P.nw * 3;
+    // LDS copy of the extrusion tables of this column range, CH steps at a time
+    constexpr int NT = (MODE == MODE_FD) ? 2 : 1;
+    constexpr int CH = ((kZStage / NT / NC) / (2 * U)) * (2 * U);
+    __shared__ double sZ[NT * NC * CH];
+    __shared__ float2 sZd[VJP ? NC * CH : 1];
+    const int64_t zcomp = (int64_t)comp * P.nclass * P.nw * 3;
+    auto stage_z = [&](int wc) {
+        __syncthreads();
+        const int len = min(CH, w1 - wc);
+        const int tot = NT * P.nclass * len;
+        for (int i = tid; i < tot; i += kBlock) {
+            const int tb = i / (P.nclass * len), r = i - tb * (P.nclass * len);
+            const int c = r / len, j = r - c * len;
+            const double* z = (tb == 0 ? P.ztab : P.ztab2) + zcomp + 3 * ((int64_t)c * P.nw + wc + j);
+            sZ[(tb * NC + c) * CH + j] = z[0];
+            if constexpr (VJP) sZd[c * CH + j] = make_float2((float)z[1], (float)z[2]);
+        }
+        __syncthreads();
+    };
 
     float A[NC], Blo[NC], Bhi[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) A[c] = Blo[c] = Bhi[c] = 0.0f;
 
     if constexpr (MODE == MODE_EPS || MODE == MODE_FD) {
-        const double* __restrict__ zt2 = (MODE == MODE_FD) ? P.ztab2 + (int64_t)comp * P.nclass * P.nw * 3 : nullptr;
         float* __restrict__ outp = P.out + (int64_t)comp * P.plane + b0;
+        for (int wc = w0; wc < w1; wc += CH) {
+            stage_z(wc);
+            const int we = min(wc + CH, w1);
 #pragma unroll 2
-        for (int w = w0; w < w1; ++w) {
-            double Z[NC];
-            const double s = compose<NC>(P, F, zt0 + 3 * w, Z).s;
-            float out;
-            if constexpr (MODE == MODE_EPS) {
-                out = (float)(P.eps_bg + P.deps * s);
-            } else {
-                const double s2 = compose<NC>(P, F2, zt2 + 3 * w, Z).s;
-                out = (float)(P.deps * (s - s2));
+            for (int w = wc; w < we; ++w) {
+                double Z[NC];
+                const double s = compose<TREE>(P, F, sZ + (w - wc), CH, Z).s;
+                float out;
+                if constexpr (MODE == MODE_EPS) {
+                    out = (float)(P.eps_bg + P.deps * s);
+                } else {
+                    const double s2 = compose<TREE>(P, F2, sZ + NC * CH + (w - wc), CH, Z).s;
+                    out = (float)(P.deps * (s - s2));
+                }
+                if (act) outp[(int64_t)w * P.sw] = out;
             }
-            if (act) outp[(int64_t)w * P.sw] = out;
         }
         return;
     } else {
-        const float2* __restrict__ efp = P.ef[comp];
-        const float2* __restrict__ eap = P.ea[comp];
-        const float* __restrict__ gpl = P.geps + (int64_t)comp * P.plane;
-        // U column steps per iteration: every load of the group is issued before
-        // the first one is used, so each wavefront keeps 2U loads in flight.
-        constexpr int U = 4;
-        for (int w = w0; w < w1; w += U) {
+        int wc = w0;   // first step of the staged chunk
+        auto process = [&](const Set& st, int w) {
+            if ((w - w0) % CH == 0) {
+                wc = w;
+                stage_z(w);
+            }
             float gs[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                const int wq = min(w + q, w1 - 1);
-                const int64_t i = b0 + (int64_t)wq * P.sw;
-                if constexpr (MODE == MODE_VJP_FIELDS) {
-                    const float2 e = efp[i], a = eap[i];
-                    gs[q] = P.two_omega * (e.x * a.y + e.y * a.x);   // 2 omega Im(E Eadj)
-                } else {
-                    gs[q] = gpl[i];
-                }
+                if constexpr (MODE == MODE_VJP_FIELDS)
+                    gs[q] = P.two_omega * (st.e[q].x * st.a[q].y + st.e[q].y * st.a[q].x);   // 2 omega Im(E Eadj)
+                else
+                    gs[q] = st.g[q];
                 if (!act || w + q >= w1) gs[q] = 0.0f;
             }
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 if (w + q < w1) {
+                    const int j = w + q - wc;
                     double Z[NC];
-                    const Comp o = compose<NC>(P, F, zt0 + 3 * (w + q), Z);
+                    const Comp o = compose<TREE>(P, F, sZ + j, CH, Z);
                     const float gd = gs[q] * (float)P.deps;
                     const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
                     const float cg2 = gd * (float)o.r2, cg3 = gd * (float)o.r3;
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         if (c < P.nclass) {
-                            const int g = P.cls_group[c];
+                            constexpr int fixed = tree_group(TREE, 0) >= 0;
+                            const int g = fixed ? tree_group(TREE, c) : P.cls_group[c];
                             const float cc = (g == 0) ? cg0 : (g == 1) ? cg1 : (g == 2) ? cg2 : cg3;
                             A[c] += cc * (float)Z[c];
                             if (P.cls_wparam[c]) {
-                                const double* z = zt0 + 3 * ((int64_t)c * P.nw + w + q);
-                                Blo[c] += cc * (float)z[1];
-                                Bhi[c] += cc * (float)z[2];
+                                const float2 zd = sZd[c * CH + j];
+                                Blo[c] += cc * zd.x;
+                                Bhi[c] += cc * zd.y;
                             }
                         }
                     }
                 }
+            }
+        };
+        const int ngrp = (w1 - w0 + U - 1) / U;
+        for (int gi = 0; gi < ngrp; gi += 2) {
+            if (gi + 1 < ngrp) load_set(sb, w0 + (gi + 1) * U);
+            process(sa, w0 + gi * U);
+            if (gi + 1 < ngrp) {
+                if (gi + 2 < ngrp) load_set(sa, w0 + (gi + 2) * U);
+                process(sb, w0 + (gi + 1) * U);
             }
         }
     }
@@ -557,11 +773,14 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
             emit(P, cl.fhi, fs * Bhi[c]);
         }
     }
-    // ---- in-plane partials of every candidate
-    if (!act) {
+    // ---- in-plane partials: column sums to LDS, candidates split over the
+    // block's wavefronts, one atomic per (block, parameter field)
+    __shared__ float sA[NC * kBlock];
+    __shared__ float sG[(TYPES & T_GCART) ? (kBlock / 64) * 2 * kSegBucket : 1];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) A[c] = 0.0f;
-    }
+    for (int c = 0; c < NC; ++c) sA[c * kBlock + tid] = act ? A[c] : 0.0f;
+    __syncthreads();
+    const int u0 = tui * TU, v0 = tvi * P.tv;
     int next = 0;
     bool first = true;
     while (first || next < P.nprim) {
@@ -574,16 +793,31 @@ __global__ __launch_bounds__(256) void k_column(const KParams P) {
             n = build_list(P.bbox, P.nprim, next, T.ulo, T.uhi, T.vlo, T.vhi, s_cand, s_cnt, &next);
         }
         first = false;
-        if (!T.wave_live) continue;
-        for (int j = 0; j < n; ++j) {
+        for (int j = wave; j < n; j += kBlock / 64) {
             const int pi = uniform_int(s_cand[j]);
-            if (!wave_meets(T, P.bbox[pi])) continue;
             const DevPrim pr = P.prims[pi];
-            const float a = class_pick<NC>(A, pr.cls);
-            if (__ballot(a != 0.0f) == 0) continue;
-            emit_partials<TYPES, SIGS>(P, pr, pi, a, uc, uw, vc, vw);
+            block_partials<TYPES, SIGS>(P, pr, sA + pr.cls * kBlock, u0, v0, comp, T, sG + wave * 2 * kSegBucket);
         }
     }
+}
+
+template <int MODE, int TREE, int TYPES, int SIGS>
+__global__ __launch_bounds__(256) void k_column(const KParams P) {
+    column_body<MODE, TREE, TYPES, SIGS>(P, blockIdx.x);
+}
+
+// Several requests in one launch: request r owns blocks [first[r], first[r+1])
+// and its own parameter block plist[r] (same kernel specialization).
+template <int MODE, int TREE, int TYPES, int SIGS>
+__global__ __launch_bounds__(256) void k_column_batch(const KParams* __restrict__ plist,
+                                                      const int* __restrict__ first, int nreq) {
+    int lo = 0, hi = nreq;                   // first[lo] <= blockIdx.x < first[hi]
+    const int b = blockIdx.x;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid;
+    }
+    column_body<MODE, TREE, TYPES, SIGS>(plist[lo], b - first[lo]);
 }
 
 // ------------------------------------------------------------------ FD helpers
@@ -625,6 +859,39 @@ __global__ __launch_bounds__(256) void k_dot(const float* __restrict__ a, const 
     }
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32
+// multiplies, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Element i of E and Eadj: Philox of counter (i_lo, i_hi, 0, 0) under key
+// (seed_lo, seed_hi); u_k = (x_k + 1/2) 2^-32; two Box-Muller pairs give
+// (Re E, Im E) from (u0, u1) and (Re Eadj, Im Eadj) from (u2, u3).
+__global__ __launch_bounds__(256) void k_fieldgen(float2* __restrict__ e, float2* __restrict__ a, int64_t n,
+                                                  uint32_t k0, uint32_t k1) {
+    const float scale = 2.3283064365386963e-10f;   // 2^-32
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u), k0, k1);
+        const float u0 = ((float)x.x + 0.5f) * scale, u1 = ((float)x.y + 0.5f) * scale;
+        const float u2 = ((float)x.z + 0.5f) * scale, u3 = ((float)x.w + 0.5f) * scale;
+        const float r0 = sqrtf(-2.0f * logf(u0)), r1 = sqrtf(-2.0f * logf(u2));
+        float s0, c0, s1, c1;
+        sincosf(6.283185307179586f * u1, &s0, &c0);
+        sincosf(6.283185307179586f * u3, &s1, &c1);
+        e[i] = make_float2(r0 * c0, r0 * s0);
+        a[i] = make_float2(r1 * c1, r1 * s1);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -648,34 +915,79 @@ hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st) {
 }
 
 template <int MODE, int TYPES, int SIGS>
-static hipError_t launch_variant(int ncls, const KParams& kp, hipStream_t st) {
+static hipError_t launch_variant(int tree, const KParams& kp, hipStream_t st) {
     const int64_t blocks = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
     const dim3 grid((unsigned)blocks), blk(256);
-    switch (ncls) {
-        case 1: hipLaunchKernelGGL((k_column<MODE, 1, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        case 2: hipLaunchKernelGGL((k_column<MODE, 2, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        case 4: hipLaunchKernelGGL((k_column<MODE, 4, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        default: hipLaunchKernelGGL((k_column<MODE, 8, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+    switch (tree) {
+        case TR_U1: hipLaunchKernelGGL((k_column<MODE, TR_U1, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case TR_U2: hipLaunchKernelGGL((k_column<MODE, TR_U2, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case TR_D11: hipLaunchKernelGGL((k_column<MODE, TR_D11, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case TR_D12: hipLaunchKernelGGL((k_column<MODE, TR_D12, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        default:
+            // generic op trees only come with the catch-all feature set
+            if constexpr (TYPES == T_ALL && SIGS == S_ALL) {
+                if (tree == TR_GEN4) hipLaunchKernelGGL((k_column<MODE, TR_GEN4, TYPES, SIGS>), grid, blk, 0, st, kp);
+                else hipLaunchKernelGGL((k_column<MODE, TR_GEN8, TYPES, SIGS>), grid, blk, 0, st, kp);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            break;
     }
     return hipGetLastError();
 }
 
-template <int MODE>
-static hipError_t launch_mode(int ncls, int variant, const KParams& kp, hipStream_t st) {
+template <int MODE, int TYPES, int SIGS>
+static hipError_t launch_batch_variant(int tree, const KParams* plist, const int* first, int nreq, int64_t blocks,
+                                       hipStream_t st) {
+    const dim3 grid((unsigned)blocks), blk(256);
+    switch (tree) {
+        case TR_U1: hipLaunchKernelGGL((k_column_batch<MODE, TR_U1, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq); break;
+        case TR_U2: hipLaunchKernelGGL((k_column_batch<MODE, TR_U2, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq); break;
+        case TR_D11: hipLaunchKernelGGL((k_column_batch<MODE, TR_D11, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq); break;
+        case TR_D12: hipLaunchKernelGGL((k_column_batch<MODE, TR_D12, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq); break;
+        default:
+            if constexpr (TYPES == T_ALL && SIGS == S_ALL) {
+                if (tree == TR_GEN4)
+                    hipLaunchKernelGGL((k_column_batch<MODE, TR_GEN4, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq);
+                else
+                    hipLaunchKernelGGL((k_column_batch<MODE, TR_GEN8, TYPES, SIGS>), grid, blk, 0, st, plist, first, nreq);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_column_batch(int tree, int variant, const KParams* plist, const int* first, int nreq,
+                               int64_t blocks, hipStream_t st) {
     switch (variant) {
-        case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(ncls, kp, st);
-        case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(ncls, kp, st);
-        case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(ncls, kp, st);
-        default: return launch_variant<MODE, T_ALL, S_ALL>(ncls, kp, st);
+        case VAR_BOX_LIN: return launch_batch_variant<MODE_VJP_FIELDS, T_BOX, S_LIN>(tree, plist, first, nreq, blocks, st);
+        case VAR_GCART_LIN:
+            return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_GCART, S_LIN>(tree, plist, first, nreq, blocks, st);
+        case VAR_ELL_SIGMOID:
+            return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, plist, first, nreq, blocks,
+                                                                                          st);
+        default: return launch_batch_variant<MODE_VJP_FIELDS, T_ALL, S_ALL>(tree, plist, first, nreq, blocks, st);
     }
 }
 
-hipError_t launch_column(int mode, int ncls, int variant, const KParams& kp, hipStream_t st) {
+template <int MODE>
+static hipError_t launch_mode(int tree, int variant, const KParams& kp, hipStream_t st) {
+    switch (variant) {
+        case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(tree, kp, st);
+        case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(tree, kp, st);
+        case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, kp, st);
+        default: return launch_variant<MODE, T_ALL, S_ALL>(tree, kp, st);
+    }
+}
+
+hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st) {
     switch (mode) {
-        case MODE_EPS: return launch_mode<MODE_EPS>(ncls, variant, kp, st);
-        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(ncls, variant, kp, st);
-        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(ncls, variant, kp, st);
-        default: return launch_mode<MODE_FD>(ncls, variant, kp, st);
+        case MODE_EPS: return launch_mode<MODE_EPS>(tree, variant, kp, st);
+        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(tree, variant, kp, st);
+        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(tree, variant, kp, st);
+        default: return launch_mode<MODE_FD>(tree, variant, kp, st);
     }
 }
 
@@ -690,6 +1002,13 @@ hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int n
 
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_dot, dim3(2048), dim3(256), 0, st, a, b, n, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fieldgen(float2* e, float2* a, int64_t n, uint64_t seed, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>(8192, (n + 255) / 256);
+    hipLaunchKernelGGL(k_fieldgen, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, e, a, n,
+                       (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();
 }
 

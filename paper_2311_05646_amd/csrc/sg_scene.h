@@ -1,0 +1,82 @@
+// Host-side internals shared by the C-ABI entry points (sg_api.hip) and the
+// serving runtime (sg_serve.hip): error state, context and compiled scene.
+#pragma once
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sg_internal.h"
+
+namespace sg {
+
+sg_status fail(sg_status code, const char* fmt, ...);
+
+}  // namespace sg
+
+#define HIP_OK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return sg::fail(SG_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+struct sg_ctx {
+    int device;
+};
+
+struct sg_scene {
+    sg_ctx* ctx = nullptr;
+    int dim = 0, ncomp = 0, comp_axis[3] = {0, 0, 0};
+    int64_t n[3] = {0, 0, 0};
+    int64_t n_params = 0;
+    int64_t nfield = 0;
+    double eps_bg = 0, eps_fg = 0;
+    int col = 2;                      // column axis: 1 (y) or 2 (z)
+    int axis_v = 1;
+    int nu = 0, nv = 0, nw = 0;
+    int64_t sv = 0, sw = 0, plane = 0;
+    int nprim = 0, nclass = 0, ncls_pad = 1;
+    int variant = sg::VAR_ALL;
+    int tree = sg::TR_GEN8;
+    int ngroup = 0, root_op = sg::ROOT_NONE;
+    int group_op[sg::kMaxGroups] = {0, 0, 0, 0};
+    double group_nm1[sg::kMaxGroups] = {0, 0, 0, 0};
+    double root_nm1 = 0;
+    std::vector<sg::DevClass> classes;
+    std::vector<sg_field> fields;
+    int block_x = 0, nseg = 0;        // 0: automatic
+    // device tables
+    double* d_lat = nullptr;          // per component: uc uw vc vw wc ww
+    int64_t lat_off[sg::kMaxComp][6] = {};
+    sg_field* d_fref = nullptr;
+    sg::DevPrim* d_prims = nullptr;
+    sg::DevClass* d_cls = nullptr;
+    double* d_consts = nullptr;
+    double* d_p = nullptr;
+    double* d_fval[2] = {nullptr, nullptr};
+    double4* d_bbox[2] = {nullptr, nullptr};
+    double* d_ztab[2] = {nullptr, nullptr};
+    double* d_grad = nullptr;
+    float* d_work[2] = {nullptr, nullptr};
+    double* h_p = nullptr;            // pinned staging
+    double* h_grad = nullptr;
+    hipEvent_t p_evt = nullptr;
+    bool p_evt_pending = false;
+    // tracing: events around the main column-kernel launches
+    bool timing = false;
+    struct Rec {
+        int mode;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> evpool;
+    std::mutex mu;
+};
+
+namespace sg {
+// launch parameters of a scene's kernels, pointing at its own staging buffers
+StageParams stage_params(sg_scene* s, const double* dp);
+KParams column_params(sg_scene* s);
+// bytes of device staging one gradient evaluation of the scene needs
+int64_t staging_bytes(const sg_scene* s);
+}  // namespace sg

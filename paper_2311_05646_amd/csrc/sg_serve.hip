@@ -1,0 +1,549 @@
+// Serving runtime: continuous batching of gradient requests (see the serving
+// section of include/shapegrad.h for the contract).
+//
+// One scheduler thread owns all device work.  Each turn it
+//   1. admits queued requests in arrival order while a request slot is free and
+//      the request's device bytes fit the remaining HBM budget (a request that
+//      does not fit waits at the head of the queue);
+//   2. polls the events of the batches in flight and completes their requests;
+//   3. when a stream is free, forms a batch of up to max_batch admitted
+//      requests and enqueues it on that stream: p upload, Philox fields, stage
+//      and one batched column-kernel launch per kernel specialization, then the
+//      gradient copies and an event.
+// Clients never touch the device: serve_submit queues, serve_poll waits on a
+// condition variable for the scheduler to publish the result.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sg_scene.h"
+
+using namespace sg;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+enum ReqState { PENDING, ADMITTED, LAUNCHED, DONE, CANCELLED, FAILED };
+
+struct Buf {                 // device buffers of one admitted request
+    float2* e = nullptr;
+    float2* a = nullptr;
+    double* p = nullptr;
+    double* fval = nullptr;
+    double4* bbox = nullptr;
+    double* ztab = nullptr;
+    double* grad = nullptr;
+    double* h_p = nullptr;   // pinned
+    double* h_grad = nullptr;
+};
+
+struct Session {
+    uint32_t id = 0;
+    sg_scene* scene = nullptr;      // null for fake sessions
+    int64_t n_params = 0;
+    int64_t req_bytes = 0;
+    std::vector<Buf*> free_bufs;
+    std::vector<Buf*> all_bufs;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    Session* s = nullptr;
+    std::vector<double> p, grad;
+    uint64_t seed = 0;
+    double omega = 0;
+    int state = PENDING;
+    bool cancel = false;
+    sg_status status = SG_OK;
+    Buf* buf = nullptr;
+    sg_req_stats st{};
+};
+
+struct Lane {                      // one stream and the batch in flight on it
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Req*> batch;
+    bool busy = false;
+    bool failed = false;
+    int64_t fake_ready_ns = 0;
+    KParams* d_plist = nullptr;     // device copies of the batch's launch parameters
+    int* d_first = nullptr;
+    KParams* h_plist = nullptr;     // pinned
+    int* h_first = nullptr;
+};
+
+}  // namespace
+
+struct sg_server {
+    sg_ctx* ctx = nullptr;
+    sg_server_opts opts{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread th;
+    bool stop = false;
+    std::vector<std::unique_ptr<Session>> sessions;
+    std::deque<Req*> pending;
+    std::deque<Req*> ready;
+    std::unordered_map<uint64_t, Req*> reqs;
+    uint64_t next_ticket = 1;
+    int64_t bytes_used = 0;
+    int slots_used = 0;
+    std::vector<Lane> lanes;
+    int next_lane = 0;
+    int64_t launches = 0, completed = 0, max_batch_seen = 0;
+    int64_t fault_launch = -1;      // SG_FAULT_INJECT=launch:N
+};
+
+namespace {
+
+void free_buf(Buf* b) {
+    hipFree(b->e);
+    hipFree(b->a);
+    hipFree(b->p);
+    hipFree(b->fval);
+    hipFree(b->bbox);
+    hipFree(b->ztab);
+    hipFree(b->grad);
+    if (b->h_p) hipHostFree(b->h_p);
+    if (b->h_grad) hipHostFree(b->h_grad);
+    delete b;
+}
+
+bool alloc_buf(sg_scene* sc, Buf* b) {
+    const int64_t nfield = std::max<int64_t>(1, sc->nfield), n = std::max<int64_t>(1, sc->n_params);
+    const int64_t cm = (int64_t)sc->ncomp * sc->plane;
+    hipError_t e = hipMalloc((void**)&b->e, cm * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->a, cm * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->p, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->fval, nfield * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->bbox, std::max(1, sc->nprim) * sizeof(double4));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->ztab, (size_t)sc->ncomp * sc->nclass * sc->nw * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->grad, n * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_p, n * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_grad, n * sizeof(double));
+    return e == hipSuccess;
+}
+
+// fake results: grad_k = 2 p_k + (seed mod 1000)
+void fake_result(Req* r) {
+    r->grad.resize(r->s->n_params);
+    for (int64_t k = 0; k < r->s->n_params; ++k) r->grad[k] = 2.0 * r->p[k] + (double)(r->seed % 1000);
+}
+
+void release(sg_server* v, Req* r) {
+    if (r->buf) {
+        r->s->free_bufs.push_back(r->buf);
+        r->buf = nullptr;
+    }
+    v->bytes_used -= r->s->req_bytes;
+    v->slots_used -= 1;
+}
+
+// Admit queued requests in arrival order while slots and budget allow.
+void admit(sg_server* v) {
+    while (!v->pending.empty()) {
+        Req* r = v->pending.front();
+        if (v->slots_used >= v->opts.max_slots) return;
+        if (v->bytes_used + r->s->req_bytes > v->opts.hbm_budget_bytes) return;
+        if (!v->opts.fake_executor) {
+            if (r->s->free_bufs.empty()) {
+                Buf* b = new Buf;
+                if (!alloc_buf(r->s->scene, b)) {
+                    free_buf(b);
+                    return;        // device memory short: try again when something completes
+                }
+                r->s->all_bufs.push_back(b);
+                r->s->free_bufs.push_back(b);
+            }
+            r->buf = r->s->free_bufs.back();
+            r->s->free_bufs.pop_back();
+        }
+        v->pending.pop_front();
+        v->bytes_used += r->s->req_bytes;
+        v->slots_used += 1;
+        r->state = ADMITTED;
+        r->st.admit_ns = now_ns();
+        v->ready.push_back(r);
+    }
+}
+
+void finish_batch(sg_server* v, Lane& L, bool ok) {
+    const int64_t t = now_ns();
+    for (Req* r : L.batch) {
+        if (r->cancel) {
+            r->state = CANCELLED;
+            r->status = SG_E_CANCELLED;
+        } else if (!ok) {
+            r->state = FAILED;
+            r->status = SG_E_DEVICE;
+        } else {
+            if (v->opts.fake_executor) {
+                fake_result(r);
+            } else {
+                r->grad.assign(r->buf->h_grad, r->buf->h_grad + r->s->n_params);
+            }
+            r->state = DONE;
+            r->status = SG_OK;
+            v->completed++;
+        }
+        r->st.done_ns = t;
+        release(v, r);
+    }
+    L.batch.clear();
+    L.busy = false;
+    L.failed = false;
+}
+
+// Enqueue one batch on lane L (device work only; called with the lock held).
+bool launch_batch(sg_server* v, Lane& L) {
+    const int64_t t = now_ns();
+    const int nb = (int)L.batch.size();
+    for (Req* r : L.batch) {
+        r->state = LAUNCHED;
+        r->st.launch_ns = t;
+        r->st.batch_size = nb;
+    }
+    v->max_batch_seen = std::max<int64_t>(v->max_batch_seen, nb);
+    const bool inject = (v->launches == v->fault_launch);
+    v->launches++;
+    if (v->opts.fake_executor) {
+        L.fake_ready_ns = t + v->opts.fake_us * 1000;
+        L.failed = inject;
+        return true;
+    }
+    if (inject) {
+        L.failed = true;
+        return true;
+    }
+    hipStream_t st = L.stream;
+    // per request: p, fields, stage (resolved fields, support boxes, extrusion tables, zeroed gradient)
+    for (Req* r : L.batch) {
+        sg_scene* sc = r->s->scene;
+        Buf* b = r->buf;
+        std::memcpy(b->h_p, r->p.data(), r->s->n_params * sizeof(double));
+        if (r->s->n_params && hipMemcpyAsync(b->p, b->h_p, r->s->n_params * sizeof(double), hipMemcpyHostToDevice, st))
+            return false;
+        if (launch_fieldgen(b->e, b->a, (int64_t)sc->ncomp * sc->plane, r->seed, st) != hipSuccess) return false;
+        StageParams sp = stage_params(sc, b->p);
+        sp.fval[0] = b->fval;
+        sp.bbox[0] = b->bbox;
+        sp.ztab[0] = b->ztab;
+        sp.zero_ptr = b->grad;
+        sp.zero_n = sc->n_params;
+        if (launch_stage(sp, 1, st) != hipSuccess) return false;
+    }
+    // one batched launch per kernel specialization; a group of g requests uses
+    // h_plist[g0, g0 + g) and the prefix h_first[g0, g0 + g] (terminated by its total)
+    std::vector<bool> done(nb, false);
+    int slot = 0;
+    for (int i = 0; i < nb; ++i) {
+        if (done[i]) continue;
+        const int tree = L.batch[i]->s->scene->tree, var = L.batch[i]->s->scene->variant;
+        const int g0 = slot;
+        int ng = 0, blocks = 0;
+        for (int j = i; j < nb; ++j) {
+            sg_scene* sc = L.batch[j]->s->scene;
+            if (done[j] || sc->tree != tree || sc->variant != var) continue;
+            done[j] = true;
+            Buf* b = L.batch[j]->buf;
+            KParams kp = column_params(sc);
+            kp.fval = b->fval;
+            kp.bbox = b->bbox;
+            kp.ztab = b->ztab;
+            kp.grad = b->grad;
+            for (int c = 0; c < kMaxComp; ++c) {
+                const int cc = std::min(c, sc->ncomp - 1);
+                kp.ef[c] = b->e + (int64_t)cc * sc->plane;
+                kp.ea[c] = b->a + (int64_t)cc * sc->plane;
+            }
+            kp.two_omega = (float)(2.0 * L.batch[j]->omega);
+            L.h_plist[g0 + ng] = kp;
+            L.h_first[g0 + ng] = blocks;
+            blocks += kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
+            ++ng;
+        }
+        L.h_first[g0 + ng] = blocks;
+        if (hipMemcpyAsync(L.d_plist + g0, L.h_plist + g0, ng * sizeof(KParams), hipMemcpyHostToDevice, st)) return false;
+        if (hipMemcpyAsync(L.d_first + g0, L.h_first + g0, (ng + 1) * sizeof(int), hipMemcpyHostToDevice, st))
+            return false;
+        if (launch_column_batch(tree, var, L.d_plist + g0, L.d_first + g0, ng, blocks, st) != hipSuccess) return false;
+        slot = g0 + ng + 1;
+    }
+    for (Req* r : L.batch) {
+        if (r->s->n_params &&
+            hipMemcpyAsync(r->buf->h_grad, r->buf->grad, r->s->n_params * sizeof(double), hipMemcpyDeviceToHost, st))
+            return false;
+    }
+    return hipEventRecord(L.done, st) == hipSuccess;
+}
+
+void scheduler(sg_server* v) {
+    if (!v->opts.fake_executor) hipSetDevice(v->ctx->device);
+    std::unique_lock<std::mutex> lk(v->mu);
+    while (true) {
+        admit(v);
+        // completions
+        bool any_busy = false;
+        for (Lane& L : v->lanes) {
+            if (!L.busy) continue;
+            bool fin = false, ok = true;
+            if (v->opts.fake_executor) {
+                fin = now_ns() >= L.fake_ready_ns;
+                ok = !L.failed;
+            } else if (L.failed) {
+                // an injected failure: wait for whatever reached the stream, then fail the batch
+                fin = hipStreamQuery(L.stream) != hipErrorNotReady;
+                ok = false;
+            } else {
+                const hipError_t q = hipEventQuery(L.done);
+                fin = q != hipErrorNotReady;
+                ok = q == hipSuccess;
+            }
+            if (fin) {
+                finish_batch(v, L, ok);
+                v->cv_done.notify_all();
+            } else {
+                any_busy = true;
+            }
+        }
+        admit(v);
+        // launches
+        for (int k = 0; k < (int)v->lanes.size() && !v->ready.empty(); ++k) {
+            Lane& L = v->lanes[(v->next_lane + k) % v->lanes.size()];
+            if (L.busy) continue;
+            while (!v->ready.empty() && (int)L.batch.size() < v->opts.max_batch) {
+                Req* r = v->ready.front();
+                v->ready.pop_front();
+                L.batch.push_back(r);
+            }
+            L.busy = true;
+            if (!launch_batch(v, L)) L.failed = true;
+            any_busy = true;
+            v->next_lane = (v->next_lane + k + 1) % v->lanes.size();
+        }
+        if (v->stop && v->pending.empty() && v->ready.empty() && !any_busy) break;
+        if (any_busy) {
+            // batches in flight: poll their events at a fine grain
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        } else if (!v->stop) {
+            v->cv_work.wait_for(lk, std::chrono::milliseconds(50));
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* stream) {
+    if (!e_fwd || !e_adj || n < 0) return fail(SG_E_INVALID, "sg_fieldgen: bad arguments");
+    if (n == 0) return SG_OK;
+    HIP_OK(launch_fieldgen((float2*)e_fwd, (float2*)e_adj, n, seed, (hipStream_t)stream));
+    return SG_OK;
+}
+
+extern "C" sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* o, sg_server** out) {
+    if (!o || !out) return fail(SG_E_INVALID, "sg_server_create: NULL argument");
+    *out = nullptr;
+    if (!o->fake_executor && !ctx) return fail(SG_E_INVALID, "sg_server_create: NULL ctx");
+    if (o->hbm_budget_bytes <= 0 || o->max_slots < 1 || o->max_batch < 1 || o->n_streams < 1 || o->n_streams > 8 ||
+        o->fake_us < 0)
+        return fail(SG_E_INVALID, "sg_server_create: bad options");
+    auto* v = new sg_server;
+    v->ctx = ctx;
+    v->opts = *o;
+    if (const char* fi = std::getenv("SG_FAULT_INJECT")) {
+        if (std::strncmp(fi, "launch:", 7) == 0) v->fault_launch = std::atoll(fi + 7);
+    }
+    v->lanes.resize(o->n_streams);
+    if (!o->fake_executor) {
+        hipError_t e = hipSetDevice(ctx->device);
+        for (Lane& L : v->lanes) {
+            if (e == hipSuccess) e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+            const size_t np = 2 * (size_t)o->max_batch + 2;
+            if (e == hipSuccess) e = hipMalloc((void**)&L.d_plist, np * sizeof(KParams));
+            if (e == hipSuccess) e = hipMalloc((void**)&L.d_first, (np + 1) * sizeof(int));
+            if (e == hipSuccess) e = hipHostMalloc((void**)&L.h_plist, np * sizeof(KParams));
+            if (e == hipSuccess) e = hipHostMalloc((void**)&L.h_first, (np + 1) * sizeof(int));
+        }
+        if (e != hipSuccess) {
+            sg_server_destroy(v);
+            return fail(SG_E_DEVICE, "sg_server_create: %s", hipGetErrorString(e));
+        }
+    }
+    v->th = std::thread(scheduler, v);
+    *out = v;
+    return SG_OK;
+}
+
+extern "C" sg_status sg_server_destroy(sg_server* v) {
+    if (!v) return fail(SG_E_INVALID, "NULL server");
+    {
+        std::lock_guard<std::mutex> lk(v->mu);
+        v->stop = true;
+        for (Req* r : v->pending) {
+            r->state = CANCELLED;
+            r->status = SG_E_CANCELLED;
+        }
+        v->pending.clear();
+        for (Req* r : v->ready) {
+            r->state = CANCELLED;
+            r->status = SG_E_CANCELLED;
+            release(v, r);
+        }
+        v->ready.clear();
+    }
+    v->cv_work.notify_all();
+    if (v->th.joinable()) v->th.join();
+    v->cv_done.notify_all();
+    for (auto& kv : v->reqs) delete kv.second;
+    v->reqs.clear();
+    if (!v->opts.fake_executor) {
+        for (auto& s : v->sessions)
+            for (Buf* b : s->all_bufs) free_buf(b);
+        for (Lane& L : v->lanes) {
+            if (L.stream) hipStreamDestroy(L.stream);
+            if (L.done) hipEventDestroy(L.done);
+            hipFree(L.d_plist);
+            hipFree(L.d_first);
+            if (L.h_plist) hipHostFree(L.h_plist);
+            if (L.h_first) hipHostFree(L.h_first);
+        }
+    }
+    delete v;
+    return SG_OK;
+}
+
+static sg_status open_session(sg_server* v, sg_scene* sc, int64_t n_params, int64_t bytes, uint32_t* id) {
+    std::lock_guard<std::mutex> lk(v->mu);
+    auto s = std::make_unique<Session>();
+    s->id = (uint32_t)v->sessions.size();
+    s->scene = sc;
+    s->n_params = n_params;
+    s->req_bytes = bytes;
+    *id = s->id;
+    v->sessions.push_back(std::move(s));
+    return SG_OK;
+}
+
+extern "C" sg_status serve_open_session(sg_server* v, sg_scene* sc, uint32_t* id) {
+    if (!v || !sc || !id) return fail(SG_E_INVALID, "serve_open_session: NULL argument");
+    if (v->opts.fake_executor) return fail(SG_E_INVALID, "fake-executor servers take fake sessions");
+    if (sc->ctx->device != v->ctx->device) return fail(SG_E_INVALID, "scene on another device");
+    const int64_t bytes = 16 * (int64_t)sc->ncomp * sc->plane + staging_bytes(sc);
+    return open_session(v, sc, sc->n_params, bytes, id);
+}
+
+extern "C" sg_status serve_open_fake_session(sg_server* v, int64_t n_params, int64_t bytes, uint32_t* id) {
+    if (!v || !id) return fail(SG_E_INVALID, "serve_open_fake_session: NULL argument");
+    if (!v->opts.fake_executor) return fail(SG_E_INVALID, "only fake-executor servers take fake sessions");
+    if (n_params < 0 || bytes < 0) return fail(SG_E_INVALID, "bad sizes");
+    return open_session(v, nullptr, n_params, bytes, id);
+}
+
+extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, uint64_t seed, double omega,
+                                  uint64_t* ticket) {
+    if (!v || !ticket) return fail(SG_E_INVALID, "serve_submit: NULL argument");
+    Req* r;
+    {
+        std::lock_guard<std::mutex> lk(v->mu);
+        if (sid >= v->sessions.size()) return fail(SG_E_INVALID, "serve_submit: unknown session %u", sid);
+        Session* s = v->sessions[sid].get();
+        if (s->n_params > 0 && !p) return fail(SG_E_INVALID, "serve_submit: p is NULL");
+        for (int64_t k = 0; k < s->n_params; ++k)
+            if (!std::isfinite(p[k])) return fail(SG_E_INVALID, "serve_submit: p[%lld] not finite", (long long)k);
+        if (!std::isfinite(omega)) return fail(SG_E_INVALID, "serve_submit: omega not finite");
+        if (s->req_bytes > v->opts.hbm_budget_bytes)
+            return fail(SG_E_TOO_LARGE, "request needs %lld bytes, budget is %lld", (long long)s->req_bytes,
+                        (long long)v->opts.hbm_budget_bytes);
+        if (v->stop) return fail(SG_E_INVALID, "server is shutting down");
+        r = new Req;
+        r->ticket = v->next_ticket++;
+        r->s = s;
+        r->p.assign(p, p + s->n_params);
+        r->seed = seed;
+        r->omega = omega;
+        r->st.submit_ns = now_ns();
+        v->reqs[r->ticket] = r;
+        v->pending.push_back(r);
+        *ticket = r->ticket;
+    }
+    v->cv_work.notify_one();
+    return SG_OK;
+}
+
+extern "C" sg_status serve_poll(sg_server* v, uint64_t ticket, double* grad_out, int64_t timeout_us,
+                                sg_req_stats* stats) {
+    if (!v) return fail(SG_E_INVALID, "serve_poll: NULL server");
+    std::unique_lock<std::mutex> lk(v->mu);
+    auto it = v->reqs.find(ticket);
+    if (it == v->reqs.end()) return fail(SG_E_INVALID, "serve_poll: unknown ticket %llu", (unsigned long long)ticket);
+    Req* r = it->second;
+    auto final_state = [&] { return r->state == DONE || r->state == CANCELLED || r->state == FAILED; };
+    if (!final_state()) {
+        if (timeout_us < 0) v->cv_done.wait(lk, final_state);
+        else if (timeout_us > 0) v->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), final_state);
+    }
+    if (!final_state()) return SG_EAGAIN;
+    const sg_status st = r->status;
+    if (st == SG_OK && r->s->n_params > 0) {
+        if (!grad_out) return fail(SG_E_INVALID, "serve_poll: grad_out is NULL");
+        std::memcpy(grad_out, r->grad.data(), r->s->n_params * sizeof(double));
+    }
+    if (stats) *stats = r->st;
+    v->reqs.erase(it);
+    delete r;
+    if (st == SG_E_CANCELLED) return fail(SG_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+    if (st != SG_OK) return fail(st, "request %llu failed on the device", (unsigned long long)ticket);
+    return SG_OK;
+}
+
+extern "C" sg_status serve_cancel(sg_server* v, uint64_t ticket) {
+    if (!v) return fail(SG_E_INVALID, "serve_cancel: NULL server");
+    std::lock_guard<std::mutex> lk(v->mu);
+    auto it = v->reqs.find(ticket);
+    if (it == v->reqs.end()) return fail(SG_E_INVALID, "serve_cancel: unknown ticket");
+    Req* r = it->second;
+    if (r->state == PENDING) {
+        v->pending.erase(std::find(v->pending.begin(), v->pending.end(), r));
+        r->state = CANCELLED;
+        r->status = SG_E_CANCELLED;
+    } else if (r->state == ADMITTED) {
+        v->ready.erase(std::find(v->ready.begin(), v->ready.end(), r));
+        r->state = CANCELLED;
+        r->status = SG_E_CANCELLED;
+        release(v, r);
+    } else if (r->state == LAUNCHED) {
+        r->cancel = true;
+    }
+    v->cv_done.notify_all();
+    return SG_OK;
+}
+
+extern "C" sg_status serve_counters(sg_server* v, int64_t* completed, int64_t* batches, int64_t* max_batch_seen,
+                                    int64_t* bytes_in_use) {
+    if (!v) return fail(SG_E_INVALID, "NULL server");
+    std::lock_guard<std::mutex> lk(v->mu);
+    if (completed) *completed = v->completed;
+    if (batches) *batches = v->launches;
+    if (max_batch_seen) *max_batch_seen = v->max_batch_seen;
+    if (bytes_in_use) *bytes_in_use = v->bytes_used;
+    return SG_OK;
+}

@@ -1,0 +1,110 @@
+"""Parity at the full workload sizes (the launch configuration bench.py
+times): eps on randomly sampled samples of every component, and the fused
+gradient on sampled parameters, each computed by the oracle over every
+sample where that parameter's derivative can be non-zero; plus the GPU
+finite-difference Jacobian against the fused gradient at full size."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import primitives as prm
+from oracle import scene as S
+from oracle.lattice import component_samples
+from tests.gpu_util import api, rel, to_dev
+from paper_2311_05646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _setup(name):
+    if name not in _CACHE:
+        _CACHE.clear()
+        torch.cuda.empty_cache()
+        print(f"[fullsize] generating {name}", flush=True)
+        cfg = W.CONFIGS[name]()
+        sc = api().Scene(cfg["scene"])
+        E, A = cfg["E"].astype(np.complex64), cfg["A"].astype(np.complex64)
+        _CACHE[name] = (cfg, sc, E, A, to_dev(E), to_dev(A))
+    return _CACHE[name]
+
+
+def _param_region(desc, p, k, ci):
+    """Flat indices (component ci) of every sample where d eps / d p_k can be
+    non-zero: the support boxes of the primitives that reference p_k; for a
+    vertex of a piecewise-linear boundary, cut to the vertex's hat support in x
+    and to the boundary's reach in y."""
+    vals = S.resolve(desc, p)
+    X, Y, Z = desc["nodes"]
+    wmax = [float(np.diff(np.asarray(a)).max()) for a in (X, Y, Z)]
+    smp = component_samples(desc, desc["components"][ci])
+    nx, ny = len(X) - 1, len(Y) - 1
+    out = []
+    for i, pr in enumerate(desc["prims"]):
+        hits = [fi for fi, f in enumerate(pr["fields"]) if f[2] == k]
+        if not hits:
+            continue
+        lo, hi = prm.bbox(pr, vals[i], wmax)
+        lo, hi = list(lo), list(hi)
+        if pr["type"] == "gcart":
+            M = pr["nvert"]
+            xv = pr["consts"]
+            for fi in hits:
+                if 2 <= fi < 2 + 2 * M:
+                    j = (fi - 2) % M
+                    side = vals[i][2:2 + M] if fi < 2 + M else vals[i][2 + M:2 + 2 * M]
+                    lo[0] = max(lo[0], xv[max(j - 1, 0)] - (1e9 if j == 0 else 0.0))
+                    hi[0] = min(hi[0], xv[min(j + 1, M - 1)] + (1e9 if j == M - 1 else 0.0))
+                    reach = 0.5 * wmax[1]
+                    ys = side[max(j - 1, 0):min(j + 2, M)]
+                    lo[1], hi[1] = min(ys) - reach, max(ys) + reach
+        sel = [np.nonzero((smp[a][0] >= lo[ai]) & (smp[a][0] <= hi[ai]))[0] for ai, a in enumerate("xyz")]
+        iz, iy, ix = np.meshgrid(sel[2], sel[1], sel[0], indexing="ij")
+        out.append(((iz * ny + iy) * nx + ix).ravel())
+    return np.unique(np.concatenate(out)) if out else np.zeros(0, dtype=np.int64)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def test_eps_sampled(name):
+    cfg, sc, E, A, Ed, Ad = _setup(name)
+    eps = api().eps_build(sc, cfg["p"]).cpu().numpy()
+    rng = np.random.default_rng(7)
+    for ci in range(sc.ncomp):
+        flat = eps[ci].ravel()
+        # random samples plus samples near every primitive boundary (where eps varies)
+        idx = rng.choice(flat.size, 3000, replace=False)
+        mid = np.nonzero((flat > cfg["scene"]["eps_bg"] + 1e-3) & (flat < cfg["scene"]["eps_fg"] - 1e-3))[0]
+        if mid.size:
+            idx = np.concatenate([idx, rng.choice(mid, min(3000, mid.size), replace=False)])
+        ref = S.eps_at(cfg["scene"], cfg["p"], ci, idx)
+        print(f"[fullsize] {name} comp {ci}: {idx.size} samples", flush=True)
+        assert np.max(np.abs(flat[idx] - ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("name,nk", [("c2", 16), ("c3", 10), ("c4", 12)])
+def test_vjp_sampled_params(name, nk):
+    cfg, sc, E, A, Ed, Ad = _setup(name)
+    got = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    rng = np.random.default_rng(3)
+    ks = np.sort(rng.choice(sc.n_params, nk, replace=False))
+    ref = np.zeros(nk)
+    d = cfg["scene"]
+    for j, k in enumerate(ks):
+        acc = np.zeros(d["n_params"])
+        for ci in range(sc.ncomp):
+            region = _param_region(d, cfg["p"], int(k), ci)
+            g_fn = lambda f, ci=ci: S.sensitivity(E[ci].ravel()[f], A[ci].ravel()[f], cfg["omega"])
+            S.grad_analytic_region(d, cfg["p"], g_fn, ci, region, acc)
+        ref[j] = acc[k]
+        print(f"[fullsize] {name} param {k}: gpu {got[k]:.6e} oracle {ref[j]:.6e}", flush=True)
+    assert rel(got[ks], ref) <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def test_fd_matches_vjp_full_size(name):
+    cfg, sc, E, A, Ed, Ad = _setup(name)
+    g_vjp = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    g_fd = api().eps_grad_fd(sc, cfg["p"], Ed, Ad, cfg["omega"], cfg["h"])
+    print(f"[fullsize] {name} fd vs vjp rel {rel(g_fd, g_vjp):.3e}", flush=True)
+    assert rel(g_fd, g_vjp) <= 1e-4

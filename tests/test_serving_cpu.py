@@ -1,0 +1,159 @@
+"""Scheduling logic of the serving loop, on the CPU: the C++ scheduler runs
+with its fake executor (no device work; a request's result is
+grad_k = 2 p_k + (seed mod 1000) after a fixed delay).  Covers routing of
+results to tickets, HBM-budget admission in arrival order, slot limits,
+batching of requests that arrive while others run, cancellation, polling
+time-outs, invalid requests and an injected launch failure."""
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _server(**kw):
+    from paper_2311_05646_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2311_05646_amd import build
+        build.build()
+    from paper_2311_05646_amd.api import Server
+    kw.setdefault("fake_executor", True)
+    return Server(**kw)
+
+
+def _expect(p, seed):
+    return 2.0 * np.asarray(p) + (seed % 1000)
+
+
+def test_results_reach_their_tickets():
+    srv = _server(hbm_budget_bytes=1 << 20, max_slots=8, max_batch=4, n_streams=2, fake_us=2000)
+    sids = [srv.open_fake_session(n, 1000) for n in (3, 7, 1)]
+    rng = np.random.default_rng(0)
+    sent = []
+    for i in range(30):
+        sid = sids[i % 3]
+        p = rng.standard_normal(srv.n_params[sid])
+        sent.append((srv.submit(sid, p, 1000 + i, 1.0), sid, p, 1000 + i))
+    for t, sid, p, seed in sent:
+        st, g, stats = srv.poll(t, srv.n_params[sid])
+        assert st == "ok"
+        assert np.array_equal(g, _expect(p, seed))
+        assert stats["submit_ns"] <= stats["admit_ns"] <= stats["launch_ns"] <= stats["done_ns"]
+    c = srv.counters()
+    assert c["completed"] == 30 and c["bytes_in_use"] == 0
+    assert 1 < c["max_batch"] <= 4
+    srv.close()
+
+
+def test_budget_admits_in_arrival_order():
+    # budget fits 2 requests of 400 bytes at a time
+    srv = _server(hbm_budget_bytes=1000, max_slots=16, max_batch=16, n_streams=1, fake_us=20000)
+    sid = srv.open_fake_session(2, 400)
+    tickets = [srv.submit(sid, [i, i], i, 1.0) for i in range(6)]
+    time.sleep(0.005)
+    assert srv.counters()["bytes_in_use"] <= 1000
+    admits = []
+    for i, t in enumerate(tickets):
+        st, g, stats = srv.poll(t, 2)
+        assert st == "ok" and np.array_equal(g, _expect([i, i], i))
+        admits.append(stats["admit_ns"])
+    assert admits == sorted(admits)
+    # at most two batches' worth of requests ran at once: 3 rounds of 20 ms
+    srv.close()
+
+
+def test_too_large_is_rejected_immediately():
+    from paper_2311_05646_amd._lib import SGError
+    srv = _server(hbm_budget_bytes=1000, max_slots=4, max_batch=4, n_streams=1, fake_us=0)
+    sid = srv.open_fake_session(1, 5000)
+    with pytest.raises(SGError) as e:
+        srv.submit(sid, [0.0], 1, 1.0)
+    assert e.value.code == -3
+    srv.close()
+
+
+def test_slot_limit():
+    srv = _server(hbm_budget_bytes=1 << 30, max_slots=2, max_batch=8, n_streams=4, fake_us=30000)
+    sid = srv.open_fake_session(1, 10)
+    ts = [srv.submit(sid, [float(i)], i, 1.0) for i in range(5)]
+    time.sleep(0.01)
+    c = srv.counters()
+    assert c["bytes_in_use"] == 20          # two admitted, three waiting
+    for t in ts:
+        assert srv.poll(t, 1)[0] == "ok"
+    assert srv.counters()["max_batch"] <= 2
+    srv.close()
+
+
+def test_continuous_batching_of_late_arrivals():
+    srv = _server(hbm_budget_bytes=1 << 30, max_slots=64, max_batch=64, n_streams=2, fake_us=30000)
+    sid = srv.open_fake_session(1, 10)
+    first = srv.submit(sid, [1.0], 1, 1.0)
+    time.sleep(0.005)                         # the first batch is running
+    late = [srv.submit(sid, [float(i)], i, 1.0) for i in range(10)]
+    st, g, s_first = srv.poll(first, 1)
+    stats = [srv.poll(t, 1)[2] for t in late]
+    # late arrivals were admitted and launched on the free stream while the
+    # first request was still running, several per launch
+    assert min(s["launch_ns"] for s in stats) < s_first["done_ns"]
+    assert len({s["launch_ns"] for s in stats}) <= 3
+    assert max(s["batch_size"] for s in stats) > 1
+    srv.close()
+
+
+def test_cancel_and_timeout():
+    from paper_2311_05646_amd._lib import SGError
+    srv = _server(hbm_budget_bytes=1 << 30, max_slots=1, max_batch=1, n_streams=1, fake_us=50000)
+    sid = srv.open_fake_session(1, 10)
+    t1 = srv.submit(sid, [1.0], 1, 1.0)
+    t2 = srv.submit(sid, [2.0], 2, 1.0)      # waits behind t1 (one slot)
+    assert srv.poll(t1, 1, timeout_us=1000)[0] == "pending"
+    srv.cancel(t2)
+    with pytest.raises(SGError) as e:
+        srv.poll(t2, 1)
+    assert e.value.code == -5
+    assert srv.poll(t1, 1)[0] == "ok"
+    with pytest.raises(SGError):
+        srv.poll(t1, 1)                       # retired
+    srv.close()
+
+
+def test_invalid_requests():
+    from paper_2311_05646_amd._lib import SGError
+    srv = _server(hbm_budget_bytes=1 << 20, max_slots=4, max_batch=4, n_streams=1, fake_us=0)
+    sid = srv.open_fake_session(2, 10)
+    with pytest.raises(SGError):
+        srv.submit(sid, [np.nan, 0.0], 1, 1.0)
+    with pytest.raises(SGError):
+        srv.submit(sid + 5, [0.0, 0.0], 1, 1.0)
+    with pytest.raises(ValueError):
+        srv.submit(sid, [0.0], 1, 1.0)
+    srv.close()
+
+
+def test_injected_launch_failure_fails_only_that_batch():
+    code = r'''
+import sys, numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2311_05646_amd.api import Server
+from paper_2311_05646_amd._lib import SGError
+srv = Server(hbm_budget_bytes=1 << 20, max_slots=1, max_batch=1, n_streams=1, fake_executor=True, fake_us=1000)
+sid = srv.open_fake_session(1, 10)
+ts = [srv.submit(sid, [float(i)], i, 1.0) for i in range(4)]
+out = []
+for t in ts:
+    try:
+        out.append(srv.poll(t, 1)[0])
+    except SGError as e:
+        out.append(e.code)
+print(out)
+srv.close()
+'''
+    env = dict(os.environ, SG_FAULT_INJECT="launch:1")
+    r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "['ok', -4, 'ok', 'ok']"
