@@ -135,6 +135,74 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
             "eps_us": 1e3 * ve / ne, "eps_GBps": 4.0 * m / (ve / ne * 1e-3) / 1e9, "samples": m}
 
 
+def bench_serving(api, W, seconds=3.0, think_us=200.0):
+    """64 closed-loop sessions (the serving mix) against the serving loop:
+    each session submits, waits for its gradient, thinks Exp(think_us) and
+    submits again with fresh p and a fresh field seed.  The same requests are
+    then replayed one at a time through the single-request entry points."""
+    import numpy as np
+    import torch
+    mix = W.make_serving_mix()
+    scenes = [api.Scene(c["scene"]) for c in mix]
+    srv = api.Server(hbm_budget_bytes=24 << 30, max_slots=64, max_batch=16, n_streams=2)
+    sids = [srv.open_session(sc) for sc in scenes]
+    rng = np.random.default_rng(5)
+    seed_ctr = [1]
+
+    def new_req(i):
+        c = mix[i]
+        p = c["p"] + c["jitter"] * rng.standard_normal(c["p"].shape)
+        seed_ctr[0] += 1
+        return p, (W.BASE_SEED << 16) + seed_ctr[0]
+
+    # warm-up: one request per session (allocates each session's buffers)
+    warm = [(i, srv.submit(sids[i], *new_req(i), mix[i]["omega"])) for i in range(len(mix))]
+    for i, t in warm:
+        srv.poll(t, scenes[i].n_params)
+    # timed closed loop
+    lat, done_reqs = [], []
+    outstanding = {}
+    next_at = {i: 0.0 for i in range(len(mix))}
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        if now >= seconds and not outstanding:
+            break
+        for i in range(len(mix)):
+            if i not in outstanding and now < seconds and now >= next_at[i]:
+                p, sd = new_req(i)
+                outstanding[i] = (srv.submit(sids[i], p, sd, mix[i]["omega"]), p, sd)
+        for i in list(outstanding):
+            t, p, sd = outstanding[i]
+            st, g, stt = srv.poll(t, scenes[i].n_params, timeout_us=0)
+            if st == "ok":
+                del outstanding[i]
+                lat.append((stt["done_ns"] - stt["submit_ns"]) * 1e-6)
+                done_reqs.append((i, p, sd))
+                next_at[i] = (time.perf_counter() - t0) + rng.exponential(think_us * 1e-6)
+    wall = time.perf_counter() - t0
+    cnt = srv.counters()
+    srv.close()
+    # the same requests, one at a time
+    t1 = time.perf_counter()
+    seq_lat = []
+    for i, p, sd in done_reqs:
+        ts = time.perf_counter()
+        E, A = api.fieldgen(scenes[i], sd)
+        api.eps_grad_vjp(scenes[i], p, E, A, mix[i]["omega"])      # host grad: waits for the result
+        seq_lat.append((time.perf_counter() - ts) * 1e3)
+    seq_wall = time.perf_counter() - t1
+    kinds = {k: sum(1 for c in mix if c["kind"] == k) for k in ("c1", "c2s", "c3")}
+    lat = np.array(lat)
+    return {"sessions": len(mix), "session_kinds": kinds, "requests": len(done_reqs), "seconds": wall,
+            "grads_per_s": len(done_reqs) / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "batches": cnt["batches"], "max_batch": cnt["max_batch"],
+            "sequential": {"grads_per_s": len(done_reqs) / seq_wall,
+                           "p50_ms": float(np.percentile(seq_lat, 50)), "p99_ms": float(np.percentile(seq_lat, 99))},
+            "speedup_vs_sequential": (len(done_reqs) / wall) / (len(done_reqs) / seq_wall),
+            "think_us": think_us}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +210,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true", help="also run the reference copy kernel (1 GiB)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path shards by grid slab "
@@ -267,14 +336,9 @@ def main():
         torch.cuda.empty_cache()
     out["3d"] = also
 
-    # ---- serving (continuous batching) -- filled in by the serving runtime when present
-    out["serve"] = None
-    try:
-        from paper_2311_05646_amd import serving
-        log("[bench] serving")
-        out["serve"] = serving.bench_serving(api, W)
-    except ImportError:
-        pass
+    # ---- serving: continuous batching vs one-at-a-time launches
+    log("[bench] serving")
+    out["serve"] = bench_serving(api, W, seconds=args.serve_seconds)
 
     # ---- CPU oracle on this host
     log("[bench] cpu baseline (oracle)")

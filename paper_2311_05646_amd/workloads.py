@@ -309,6 +309,34 @@ def make_c4(seed=BASE_SEED + 3, with_fields=True, **kw):
     return out
 
 
+def make_serving_mix(seed=BASE_SEED + 4, n_sessions=64):
+    """Serving mix: sessions of three kinds drawn 30 / 50 / 20 %: the 2D
+    plain-method grating (160x80, Ez), the 2D blazed grating scaled by
+    s_x, s_y ~ U(0.5, 1) per axis (the etch count scales with s_x), and the 3D
+    taper.  Returns a list of dicts with scene, p, omega and the per-request
+    perturbation scale (0.2 of the smallest cell)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    kinds = rng.choice(3, size=n_sessions, p=[0.3, 0.5, 0.2])
+    out = []
+    for i, kind in enumerate(kinds):
+        if kind == 0:
+            c = make_c1(seed + 10 * i)
+            c.pop("E"), c.pop("A")
+            c["kind"], c["jitter"] = "c1", 0.2 * 0.02
+        elif kind == 1:
+            sx, sy = rng.uniform(0.5, 1.0, size=2)
+            nx, ny = int(4000 * sx), int(600 * sy)
+            L = 70.0 * nx / 4000
+            r2 = np.random.Generator(np.random.PCG64(seed + 10 * i))
+            scene, p = c2_scene(r2, nx=nx, ny=ny, n_periods=max(1, int((L - 7.0) / 1.2)), x_start=5.0, period=1.2)
+            c = {"scene": scene, "p": p, "omega": _wl_omega(1.55), "kind": "c2s", "jitter": 0.2 * 0.01}
+        else:
+            c = make_c3(seed + 10 * i, with_fields=False)
+            c["kind"], c["jitter"] = "c3", 0.2 * 0.01
+        out.append(c)
+    return out
+
+
 # small variants of the same structure (several tiles, ragged tails)
 def make_c2_small(seed=BASE_SEED + 11):
     return make_c2(seed, nx=300, ny=64, n_periods=3, x_start=1.2, period=1.0)
