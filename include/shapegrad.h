@@ -240,11 +240,13 @@ sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches
                          int64_t* bytes_in_use);
 
 /* Kernel tracing.  With timing enabled the scene records a pair of HIP events
- * on the call's stream around every launch of its main column kernel.
- * sg_scene_set_timing(scene, 1) enables and clears the records, 0 disables.
- * sg_scene_kernel_time() waits for the recorded launches of one kind (mode:
- * 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps, 3 eps_grad_fd rasterization)
- * and returns their summed duration (ms) and count. */
+ * on the call's stream around every launch of its column kernel (the kernel
+ * that evaluates eps or its reverse mode; a call also runs a small staging
+ * kernel before it).  sg_scene_set_timing(scene, 1) enables and clears the
+ * records, 0 disables.  sg_scene_kernel_time() waits for the recorded launches
+ * of one kind (mode: 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps,
+ * 3 eps_grad_fd rasterization) and returns their summed duration (ms) and
+ * count. */
 sg_status sg_scene_set_timing(sg_scene* scene, int enable);
 sg_status sg_scene_kernel_time(sg_scene* scene, int mode, double* total_ms, int64_t* launches);
 

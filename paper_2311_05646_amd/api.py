@@ -58,7 +58,7 @@ class Scene:
         check(lib().sg_scene_set_launch(self.handle, int(block_x), int(col_segments)))
 
     def set_timing(self, enable=True):
-        """Trace the main column kernel of every later call (HIP events on the
+        """Trace the column kernel of every later call (HIP events on the
         call's stream); enabling clears earlier records."""
         check(lib().sg_scene_set_timing(self.handle, int(bool(enable))))
 

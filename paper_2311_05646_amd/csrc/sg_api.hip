@@ -76,7 +76,10 @@ static void free_scene(sg_scene* s) {
     for (int i = 0; i < 2; ++i) {
         hipFree(s->d_fval[i]);
         hipFree(s->d_bbox[i]);
+        hipFree(s->d_prec[i]);
         hipFree(s->d_ztab[i]);
+        hipFree(s->d_code[i]);
+        hipFree(s->d_gcode[i]);
         hipFree(s->d_work[i]);
     }
     hipFree(s->d_grad);
@@ -299,6 +302,13 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     s->sv = stride[axis_v];
     s->sw = stride[col];
     s->plane = plane;
+    // the stream kernel addresses 8 column steps of complex64 samples from one
+    // buffer resource with 32-bit offsets
+    if (s->sw * 8 * 8 >= ((int64_t)1 << 31)) {
+        free_scene(s);
+        return fail(SG_E_TOO_LARGE, "the plane across the column axis holds %lld samples (limit %lld)",
+                    (long long)s->sw, (long long)(((int64_t)1 << 31) / 64 - 1));
+    }
     s->fields.assign(d->fields, d->fields + d->nfield);
 
     // extrusion classes
@@ -482,8 +492,11 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     alloc((void**)&s->d_grad, std::max<int64_t>(1, d->n_params) * sizeof(double));
     for (int v = 0; v < 2; ++v) {
         alloc((void**)&s->d_fval[v], std::max<int64_t>(1, d->nfield) * sizeof(double));
-        alloc((void**)&s->d_bbox[v], prims.size() * sizeof(double4));
+        alloc((void**)&s->d_bbox[v], prims.size() * sizeof(float4));
+        alloc((void**)&s->d_prec[v], prims.size() * sizeof(PrimRec));
         alloc((void**)&s->d_ztab[v], (size_t)d->ncomp * s->nclass * s->nw * 3 * sizeof(double));
+        alloc((void**)&s->d_code[v], (size_t)d->ncomp * s->nw * sizeof(uint32_t));
+        alloc((void**)&s->d_gcode[v], (size_t)d->ncomp * ((s->nw + kGroup - 1) / kGroup) * sizeof(uint32_t));
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_p, std::max<int64_t>(1, d->n_params) * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_grad, std::max<int64_t>(1, d->n_params) * sizeof(double));
@@ -563,7 +576,10 @@ StageParams sg::stage_params(sg_scene* s, const double* dp) {
     for (int v = 0; v < 2; ++v) {
         sp.fval[v] = s->d_fval[v];
         sp.bbox[v] = s->d_bbox[v];
+        sp.prec[v] = s->d_prec[v];
         sp.ztab[v] = s->d_ztab[v];
+        sp.code[v] = s->d_code[v];
+        sp.gcode[v] = s->d_gcode[v];
     }
     for (int c = 0; c < kMaxComp; ++c) {
         const int cc = std::min(c, s->ncomp - 1);
@@ -585,11 +601,10 @@ KParams sg::column_params(sg_scene* s) {
     kp.sv = s->sv;
     kp.sw = s->sw;
     kp.plane = s->plane;
+    // square tiles when many primitives compete for a tile, wide rows of x
+    // (contiguous field bytes per column step) otherwise
     int tu = s->block_x;
-    if (tu == 0) {
-        if (s->nv == 1) tu = 256;
-        else tu = s->nprim > 32 ? 16 : 128;
-    }
+    if (tu == 0) tu = (s->nv == 1) ? 256 : (s->nprim > 32 ? 16 : 128);
     kp.tu = tu;
     kp.tv = kBlock / tu;
     kp.tiles_u = (s->nu + tu - 1) / tu;
@@ -597,11 +612,12 @@ KParams sg::column_params(sg_scene* s) {
     int nseg = s->nseg;
     if (nseg == 0) {
         const int64_t base = (int64_t)s->ncomp * kp.tiles_u * kp.tiles_v;
-        const int64_t target = 1024;
+        const int64_t target = 768;    // about three blocks per CU
         nseg = (int)std::max<int64_t>(1, std::min<int64_t>((target + base - 1) / base, (s->nw + 15) / 16));
     }
     nseg = std::min(nseg, s->nw);
-    kp.seglen = (s->nw + nseg - 1) / nseg;
+    // segments start at multiples of the group length
+    kp.seglen = ((s->nw + nseg - 1) / nseg + kGroup - 1) / kGroup * kGroup;
     kp.nseg = (s->nw + kp.seglen - 1) / kp.seglen;
     kp.nprim = s->nprim;
     kp.nclass = s->nclass;
@@ -635,16 +651,23 @@ KParams sg::column_params(sg_scene* s) {
     kp.consts = s->d_consts;
     kp.fval = s->d_fval[0];
     kp.bbox = s->d_bbox[0];
+    kp.prec = s->d_prec[0];
     kp.ztab = s->d_ztab[0];
     kp.fval2 = s->d_fval[1];
     kp.bbox2 = s->d_bbox[1];
+    kp.prec2 = s->d_prec[1];
     kp.ztab2 = s->d_ztab[1];
+    kp.code = s->d_code[0];
+    kp.code2 = s->d_code[1];
+    kp.gcode = s->d_gcode[0];
+    kp.gcode2 = s->d_gcode[1];
     return kp;
 }
 
 int64_t sg::staging_bytes(const sg_scene* s) {
-    return 8 * std::max<int64_t>(1, s->nfield) + 32 * (int64_t)s->nprim +
-           24 * (int64_t)s->ncomp * s->nclass * s->nw + 16 * std::max<int64_t>(1, s->n_params);
+    return 8 * std::max<int64_t>(1, s->nfield) + (16 + (int64_t)sizeof(PrimRec)) * s->nprim +
+           28 * (int64_t)s->ncomp * s->nclass * s->nw + 4 * (int64_t)s->ncomp * ((s->nw + kGroup - 1) / kGroup) +
+           16 * std::max<int64_t>(1, s->n_params);
 }
 
 static sg_status check_call(sg_ctx* ctx, sg_scene* s) {

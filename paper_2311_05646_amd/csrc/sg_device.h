@@ -34,15 +34,45 @@ enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_ALL = 15 };
 enum : int { S_SIGMOID = 1, S_ERF = 2, S_SIN = 4, S_LIN = 8, S_QUAD = 16, S_ALL = 31 };
 
 // ---- one function per kind: value, and value + d/dt
+
+// Logistic sigmoid for |t| < kSigmoidCut in FP64.  With a = |t|,
+// e^-a = 2^n e^x where n = rint(-a log2 e) and |x| <= ln(2) / 2; e^x is the
+// degree-9 Taylor polynomial (truncation below 1e-11 relative), 2^n an exponent
+// shift, and 1 / (1 + e^-a) takes the hardware reciprocal plus two Newton steps.
+// sigma(t) = 1 / (1 + e^-a) for t >= 0 and e^-a / (1 + e^-a) for t < 0.
+__device__ __forceinline__ double sigm_core(double t) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2 = 0.69314718055994531;
+    const double a = fabs(t);
+    const double y = -a * kLog2e;
+    const double n = rint(y);
+    const double x = (y - n) * kLn2;
+    double p = 1.0 / 362880.0;
+    p = fma(p, x, 1.0 / 40320.0);
+    p = fma(p, x, 1.0 / 5040.0);
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    p = fma(p, x, 1.0);
+    const double e = ldexp(p, (int)n);          // e^-a in (0, 1]
+    const double d = 1.0 + e;                   // in (1, 2]
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return t >= 0.0 ? r : e * r;
+}
 __device__ __forceinline__ double sigm_v(double t) {
     if (t <= -kSigmoidCut) return 0.0;
     if (t >= kSigmoidCut) return 1.0;
-    return 1.0 / (1.0 + exp(-t));
+    return sigm_core(t);
 }
 __device__ __forceinline__ void sigm_vd(double t, double& s, double& ds) {
     if (t <= -kSigmoidCut) { s = 0.0; ds = 0.0; return; }
     if (t >= kSigmoidCut) { s = 1.0; ds = 0.0; return; }
-    s = 1.0 / (1.0 + exp(-t));
+    s = sigm_core(t);
     ds = s * (1.0 - s);
 }
 __device__ __forceinline__ double erf_v(double t) {
@@ -93,12 +123,25 @@ __device__ __forceinline__ void quad_vd(double t, double& s, double& ds) {
     ds = 0.0;
 }
 // out-of-line copies of the transcendental kinds for the catch-all kernels
+// (value and derivative come back as one pair, in registers)
 static __device__ __noinline__ double sigm_v_call(double t) { return sigm_v(t); }
-static __device__ __noinline__ void sigm_vd_call(double t, double& s, double& ds) { sigm_vd(t, s, ds); }
+static __device__ __noinline__ double2 sigm_vd_call(double t) {
+    double s, ds;
+    sigm_vd(t, s, ds);
+    return make_double2(s, ds);
+}
 static __device__ __noinline__ double erf_v_call(double t) { return erf_v(t); }
-static __device__ __noinline__ void erf_vd_call(double t, double& s, double& ds) { erf_vd(t, s, ds); }
+static __device__ __noinline__ double2 erf_vd_call(double t) {
+    double s, ds;
+    erf_vd(t, s, ds);
+    return make_double2(s, ds);
+}
 static __device__ __noinline__ double sin_v_call(double t) { return sin_v(t); }
-static __device__ __noinline__ void sin_vd_call(double t, double& s, double& ds) { sin_vd(t, s, ds); }
+static __device__ __noinline__ double2 sin_vd_call(double t) {
+    double s, ds;
+    sin_vd(t, s, ds);
+    return make_double2(s, ds);
+}
 
 // sigma(t) for a kind drawn from SIGS
 template <int SIGS>
@@ -126,11 +169,20 @@ __device__ __forceinline__ void sig_vd(int kind, double t, double& s, double& ds
         if constexpr ((SIGS & S_LIN) != 0) if (kind == SG_SIGMA_LINEAR) { lin_vd(t, s, ds); return; }
         if constexpr ((SIGS & S_QUAD) != 0) if (kind == SG_SIGMA_QUADRATIC) { quad_vd(t, s, ds); return; }
         if constexpr ((SIGS & S_SIGMOID) != 0)
-            if (kind == SG_SIGMA_SIGMOID) { if (inl) sigm_vd(t, s, ds); else sigm_vd_call(t, s, ds); return; }
+            if (kind == SG_SIGMA_SIGMOID) {
+                if (inl) { sigm_vd(t, s, ds); } else { const double2 r = sigm_vd_call(t); s = r.x; ds = r.y; }
+                return;
+            }
         if constexpr ((SIGS & S_ERF) != 0)
-            if (kind == SG_SIGMA_ERF) { if (inl) erf_vd(t, s, ds); else erf_vd_call(t, s, ds); return; }
+            if (kind == SG_SIGMA_ERF) {
+                if (inl) { erf_vd(t, s, ds); } else { const double2 r = erf_vd_call(t); s = r.x; ds = r.y; }
+                return;
+            }
         if constexpr ((SIGS & S_SIN) != 0)
-            if (kind == SG_SIGMA_SIN) { if (inl) sin_vd(t, s, ds); else sin_vd_call(t, s, ds); return; }
+            if (kind == SG_SIGMA_SIN) {
+                if (inl) { sin_vd(t, s, ds); } else { const double2 r = sin_vd_call(t); s = r.x; ds = r.y; }
+                return;
+            }
         s = 0.0;
         ds = 0.0;
     }

@@ -12,10 +12,18 @@ constexpr int kMaxComp = 3;
 constexpr int kMaxGroups = 4;
 constexpr int kMaxClasses = 8;
 constexpr int kBlock = 256;        // threads (= in-plane samples) per block
-constexpr int kCandCap = 1024;     // candidate primitives staged in LDS per pass
+constexpr int kCandCap = 2048;     // candidate primitives listed in LDS per pass
 constexpr int kZStage = 512;       // extrusion-table entries staged in LDS per chunk
 
 enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3 };
+// Column-step codes written by k_stage, one per (component, w): bits 0-7 hold
+// the mask of classes whose extrusion factor is exactly 1 when every class
+// factor is exactly 0 or 1 (and the w-bound derivatives of classes with
+// column-axis parameters vanish); kCodeGeneral marks any other step.  A group
+// code covers kGroup consecutive steps starting at a multiple of kGroup: their
+// common code, or kCodeGeneral when they differ.
+constexpr uint32_t kCodeGeneral = 1u << 16;
+constexpr int kGroup = 4;    // the stage kernel and the stream kernel's group paths assume 4
 enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
 // kernel feature variants (primitive types x in-plane sigma kinds), smallest first
 enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_ALL = 3 };
@@ -53,6 +61,20 @@ struct DevPrim {
     double iax, iay;       // 1 / aspect
 };
 
+// Per-call copy of a primitive as the in-plane and partials kernels read it
+// (written by k_stage): the record, its support box (u_lo, u_hi, v_lo, v_hi),
+// and for boxes and ellipses the resolved values of their in-plane fields
+// (boxes: u0 u1 v0 v1; ellipses: x0 y0 r) with the parameter index (-1:
+// constant) and scale of each.
+struct PrimRec {
+    DevPrim pr;
+    double4 bb;
+    double f[4];
+    double fb[4];
+    int32_t fidx[4];
+    int32_t pad[2];
+};
+
 // An extrusion class: primitives of one group that share the same factor
 // along the column axis (a Rect1D in w, or 1).
 struct DevClass {
@@ -74,8 +96,11 @@ struct StageParams {
     int64_t pert_idx;            // parameter perturbed by +delta[variant] (-1: none)
     double delta[2];
     double* fval[2];
-    double4* bbox[2];            // (u_lo, u_hi, v_lo, v_hi) of the support, per primitive
+    float4* bbox[2];             // (u_lo, u_hi, v_lo, v_hi) of the support, rounded outward
+    PrimRec* prec[2];
     double* ztab[2];             // [comp][class][w][3] = Z, dZ/dlo, dZ/dhi
+    uint32_t* code[2];           // [comp][w] step codes
+    uint32_t* gcode[2];          // [comp][group] group codes
     const double* wc[kMaxComp];  // column-axis sample centers / widths per component
     const double* ww[kMaxComp];
     int32_t nfield;
@@ -87,8 +112,8 @@ struct StageParams {
 struct KParams {
     int32_t nu, nv, nw, ncomp;
     int64_t sv, sw, plane;       // element strides of v and w, elements per component plane
-    int32_t tu, tv, tiles_u, tiles_v;
-    int32_t nseg, seglen;
+    int32_t tu, tv, tiles_u, tiles_v;        // in-plane tiles of the column kernel's blocks
+    int32_t nseg, seglen;                    // column segments (seglen a multiple of kGroup)
     int32_t nprim, nclass;
     int32_t cls_group[kMaxClasses];
     int32_t cls_wparam[kMaxClasses];
@@ -106,11 +131,17 @@ struct KParams {
     const sg_field* fref;
     const double* consts;
     const double* fval;
-    const double4* bbox;
+    const float4* bbox;
+    const PrimRec* prec;
     const double* ztab;
     const double* fval2;         // FD: the second evaluation point
-    const double4* bbox2;
+    const float4* bbox2;
+    const PrimRec* prec2;
     const double* ztab2;
+    const uint32_t* code;        // step codes [comp][w]
+    const uint32_t* code2;
+    const uint32_t* gcode;       // group codes [comp][group]
+    const uint32_t* gcode2;
     float* out;                  // eps (MODE_EPS) or difference plane (MODE_FD)
     const float2* ef[kMaxComp];
     const float2* ea[kMaxComp];

@@ -21,9 +21,23 @@
 namespace sg {
 
 // ------------------------------------------------------------------ stage
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Blocks [0, prim_blocks) take one primitive per wavefront: its fields are
+// resolved by the lanes in parallel, the support box is reduced across the
+// wavefront and lane 0 writes the primitive's record.  The remaining blocks
+// take one (component, group of column steps) or one gradient entry per thread.
 __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
     const int var = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const double delta = sp.delta[var];
     auto resolve = [&](int f) -> double {
         const sg_field r = sp.fref[f];
@@ -32,9 +46,12 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         if (r.idx == sp.pert_idx) pv += delta;
         return r.a + r.b * pv;
     };
-    if (var == 0 && sp.zero_ptr != nullptr && t < sp.zero_n) sp.zero_ptr[t] = 0.0;
-    if (t < sp.nprim) {
-        const DevPrim pr = sp.prims[t];
+    const int prim_blocks = (sp.nprim + 3) / 4;
+    if ((int)blockIdx.x < prim_blocks) {
+        const int lane = threadIdx.x & 63;
+        const int pi = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+        if (pi >= sp.nprim) return;
+        const DevPrim pr = sp.prims[pi];
         double* fv = sp.fval[var];
         int nf;
         switch (pr.type) {
@@ -43,75 +60,153 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             case SG_PRIM_POLY: nf = 2 * pr.nvert + 2; break;
             default: nf = 2 * pr.nvert + 4; break;
         }
-        for (int i = 0; i < nf; ++i) fv[pr.f0 + i] = resolve(pr.f0 + i);
+        // lane i resolves fields f0 + i, f0 + i + 64, ...; the first one stays
+        // in the lane for the boxes' and ellipses' record fields
+        double v0 = 0.0, b0 = 0.0;
+        int idx0 = -1;
+        for (int i = lane; i < nf; i += 64) {
+            const sg_field r = sp.fref[pr.f0 + i];
+            double v = r.a;
+            if (r.idx >= 0) {
+                double pv = sp.p[r.idx];
+                if (r.idx == sp.pert_idx) pv += delta;
+                v = r.a + r.b * pv;
+            }
+            fv[pr.f0 + i] = v;
+            if (i == lane) {
+                v0 = v;
+                idx0 = r.idx;
+                b0 = r.b;
+            }
+        }
         const double inf = __builtin_huge_val();
         double4 b = make_double4(-inf, inf, -inf, inf);
+        // lanes 0-3 fetch field f0 + koff: a box's u0 u1 v0 v1, otherwise the
+        // first four fields (ellipse x0 y0 r; boundary x-range)
+        int koff = min(lane, 3);
+        if (pr.type == SG_PRIM_BOX) koff = (lane == 0 ? pr.fu0 : lane == 1 ? pr.fu1 : lane == 2 ? pr.fv0 : pr.fv1) - pr.f0;
+        const double kv = __shfl(v0, koff, 64);
+        const int kidx = __shfl(idx0, koff, 64);
+        const double kb = __shfl(b0, koff, 64);
+        const double r0 = __shfl(kv, 0, 64), r1 = __shfl(kv, 1, 64), r2 = __shfl(kv, 2, 64), r3 = __shfl(kv, 3, 64);
         if (pr.type == SG_PRIM_BOX) {
-            if (pr.ubnd) { b.x = resolve(pr.fu0) - pr.reach0; b.y = resolve(pr.fu1) + pr.reach0; }
-            if (pr.vbnd) { b.z = resolve(pr.fv0) - pr.reach1; b.w = resolve(pr.fv1) + pr.reach1; }
+            if (pr.ubnd) { b.x = r0 - pr.reach0; b.y = r1 + pr.reach0; }
+            if (pr.vbnd) { b.z = r2 - pr.reach1; b.w = r3 + pr.reach1; }
         } else if (pr.type == SG_PRIM_ELLIPSE) {
-            const double R = resolve(pr.f0 + 2) + pr.reach0;
-            const double x0 = resolve(pr.f0), y0 = resolve(pr.f0 + 1);
-            if (R < 0.0) {
-                b = make_double4(inf, -inf, inf, -inf);
-            } else {
-                b = make_double4(x0 - R * pr.ax, x0 + R * pr.ax, y0 - R * pr.ay, y0 + R * pr.ay);
-            }
+            const double R = r2 + pr.reach0;
+            if (R < 0.0) b = make_double4(inf, -inf, inf, -inf);
+            else b = make_double4(r0 - R * pr.ax, r0 + R * pr.ax, r1 - R * pr.ay, r1 + R * pr.ay);
         } else if (pr.type == SG_PRIM_POLY) {
             // the support is the polygon offset outward by reach0: its vertices
             // are v_i - d (n_{i-1} + n_i) / (1 + n_{i-1} . n_i), n inward normals
+            auto resolve_f = [&](int f) -> double { return resolve(f); };
             const int N = pr.nvert;
-            b = make_double4(inf, -inf, inf, -inf);
-            for (int i = 0; i < N; ++i) {
+            double xlo = inf, xhi = -inf, ylo = inf, yhi = -inf;
+            bool open = false;
+            for (int i = lane; i < N; i += 64) {
                 const int ip = (i == 0) ? N - 1 : i - 1, in = (i + 1 == N) ? 0 : i + 1;
-                const double xi = resolve(pr.f0 + i), yi = resolve(pr.f0 + N + i);
-                const double xp = resolve(pr.f0 + ip), yp = resolve(pr.f0 + N + ip);
-                const double xn = resolve(pr.f0 + in), yn = resolve(pr.f0 + N + in);
-                double ax = xi - xp, ay = yi - yp, bx = xn - xi, by = yn - yi;
+                const double xi = resolve_f(pr.f0 + i), yi = resolve_f(pr.f0 + N + i);
+                const double xp = resolve_f(pr.f0 + ip), yp = resolve_f(pr.f0 + N + ip);
+                const double xn = resolve_f(pr.f0 + in), yn = resolve_f(pr.f0 + N + in);
+                const double ax = xi - xp, ay = yi - yp, bx = xn - xi, by = yn - yi;
                 const double la = sqrt(ax * ax + ay * ay), lb = sqrt(bx * bx + by * by);
                 const double nax = -ay / la, nay = ax / la, nbx = -by / lb, nby = bx / lb;
                 const double den = 1.0 + nax * nbx + nay * nby;
-                double ox, oy;
                 if (den > 1e-12) {
-                    ox = xi - pr.reach0 * (nax + nbx) / den;
-                    oy = yi - pr.reach0 * (nay + nby) / den;
-                    b.x = fmin(b.x, ox); b.y = fmax(b.y, ox);
-                    b.z = fmin(b.z, oy); b.w = fmax(b.w, oy);
+                    const double ox = xi - pr.reach0 * (nax + nbx) / den;
+                    const double oy = yi - pr.reach0 * (nay + nby) / den;
+                    xlo = fmin(xlo, ox); xhi = fmax(xhi, ox);
+                    ylo = fmin(ylo, oy); yhi = fmax(yhi, oy);
                 } else {
-                    b = make_double4(-inf, inf, -inf, inf);
-                    break;
+                    open = true;
                 }
             }
+            if (__ballot(open) != 0) b = make_double4(-inf, inf, -inf, inf);
+            else b = make_double4(wave_min(xlo), wave_max(xhi), wave_min(ylo), wave_max(yhi));
         } else {  // GCART
             const int M = pr.nvert;
-            b.x = resolve(pr.f0) - pr.reach0;
-            b.y = resolve(pr.f0 + 1) + pr.reach0;
             double ymax = -inf, ymin = inf;
-            for (int j = 0; j < M; ++j) {
+            for (int j = lane; j < M; j += 64) {
                 ymax = fmax(ymax, resolve(pr.f0 + 2 + j));
                 ymin = fmin(ymin, resolve(pr.f0 + 2 + M + j));
             }
-            b.z = ymin - pr.reach1;
-            b.w = ymax + pr.reach1;
+            ymax = wave_max(ymax);
+            ymin = wave_min(ymin);
+            b = make_double4(r0 - pr.reach0, r1 + pr.reach0, ymin - pr.reach1, ymax + pr.reach1);
         }
-        sp.bbox[var][t] = b;
+        // the record, written by the lanes together: the primitive's dwords,
+        // then the support box and the four record fields
+        PrimRec* rec = sp.prec[var] + pi;
+        constexpr int kPrimDw = (int)(sizeof(DevPrim) / 4);
+        if (lane < kPrimDw)
+            reinterpret_cast<uint32_t*>(&rec->pr)[lane] = reinterpret_cast<const uint32_t*>(sp.prims + pi)[lane];
+        if (lane < 4) {
+            const bool rf = pr.type == SG_PRIM_BOX || pr.type == SG_PRIM_ELLIPSE;
+            const bool live = rf && (pr.type == SG_PRIM_BOX || lane < 3);
+            rec->f[lane] = live ? kv : 0.0;
+            rec->fb[lane] = live ? kb : 0.0;
+            rec->fidx[lane] = live ? kidx : -1;
+            const double bl = lane == 0 ? b.x : lane == 1 ? b.y : lane == 2 ? b.z : b.w;
+            (&rec->bb.x)[lane] = bl;
+        }
+        if (lane == 0) {
+            // outward rounding keeps the FP32 box a superset of the support
+            sp.bbox[var][pi] = make_float4(__double2float_rd(b.x), __double2float_ru(b.y), __double2float_rd(b.z),
+                                           __double2float_ru(b.w));
+        }
+        return;
     }
-    const int64_t nz = (int64_t)sp.ncomp * sp.nclass * sp.nw;
-    if (t < nz) {
-        const int w = (int)(t % sp.nw);
-        const int c = (int)((t / sp.nw) % sp.nclass);
-        const int comp = (int)(t / ((int64_t)sp.nw * sp.nclass));
-        const DevClass cl = sp.cls[c];
-        double z = 1.0, dlo = 0.0, dhi = 0.0;
-        if (cl.bounded) {
-            const double wc = sp.wc[comp][w], wwid = sp.ww[comp][w];
-            const double k = kval(cl.smode, cl.k, wwid);
-            rect_vd<S_ALL>(cl.skind, k, wc, resolve(cl.flo), resolve(cl.fhi), z, dlo, dhi);
+    const int64_t t = (int64_t)(blockIdx.x - prim_blocks) * blockDim.x + threadIdx.x;
+    if (var == 0 && sp.zero_ptr != nullptr && t < sp.zero_n) sp.zero_ptr[t] = 0.0;
+    // extrusion tables, step codes and group codes: one thread per
+    // (component, group of kGroup column steps)
+    const int ngw = (sp.nw + kGroup - 1) / kGroup;
+    if (t < (int64_t)sp.ncomp * ngw) {
+        const int g = (int)(t % ngw);
+        const int comp = (int)(t / ngw);
+        const int wb = g * kGroup;
+        const int nq = min(kGroup, sp.nw - wb);
+        double wc[kGroup], ww[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            wc[q] = sp.wc[comp][wb + min(q, nq - 1)];
+            ww[q] = sp.ww[comp][wb + min(q, nq - 1)];
         }
-        double* zt = sp.ztab[var] + 3 * t;
-        zt[0] = z;
-        zt[1] = dlo;
-        zt[2] = dhi;
+        uint32_t mask[kGroup] = {0, 0, 0, 0};
+        bool binary[kGroup] = {true, true, true, true};
+        for (int c = 0; c < sp.nclass; ++c) {
+            const DevClass cl = sp.cls[c];
+            double lo = 0.0, hi = 0.0;
+            bool wparam = false;
+            if (cl.bounded) {
+                lo = resolve(cl.flo);
+                hi = resolve(cl.fhi);
+                wparam = sp.fref[cl.flo].idx >= 0 || sp.fref[cl.fhi].idx >= 0;
+            }
+            double* zt = sp.ztab[var] + 3 * (((int64_t)comp * sp.nclass + c) * sp.nw + wb);
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                if (q >= nq) break;
+                double z = 1.0, dlo = 0.0, dhi = 0.0;
+                if (cl.bounded) rect_vd<S_ALL>(cl.skind, kval(cl.smode, cl.k, ww[q]), wc[q], lo, hi, z, dlo, dhi);
+                zt[3 * q] = z;
+                zt[3 * q + 1] = dlo;
+                zt[3 * q + 2] = dhi;
+                if (z == 1.0) mask[q] |= 1u << c;
+                else if (z != 0.0) binary[q] = false;
+                if (wparam && (dlo != 0.0 || dhi != 0.0)) binary[q] = false;
+            }
+        }
+        uint32_t gcode = 0;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) {
+            if (q >= nq) break;
+            const uint32_t code = binary[q] ? mask[q] : kCodeGeneral;
+            sp.code[var][(int64_t)comp * sp.nw + wb + q] = code;
+            if (q == 0) gcode = code;
+            else if (code != gcode) gcode = kCodeGeneral;
+        }
+        sp.gcode[var][t] = gcode;
     }
 }
 
@@ -136,14 +231,17 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Adds the wavefront sum of v (one value per lane) times the field's scale to
-// grad[field's parameter].  Called with wave-uniform control flow.
-__device__ __forceinline__ void emit(const KParams& P, int field, float v) {
-    const sg_field r = P.fref[field];
-    if (r.idx < 0) return;
+// Adds the wavefront sum of v (one value per lane) times the field's scale b
+// to grad[idx] (idx < 0: a constant field).  Called with wave-uniform control flow.
+__device__ __forceinline__ void emit_ref(const KParams& P, int idx, double b, float v) {
+    if (idx < 0) return;
     if (__ballot(v != 0.0f) == 0) return;
     const float s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) atomicAdd(P.grad + r.idx, r.b * (double)s);
+    if ((threadIdx.x & 63) == 0) atomicAdd(P.grad + idx, b * (double)s);
+}
+__device__ __forceinline__ void emit(const KParams& P, int field, float v) {
+    const sg_field r = P.fref[field];
+    emit_ref(P, r.idx, r.b, v);
 }
 
 __device__ __forceinline__ void add_field(const KParams& P, int field, float v) {
@@ -151,37 +249,52 @@ __device__ __forceinline__ void add_field(const KParams& P, int field, float v) 
     if (r.idx >= 0 && v != 0.0f) atomicAdd(P.grad + r.idx, r.b * (double)v);
 }
 
-// Appends (in primitive order) every primitive whose support box meets the
-// tile [ulo, uhi] x [vlo, vhi] to s_cand, scanning from `start` until the list
-// could overflow.  Returns the count; *next = first primitive not scanned.
-__device__ int build_list(const double4* __restrict__ bb, int nprim, int start, double ulo, double uhi,
-                          double vlo, double vhi, int* s_cand, int* s_cnt, int* next) {
+// Appends (in primitive order) every primitive in [start, start + kScan)
+// whose support box meets the tile [ulo, uhi] x [vlo, vhi] to s_cand.  The
+// kScan / kBlock support boxes of a thread are loaded together, so a pass costs
+// one memory round trip and two barriers.  Returns the count; *next = first
+// primitive not scanned.
+constexpr int kScanPer = kCandCap / kBlock;     // support boxes per thread and pass
+constexpr int kScan = kScanPer * kBlock;        // primitives per pass (never overflows s_cand)
+constexpr int kScanCnt = kScanPer * (kBlock / 64);   // s_cnt entries
+__device__ int scan_candidates(const float4* __restrict__ bb, int nprim, int start, double ulo, double uhi,
+                               double vlo, double vhi, int* s_cand, int* s_cnt, int* next) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int n = 0;
-    int base = start;
-    for (; base < nprim && n + kBlock <= kCandCap; base += kBlock) {
-        const int i = base + tid;
-        bool hit = false;
-        if (i < nprim) {
-            const double4 b = bb[i];
-            hit = (b.x <= uhi) && (b.y >= ulo) && (b.z <= vhi) && (b.w >= vlo);
-        }
-        const uint64_t m = __ballot(hit);
-        if (lane == 0) s_cnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = n, tot = 0;
+    constexpr int NW = kBlock / 64;
+    float4 box[kScanPer];
 #pragma unroll
-        for (int q = 0; q < kBlock / 64; ++q) {
-            const int cq = s_cnt[q];
-            if (q < wave) off += cq;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = start + k * kBlock + tid;
+        box[k] = bb[min(i, nprim - 1)];
+    }
+    uint64_t m[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = start + k * kBlock + tid;
+        const float4 b = box[k];
+        const bool hit = (i < nprim) && ((double)b.x <= uhi) && ((double)b.y >= ulo) && ((double)b.z <= vhi) &&
+                         ((double)b.w >= vlo);
+        m[k] = __ballot(hit);
+        if (lane == 0) s_cnt[k * NW + wave] = __popcll(m[k]);
+    }
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const int cq = s_cnt[k * NW + q];
+            if (q < wave) off += cq;   // earlier wavefronts of this k
             tot += cq;
         }
-        if (hit) s_cand[off + __popcll(m & ((1ull << lane) - 1ull))] = i;
-        n += tot;
-        __syncthreads();
+        const int i = start + k * kBlock + tid;
+        if ((m[k] >> lane) & 1ull) s_cand[off + __popcll(m[k] & ((1ull << lane) - 1ull))] = i;
+        // the next k starts after every hit of this k
+        for (int q = wave; q < NW; ++q) off += s_cnt[k * NW + q];
     }
-    *next = base;
-    return n;
+    __syncthreads();
+    *next = start + kScan;
+    return tot;
 }
 
 struct Tile {
@@ -190,7 +303,7 @@ struct Tile {
     bool wave_live;
 };
 
-__device__ __forceinline__ bool wave_meets(const Tile& T, const double4 b) {
+__device__ __forceinline__ bool wave_meets(const Tile& T, const double4& b) {
     return (b.x <= T.wuhi) && (b.y >= T.wulo) && (b.z <= T.wvhi) && (b.w >= T.wvlo);
 }
 
@@ -201,27 +314,75 @@ __device__ __forceinline__ void add_to_class(double (&F)[NC], int cls, double v)
         if (c == cls) F[c] += v;
 }
 
-// Sum of F_h over the candidates, per class, at (uc, vc).
+constexpr int kStageRec = 32;   // candidate records staged in LDS per round
+
+// Copies the records of candidates s_cand[j0, j0 + n) (n <= kStageRec) to
+// s_rec, one thread per candidate; barriers before (earlier readers) and after.
+__device__ __forceinline__ void stage_cands(const PrimRec* __restrict__ prec, const int* s_cand, int j0, int n,
+                                            PrimRec* s_rec) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < n) s_rec[t] = prec[s_cand[j0 + t]];
+    __syncthreads();
+}
+
+// In-plane factor F(u, v) of a staged candidate (value only).
+template <int TYPES, int SIGS>
+__device__ __forceinline__ double cand_value(const PrimRec& c, const double* __restrict__ fv,
+                                             const double* __restrict__ cst, double uc, double uw, double vc,
+                                             double vw) {
+    const DevPrim& pr = c.pr;
+    if constexpr ((TYPES & T_BOX) != 0) {
+        if (TYPES == T_BOX || pr.type == SG_PRIM_BOX) {
+            double f = 1.0;
+            if (pr.ubnd) f = rect_v<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, c.f[0], c.f[1]);
+            if (pr.vbnd) f *= rect_v<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, vw), vc, c.f[2], c.f[3]);
+            return f;
+        }
+    }
+    if constexpr ((TYPES & T_ELL) != 0) {
+        if (pr.type == SG_PRIM_ELLIPSE) {
+            const double dx = (uc - c.f[0]) * pr.iax, dy = (vc - c.f[1]) * pr.iay;
+            const double rho2 = dx * dx + dy * dy;
+            const double r = c.f[2];
+            const double rhi = r + pr.reach0, rlo = r - pr.reach0;
+            if (rhi <= 0.0 || rho2 >= rhi * rhi) return 0.0;      // beyond the sigma support
+            if (rlo > 0.0 && rho2 <= rlo * rlo) return 1.0;
+            return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
+        }
+    }
+    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0) return prim_value<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, cst, uc, uw, vc, vw);
+    return 0.0;
+}
+
+// Sum of F_h over the candidates, per class, at (uc, vc).  When every
+// candidate of the tile fits one staging round, the records stay in s_rec for
+// the partials (*staged_all; *ncand of them).
 template <int NC, int TYPES, int SIGS>
-__device__ void inplane_sums(const KParams& P, const double4* __restrict__ bbox, const double* __restrict__ fval,
-                             const Tile& T, double uc, double uw, double vc, double vw, int* s_cand, int* s_cnt,
-                             double (&F)[NC], int& nlist, bool& complete) {
+__device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __restrict__ bbox, const PrimRec* __restrict__ prec,
+                             const double* __restrict__ fval, const Tile& T, double uc, double uw, double vc,
+                             double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC], int& ncand,
+                             bool& staged_all) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) F[c] = 0.0;
-    int next = 0;
-    bool first = true;
-    while (first || next < P.nprim) {
-        if (!first) __syncthreads();
-        const int n = build_list(bbox, P.nprim, next, T.ulo, T.uhi, T.vlo, T.vhi, s_cand, s_cnt, &next);
-        if (first) { complete = next >= P.nprim; nlist = n; }
-        first = false;
-        if (!T.wave_live) continue;
-        for (int j = 0; j < n; ++j) {
-            const int pi = uniform_int(s_cand[j]);
-            if (!wave_meets(T, bbox[pi])) continue;
-            const DevPrim pr = P.prims[pi];
-            const double f = prim_value<TYPES, SIGS>(pr, fval, P.consts, uc, uw, vc, vw);
-            add_to_class(F, pr.cls, f);
+    ncand = 0;
+    staged_all = false;
+    for (int next = 0; next < P.nprim;) {
+        const bool first = next == 0;
+        const int n = scan_candidates(bbox, P.nprim, next, T.ulo, T.uhi, T.vlo, T.vhi, s_cand, s_cnt, &next);
+        if (first && next >= P.nprim && n <= kStageRec) {
+            staged_all = true;
+            ncand = n;
+        }
+        for (int j0 = 0; j0 < n; j0 += kStageRec) {
+            const int nj = min(kStageRec, n - j0);
+            stage_cands(prec, s_cand, j0, nj, s_rec);
+            if (!T.wave_live) continue;
+            for (int j = 0; j < nj; ++j) {
+                if (!wave_meets(T, s_rec[j].bb)) continue;
+                const double f = cand_value<TYPES, SIGS>(s_rec[j], fval, P.consts, uc, uw, vc, vw);
+                add_to_class(F, s_rec[j].pr.cls, f);
+            }
         }
     }
 }
@@ -244,32 +405,32 @@ __device__ __forceinline__ void group_op(const KParams& P, int g, double S, doub
     }
 }
 
-// zs points at the class-0 entry of this column step; class c sits zstride further.
+// Extrusion factors of a step on which every class factor is exactly 0 or 1:
+// bit c of mask set <=> Z_c = 1.
+template <int NC>
+__device__ __forceinline__ void mask_z(uint32_t mask, double (&Z)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) Z[c] = ((mask >> c) & 1u) ? 1.0 : 0.0;
+}
+
 template <int TREE>
-__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree_nc(TREE)], const double* zs,
-                                        int zstride, double (&Z)[tree_nc(TREE)]) {
+__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree_nc(TREE)],
+                                        const double (&Z)[tree_nc(TREE)]) {
     constexpr int NC = tree_nc(TREE);
     Comp o;
     if constexpr (TREE == TR_U1 || TREE == TR_U2) {
         double S = 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            Z[c] = zs[c * zstride];
-            S += F[c] * Z[c];
-        }
+        for (int c = 0; c < NC; ++c) S += F[c] * Z[c];
         o.s = fmin(1.0, S);
         o.r0 = S < 1.0 ? 1.0 : 0.0;
         o.r1 = o.r2 = o.r3 = 0.0;
         return o;
     } else if constexpr (TREE == TR_D11 || TREE == TR_D12) {
-        Z[0] = zs[0];
         const double S0 = F[0] * Z[0];
         double S1 = 0.0;
 #pragma unroll
-        for (int c = 1; c < NC; ++c) {
-            Z[c] = zs[c * zstride];
-            S1 += F[c] * Z[c];
-        }
+        for (int c = 1; c < NC; ++c) S1 += F[c] * Z[c];
         const double v0 = fmin(1.0, S0), v1 = fmin(1.0, S1);
         const double d = v0 - v1;
         o.s = fmax(0.0, d);
@@ -283,15 +444,12 @@ __device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (c < P.nclass) {
-                Z[c] = zs[c * zstride];
                 const double t = F[c] * Z[c];
                 const int g = P.cls_group[c];
                 if (g == 0) S0 += t;
                 else if (g == 1) S1 += t;
                 else if (g == 2) S2 += t;
                 else S3 += t;
-            } else {
-                Z[c] = 0.0;
             }
         }
         double v0, v1 = 0.0, v2 = 0.0, v3 = 0.0, m0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
@@ -330,10 +488,20 @@ __device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree
 }
 
 
+// Coordinates of the kBlock samples of a tile in LDS, [4][kBlock]: centers and
+// widths along u, then along v.
+struct SampleLat {
+    const double* p;
+    __device__ double uc(int t) const { return p[t]; }
+    __device__ double uw(int t) const { return p[kBlock + t]; }
+    __device__ double vc(int t) const { return p[2 * kBlock + t]; }
+    __device__ double vw(int t) const { return p[3 * kBlock + t]; }
+};
+
 // Partials of a convex polygon at one sample, times a; one reduction per
 // vertex field and edge.
 template <int SIGS>
-__device__ void poly_partials(const KParams& P, const DevPrim& pr, double ad, double uc, double vc) {
+__device__ __forceinline__ void poly_partials(const KParams& P, const DevPrim& pr, double ad, double uc, double vc) {
     const double* fv = P.fval;
     const int N = pr.nvert;
     const double* xs = fv + pr.f0;
@@ -377,11 +545,10 @@ __device__ void poly_partials(const KParams& P, const DevPrim& pr, double ad, do
 constexpr int kSegBucket = 256;
 
 template <int SIGS>
-__device__ void gcart_partials(const KParams& P, const DevPrim& pr, const float* sAc, int u0, int v0, int comp,
+__device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& pr, const float* sAc, const SampleLat& L,
                                const Tile& T, float* sg) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
-    const int TU = P.tu;
     const double* fv = P.fval;
     const int M = pr.nvert;
     const double* xv = P.consts + pr.c0;
@@ -398,20 +565,20 @@ __device__ void gcart_partials(const KParams& P, const DevPrim& pr, const float*
         __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0): the zeros are in LDS
         __builtin_amdgcn_wave_barrier();
     }
+    const double xs0 = fv[pr.f0], xs1 = fv[pr.f0 + 1];
     double sxs = 0.0, sxe = 0.0;
 #pragma unroll 1
     for (int q = 0; q < Q; ++q) {
         const int t = q * 64 + lane;
         const float a = sAc[t];
         if (__ballot(a != 0.0f) == 0) continue;
-        const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
-        const double uc = P.uc[comp][uq], uw = P.uw[comp][uq], vc = P.vc[comp][vq], vw = P.vw[comp][vq];
+        const double uc = L.uc(t), uw = L.uw(t), vc = L.vc(t), vw = L.vw(t);
         const double ad = (double)a;
         float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, c3 = 0.0f;
         int j = 0;
         if (a != 0.0f) {
             double rx, drx0, drx1;
-            rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1], rx, drx0, drx1);
+            rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, xs0, xs1, rx, drx0, drx1);
             double t01;
             gcart_segment(xv, M, uc, j, t01);
             const double fp = (1.0 - t01) * yp[j] + t01 * yp[j + 1];
@@ -473,30 +640,25 @@ __device__ void gcart_partials(const KParams& P, const DevPrim& pr, const float*
 // class column sums sAc[sample], summed over the lane's samples, reduced over
 // the wavefront, and added with one atomic per parameter field.
 template <int TYPES, int SIGS>
-__device__ void block_partials(const KParams& P, const DevPrim& pr, const float* sAc, int u0, int v0, int comp,
+__device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& cr, const float* sAc, const SampleLat& L,
                                const Tile& T, float* sg) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
-    const int TU = P.tu;
-    const double* fv = P.fval;
+    const DevPrim& pr = cr.pr;
     const int type = (TYPES == T_BOX) ? SG_PRIM_BOX : pr.type;
     if constexpr ((TYPES & T_BOX) != 0) {
         if (type == SG_PRIM_BOX) {
+            const double u0 = cr.f[0], u1 = cr.f[1], v0 = cr.f[2], v1 = cr.f[3];
             double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int t = q * 64 + lane;
                 const float a = sAc[t];
                 if (a != 0.0f) {
-                    const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
                     const double ad = (double)a;
                     double ru = 1.0, du0 = 0.0, du1 = 0.0, rv = 1.0, dv0 = 0.0, dv1 = 0.0;
-                    if (pr.ubnd)
-                        rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, P.uw[comp][uq]), P.uc[comp][uq], fv[pr.fu0],
-                                      fv[pr.fu1], ru, du0, du1);
-                    if (pr.vbnd)
-                        rect_vd<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, P.vw[comp][vq]), P.vc[comp][vq], fv[pr.fv0],
-                                      fv[pr.fv1], rv, dv0, dv1);
+                    if (pr.ubnd) rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, L.uw(t)), L.uc(t), u0, u1, ru, du0, du1);
+                    if (pr.vbnd) rect_vd<SIGS>(pr.sk1, kval(pr.sm1, pr.k1, L.vw(t)), L.vc(t), v0, v1, rv, dv0, dv1);
                     s0 += ad * du0 * rv;
                     s1 += ad * du1 * rv;
                     s2 += ad * ru * dv0;
@@ -504,28 +666,27 @@ __device__ void block_partials(const KParams& P, const DevPrim& pr, const float*
                 }
             }
             if (pr.ubnd) {
-                emit(P, pr.fu0, (float)s0);
-                emit(P, pr.fu1, (float)s1);
+                emit_ref(P, cr.fidx[0], cr.fb[0], (float)s0);
+                emit_ref(P, cr.fidx[1], cr.fb[1], (float)s1);
             }
             if (pr.vbnd) {
-                emit(P, pr.fv0, (float)s2);
-                emit(P, pr.fv1, (float)s3);
+                emit_ref(P, cr.fidx[2], cr.fb[2], (float)s2);
+                emit_ref(P, cr.fidx[3], cr.fb[3], (float)s3);
             }
             return;
         }
     }
     if constexpr ((TYPES & T_ELL) != 0) {
         if (type == SG_PRIM_ELLIPSE) {
-            const double x0 = fv[pr.f0], y0 = fv[pr.f0 + 1], r = fv[pr.f0 + 2];
+            const double x0 = cr.f[0], y0 = cr.f[1], r = cr.f[2];
             const double rhi = r + pr.reach0, rlo = r - pr.reach0;
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int q = 0; q < Q; ++q) {
                 const int t = q * 64 + lane;
                 const float a = sAc[t];
                 if (a != 0.0f) {
-                    const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
-                    const double qx = (P.uc[comp][uq] - x0) * pr.iax, qy = (P.vc[comp][vq] - y0) * pr.iay;
+                    const double qx = (L.uc(t) - x0) * pr.iax, qy = (L.vc(t) - y0) * pr.iay;
                     const double rho2 = qx * qx + qy * qy;
                     if (rhi > 0.0 && rho2 < rhi * rhi && !(rlo > 0.0 && rho2 <= rlo * rlo)) {
                         // derivatives only: FP32 after the FP64 differences
@@ -540,9 +701,9 @@ __device__ void block_partials(const KParams& P, const DevPrim& pr, const float*
                     }
                 }
             }
-            emit(P, pr.f0, (float)s0);
-            emit(P, pr.f0 + 1, (float)s1);
-            emit(P, pr.f0 + 2, (float)s2);
+            emit_ref(P, cr.fidx[0], cr.fb[0], (float)s0);
+            emit_ref(P, cr.fidx[1], cr.fb[1], (float)s1);
+            emit_ref(P, cr.fidx[2], cr.fb[2], (float)s2);
             return;
         }
     }
@@ -553,250 +714,404 @@ __device__ void block_partials(const KParams& P, const DevPrim& pr, const float*
                 const int t = q * 64 + lane;
                 const float a = sAc[t];
                 if (__ballot(a != 0.0f) == 0) continue;
-                const int uq = min(u0 + (t & (TU - 1)), P.nu - 1), vq = min(v0 + t / TU, P.nv - 1);
-                poly_partials<SIGS>(P, pr, (double)a, P.uc[comp][uq], P.vc[comp][vq]);
+                poly_partials<SIGS>(P, pr, (double)a, L.uc(t), L.vc(t));
             }
             return;
         }
     }
     if constexpr ((TYPES & T_GCART) != 0) {
         if (type == SG_PRIM_GCART) {
-            gcart_partials<SIGS>(P, pr, sAc, u0, v0, comp, T, sg);
+            gcart_partials<SIGS>(P, pr, sAc, L, T, sg);
             return;
         }
     }
 }
 
-// ------------------------------------------------------------------ column kernel
-template <int MODE, int TREE, int TYPES, int SIGS>
-__device__ __forceinline__ void column_body(const KParams& P, int b) {
-    constexpr int NC = tree_nc(TREE);
-    __shared__ int s_cand[kCandCap];
-    __shared__ int s_cnt[kBlock / 64];
-    const int tid = threadIdx.x, wave = tid >> 6;
+// ------------------------------------------------------------------ tiles
+// In-plane tile of a block: kBlock samples, tu x tv, and its wavefronts' sub-tiles.
+struct TileGeom {
+    int comp, u, v, uu, vv;
+    bool act;
+    double uc, uw, vc, vw;
+    Tile T;
+};
 
-    const int seg = b % P.nseg;
-    b /= P.nseg;
+__device__ __forceinline__ TileGeom tile_geom(const KParams& P, int b) {
+    const int tid = threadIdx.x, wave = tid >> 6;
+    TileGeom G;
     const int tvi = b % P.tiles_v;
     b /= P.tiles_v;
     const int tui = b % P.tiles_u;
-    const int comp = b / P.tiles_u;
-
+    G.comp = b / P.tiles_u;
     const int TU = P.tu;
-    const int lu = tid & (TU - 1), lv = tid / TU;
-    const int u = tui * TU + lu, v = tvi * P.tv + lv;
-    const bool act = (u < P.nu) && (v < P.nv);
-    const int uu = min(u, P.nu - 1), vv = min(v, P.nv - 1);
-    const double* __restrict__ ucs = P.uc[comp];
-    const double* __restrict__ vcs = P.vc[comp];
-    const double uc = ucs[uu], uw = P.uw[comp][uu];
-    const double vc = vcs[vv], vw = P.vw[comp][vv];
-
-    Tile T;
-    {
-        const int u0 = tui * TU, u1 = min(u0 + TU, P.nu) - 1;
-        const int v0 = tvi * P.tv, v1 = min(v0 + P.tv, P.nv) - 1;
-        T.ulo = ucs[u0];
-        T.uhi = ucs[u1];
-        T.vlo = vcs[v0];
-        T.vhi = vcs[v1];
-        int wu0, wu1, wv0, wv1;
-        if (TU <= 64) {
-            wu0 = u0;
-            wu1 = u1;
-            wv0 = v0 + wave * (64 / TU);
-            wv1 = min(wv0 + 64 / TU, P.nv) - 1;
-        } else {
-            wu0 = u0 + (wave * 64) % TU;
-            wu1 = min(wu0 + 64, P.nu) - 1;
-            wv0 = wv1 = v0 + (wave * 64) / TU;
-        }
-        T.wave_live = (wu0 < P.nu) && (wv0 < P.nv);
-        T.wulo = ucs[min(wu0, P.nu - 1)];
-        T.wuhi = ucs[max(0, min(wu1, P.nu - 1))];
-        T.wvlo = vcs[min(wv0, P.nv - 1)];
-        T.wvhi = vcs[max(0, min(wv1, P.nv - 1))];
+    G.u = tui * TU + (tid & (TU - 1));
+    G.v = tvi * P.tv + tid / TU;
+    G.act = (G.u < P.nu) && (G.v < P.nv);
+    G.uu = min(G.u, P.nu - 1);
+    G.vv = min(G.v, P.nv - 1);
+    const double* __restrict__ ucs = P.uc[G.comp];
+    const double* __restrict__ vcs = P.vc[G.comp];
+    G.uc = ucs[G.uu];
+    G.uw = P.uw[G.comp][G.uu];
+    G.vc = vcs[G.vv];
+    G.vw = P.vw[G.comp][G.vv];
+    const int u0 = tui * TU, u1 = min(u0 + TU, P.nu) - 1;
+    const int v0 = tvi * P.tv, v1 = min(v0 + P.tv, P.nv) - 1;
+    Tile& T = G.T;
+    T.ulo = ucs[u0];
+    T.uhi = ucs[u1];
+    T.vlo = vcs[v0];
+    T.vhi = vcs[v1];
+    int wu0, wu1, wv0, wv1;
+    if (TU <= 64) {
+        wu0 = u0;
+        wu1 = u1;
+        wv0 = v0 + wave * (64 / TU);
+        wv1 = min(wv0 + 64 / TU, P.nv) - 1;
+    } else {
+        wu0 = u0 + (wave * 64) % TU;
+        wu1 = min(wu0 + 64, P.nu) - 1;
+        wv0 = wv1 = v0 + (wave * 64) / TU;
     }
+    T.wave_live = (wu0 < P.nu) && (wv0 < P.nv);
+    T.wulo = ucs[min(wu0, P.nu - 1)];
+    T.wuhi = ucs[max(0, min(wu1, P.nu - 1))];
+    T.wvlo = vcs[min(wv0, P.nv - 1)];
+    T.wvhi = vcs[max(0, min(wv1, P.nv - 1))];
+    return G;
+}
 
-    // Column steps [w0, w1).  Field loads are double-buffered in two register
-    // sets of U steps each: while one group is being composed the next one is
-    // in flight.  The first group goes out before the in-plane pass.
+// ------------------------------------------------------------------ column kernel
+// Tables every wavefront reads at the same address (step and group codes,
+// extrusion tables) are read through the constant address space, which lets
+// the compiler use scalar loads: they neither occupy vector registers nor wait
+// behind the field loads.
+typedef __attribute__((address_space(4))) const uint32_t* ConstU32;
+typedef __attribute__((address_space(4))) const double* ConstF64;
+template <class T>
+__device__ __forceinline__ T const_space(const void* p) {
+    return (T)(uintptr_t)p;
+}
+
+// Raw buffer resource over [base, base + bytes) (bytes clamped to 32 bits;
+// reads past the end return 0).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int64_t bytes) {
+    const int32_t n = bytes <= 0 ? 0 : (bytes >= 0xFFFFFFFFll ? (int32_t)0xFFFFFFFF : (int32_t)(uint32_t)bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
+}
+
+// One block = one in-plane tile of kBlock samples (tu x tv) of one component
+// and one segment [w0, w1) of the column (w0 a multiple of kGroup); one thread
+// per sample.
+//  1. The first set of field loads goes out; the candidate primitives of the
+//     tile are listed and their records staged in LDS; each thread sums the
+//     in-plane factors per extrusion class, F_c (FP64).
+//  2. The column is streamed.  On a "binary" step every class factor Z_c(w)
+//     is exactly 0 or 1 (and the w-bound derivatives of classes with
+//     column-axis parameters vanish): its composition depends only on F and
+//     on the mask of classes at 1.  Along a run of equal masks the column sums
+//     A_c = sum_w g(w) d eps/d s_c Z_c(w) therefore factor into (d eps/d s_c
+//     at that mask) x (sum of g over the run), and eps is one value per run.
+//     Other steps are composed one by one.  Groups of kGroup binary steps with
+//     one mask take a path with no per-step decisions.
+//  3. (VJP) A_c goes to LDS and the candidates are split over the wavefronts:
+//     in-plane partials times A_c over the tile's samples, reduced over the
+//     wavefront, one FP64 atomic per (wavefront, parameter field).
+template <int MODE, int TREE, int TYPES, int SIGS>
+__device__ __forceinline__ void column_body(const KParams& P, int b) {
+    constexpr int NC = tree_nc(TREE);
+    constexpr bool VJP = (MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
+    constexpr int U = (MODE == MODE_VJP_GEPS) ? 8 : 4;      // steps per load set (multiple of kGroup)
+    constexpr int NG = U / kGroup;
+    constexpr int EB = (MODE == MODE_VJP_FIELDS) ? 8 : 4;    // bytes per sample of the streamed planes
+    __shared__ int s_cand[kCandCap];
+    __shared__ int s_cnt[kScanCnt];
+    __shared__ PrimRec s_rec[kStageRec];
+    __shared__ float sA[VJP ? NC * kBlock : 1];
+    __shared__ double s_lat[VJP ? 4 * kBlock : 1];
+    __shared__ float sG[(VJP && (TYPES & T_GCART)) ? (kBlock / 64) * 2 * kSegBucket : 1];
+    const int tid = threadIdx.x, wave = tid >> 6;
+
+    const int seg = b % P.nseg;
+    const TileGeom G = tile_geom(P, b / P.nseg);
+    const int comp = G.comp;
+    const bool act = G.act;
     const int w0 = seg * P.seglen;
     const int w1 = min(w0 + P.seglen, P.nw);
-    const int64_t b0 = (int64_t)uu + (int64_t)vv * P.sv;     // offset within a component plane
-    constexpr bool VJP = (MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
-    constexpr int U = (MODE == MODE_VJP_GEPS) ? 8 : 4;
-    const float2* __restrict__ efp = nullptr;
-    const float2* __restrict__ eap = nullptr;
-    const float* __restrict__ gep = nullptr;
+    const int64_t b0 = (int64_t)G.uu + (int64_t)G.vv * P.sv;     // offset within a column plane
+    const uint32_t lane_off = (uint32_t)b0 * EB;
+    const int64_t plane_bytes = P.plane * EB;
+    const int64_t step_bytes = P.sw * EB;
+    const int ngw = (P.nw + kGroup - 1) / kGroup;
+    const ConstU32 gcode = const_space<ConstU32>(P.gcode + (int64_t)comp * ngw);
+    const ConstU32 gcode2 = const_space<ConstU32>(P.gcode2 + (int64_t)comp * ngw);
+    const ConstU32 code = const_space<ConstU32>(P.code + (int64_t)comp * P.nw);
+    const ConstU32 code2 = const_space<ConstU32>(P.code2 + (int64_t)comp * P.nw);
+    const int64_t zcomp = (int64_t)comp * P.nclass * P.nw * 3;
+    const ConstF64 ztab = const_space<ConstF64>(P.ztab + zcomp);
+    const ConstF64 ztab2 = const_space<ConstF64>(P.ztab2 + zcomp);
+
+    // combined code of a group / step (both evaluations for MODE_FD)
+    auto combine = [&](uint32_t c0, uint32_t c1) -> uint32_t {
+        if constexpr (MODE == MODE_FD)
+            return ((c0 | c1) & kCodeGeneral) ? kCodeGeneral : ((c0 & 0xFFu) | ((c1 & 0xFFu) << 8));
+        else
+            return c0;
+    };
+    auto group_code = [&](int w) -> uint32_t {
+        const int gi = min(w / kGroup, ngw - 1);
+        return combine(gcode[gi], (MODE == MODE_FD) ? gcode2[gi] : 0u);
+    };
+    auto step_code = [&](int w) -> uint32_t { return combine(code[w], (MODE == MODE_FD) ? code2[w] : 0u); };
+    auto load_zt = [&](ConstF64 zt, int w, double (&Z)[NC]) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Z[c] = (c < P.nclass) ? zt[3 * ((int64_t)c * P.nw + w)] : 0.0;
+    };
+
+    // Field loads: two register sets of U steps each, double-buffered.  The
+    // buffer resource of a set starts at its first step, so every load of the
+    // set is (lane offset, immediate step offset).
+    const char* plane0 = nullptr;
+    const char* plane1 = nullptr;
     if constexpr (MODE == MODE_VJP_FIELDS) {
-        efp = P.ef[comp] + b0;
-        eap = P.ea[comp] + b0;
+        plane0 = reinterpret_cast<const char*>(P.ef[comp]);
+        plane1 = reinterpret_cast<const char*>(P.ea[comp]);
     } else if constexpr (MODE == MODE_VJP_GEPS) {
-        gep = P.geps + (int64_t)comp * P.plane + b0;
+        plane0 = reinterpret_cast<const char*>(P.geps + (int64_t)comp * P.plane);
     }
+    typedef float v2f __attribute__((ext_vector_type(2)));
     struct Set {
-        float2 e[U], a[U];
+        v2f e[U], a[U];
         float g[U];
+        uint32_t gc[NG];
     };
     Set sa, sb;
     auto load_set = [&](Set& st, int w) {
+        const int64_t off = (int64_t)w * step_bytes;
+        if constexpr (MODE == MODE_VJP_FIELDS) {
+            const __amdgpu_buffer_rsrc_t re = buffer_rsrc(plane0 + off, plane_bytes - off);
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(plane1 + off, plane_bytes - off);
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int64_t off = (int64_t)min(w + q, w1 - 1) * P.sw;
-            if constexpr (MODE == MODE_VJP_FIELDS) {
-                st.e[q] = efp[off];
-                st.a[q] = eap[off];
-            } else if constexpr (MODE == MODE_VJP_GEPS) {
-                st.g[q] = gep[off];
+            for (int q = 0; q < U; ++q) {
+                st.e[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(re, lane_off,
+                                                                                      (int)(q * step_bytes), 0));
+                st.a[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(ra, lane_off,
+                                                                                      (int)(q * step_bytes), 0));
             }
+        } else if constexpr (MODE == MODE_VJP_GEPS) {
+            const __amdgpu_buffer_rsrc_t rg = buffer_rsrc(plane0 + off, plane_bytes - off);
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                st.g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, lane_off,
+                                                                                        (int)(q * step_bytes), 0));
         }
+#pragma unroll
+        for (int h = 0; h < NG; ++h) st.gc[h] = group_code(w + h * kGroup);
     };
-    if constexpr (VJP) load_set(sa, w0);
+    if constexpr (VJP) load_set(sa, w0);   // every segment holds at least one step
 
-    double F[NC];
-    int nlist;
-    bool complete;
-    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.fval, T, uc, uw, vc, vw, s_cand, s_cnt, F, nlist, complete);
-    double F2[NC];
+    // ---- 1. in-plane sums
+    double F[NC], F2[NC];
+    int ncand = 0;
+    bool staged_all = false;
+    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.prec, P.fval, G.T, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt, s_rec, F,
+                                  ncand, staged_all);
     if constexpr (MODE == MODE_FD) {
-        int nl2;
-        bool c2;
-        __syncthreads();
-        inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.fval2, T, uc, uw, vc, vw, s_cand, s_cnt, F2, nl2, c2);
+        int nc2;
+        bool sa2;
+        inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.prec2, P.fval2, G.T, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt,
+                                      s_rec, F2, nc2, sa2);
     }
 
-    // LDS copy of the extrusion tables of this column range, CH steps at a time
-    constexpr int NT = (MODE == MODE_FD) ? 2 : 1;
-    constexpr int CH = ((kZStage / NT / NC) / (2 * U)) * (2 * U);
-    __shared__ double sZ[NT * NC * CH];
-    __shared__ float2 sZd[VJP ? NC * CH : 1];
-    const int64_t zcomp = (int64_t)comp * P.nclass * P.nw * 3;
-    auto stage_z = [&](int wc) {
-        __syncthreads();
-        const int len = min(CH, w1 - wc);
-        const int tot = NT * P.nclass * len;
-        for (int i = tid; i < tot; i += kBlock) {
-            const int tb = i / (P.nclass * len), r = i - tb * (P.nclass * len);
-            const int c = r / len, j = r - c * len;
-            const double* z = (tb == 0 ? P.ztab : P.ztab2) + zcomp + 3 * ((int64_t)c * P.nw + wc + j);
-            sZ[(tb * NC + c) * CH + j] = z[0];
-            if constexpr (VJP) sZd[c * CH + j] = make_float2((float)z[1], (float)z[2]);
-        }
-        __syncthreads();
-    };
-
-    float A[NC], Blo[NC], Bhi[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) A[c] = Blo[c] = Bhi[c] = 0.0f;
-
+    // ---- 2. the column
     if constexpr (MODE == MODE_EPS || MODE == MODE_FD) {
-        float* __restrict__ outp = P.out + (int64_t)comp * P.plane + b0;
-        for (int wc = w0; wc < w1; wc += CH) {
-            stage_z(wc);
-            const int we = min(wc + CH, w1);
-#pragma unroll 2
-            for (int w = wc; w < we; ++w) {
-                double Z[NC];
-                const double s = compose<TREE>(P, F, sZ + (w - wc), CH, Z).s;
-                float out;
-                if constexpr (MODE == MODE_EPS) {
-                    out = (float)(P.eps_bg + P.deps * s);
-                } else {
-                    const double s2 = compose<TREE>(P, F2, sZ + NC * CH + (w - wc), CH, Z).s;
-                    out = (float)(P.deps * (s - s2));
+        auto value = [&](const double (&Z)[NC], const double (&Z2)[NC]) -> float {
+            const double s = compose<TREE>(P, F, Z).s;
+            if constexpr (MODE == MODE_EPS) {
+                return (float)(P.eps_bg + P.deps * s);
+            } else {
+                const double s2 = compose<TREE>(P, F2, Z2).s;
+                return (float)(P.deps * (s - s2));
+            }
+        };
+        const char* outb = reinterpret_cast<const char*>(P.out + (int64_t)comp * P.plane);
+        const int64_t out_bytes = P.plane * 4;
+        const int64_t out_step = P.sw * 4;
+        const uint32_t out_lane = (uint32_t)b0 * 4;
+        uint32_t cur = 0xFFFFFFFFu;    // mask of the current run (none yet)
+        float run_out = 0.0f;
+        for (int w = w0; w < w1; w += kGroup) {
+            const int64_t off = (int64_t)w * out_step;
+            const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(outb + off, out_bytes - off);
+            const uint32_t gc = group_code(w);
+            float out[kGroup];
+            if (!(gc & kCodeGeneral) && w + kGroup <= w1) {
+                if (gc != cur) {
+                    double Z[NC], Z2[NC];
+                    mask_z<NC>(gc & 0xFFu, Z);
+                    if constexpr (MODE == MODE_FD) mask_z<NC>((gc >> 8) & 0xFFu, Z2);
+                    run_out = value(Z, Z2);
+                    cur = gc;
                 }
-                if (act) outp[(int64_t)w * P.sw] = out;
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) out[q] = run_out;
+            } else {
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    out[q] = 0.0f;
+                    if (w + q < w1) {
+                        const uint32_t c = step_code(w + q);
+                        if (c & kCodeGeneral) {
+                            double Z[NC], Z2[NC];
+                            load_zt(ztab, w + q, Z);
+                            if constexpr (MODE == MODE_FD) load_zt(ztab2, w + q, Z2);
+                            out[q] = value(Z, Z2);
+                        } else {
+                            if (c != cur) {
+                                double Z[NC], Z2[NC];
+                                mask_z<NC>(c & 0xFFu, Z);
+                                if constexpr (MODE == MODE_FD) mask_z<NC>((c >> 8) & 0xFFu, Z2);
+                                run_out = value(Z, Z2);
+                                cur = c;
+                            }
+                            out[q] = run_out;
+                        }
+                    }
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q)
+                    if (w + q < w1)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[q]), ro, out_lane,
+                                                              (int)(q * out_step), 0);
             }
         }
         return;
     } else {
-        int wc = w0;   // first step of the staged chunk
+        float A[NC], Blo[NC], Bhi[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) A[c] = Blo[c] = Bhi[c] = 0.0f;
+        // g of one step times gscale is d F / d eps at that sample, times deps
+        const float gscale = ((MODE == MODE_VJP_FIELDS) ? P.two_omega : 1.0f) * (float)P.deps;
+        // A_c += gd * r_(group of c) * Z_c (and the w-bound partials on general steps)
+        auto accumulate = [&](const Comp& o, const double (&Z)[NC], float gd, int w, bool general) {
+            const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
+            const float cg2 = gd * (float)o.r2, cg3 = gd * (float)o.r3;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c < P.nclass) {
+                    constexpr int fixed = tree_group(TREE, 0) >= 0;
+                    const int g = fixed ? tree_group(TREE, c) : P.cls_group[c];
+                    const float cc = (g == 0) ? cg0 : (g == 1) ? cg1 : (g == 2) ? cg2 : cg3;
+                    A[c] += cc * (float)Z[c];
+                    if (general && P.cls_wparam[c]) {
+                        const int64_t zi = 3 * ((int64_t)c * P.nw + w);
+                        Blo[c] += cc * (float)ztab[zi + 1];
+                        Bhi[c] += cc * (float)ztab[zi + 2];
+                    }
+                }
+            }
+        };
+        uint32_t cur = 0;     // mask of the current run of binary steps
+        float grun = 0.0f;    // sum of g over that run
+        auto flush = [&]() {
+            if (cur != 0u) {
+                double Z[NC];
+                mask_z<NC>(cur, Z);
+                accumulate(compose<TREE>(P, F, Z), Z, grun * gscale, 0, false);
+            }
+            grun = 0.0f;
+        };
         auto process = [&](const Set& st, int w) {
-            if ((w - w0) % CH == 0) {
-                wc = w;
-                stage_z(w);
-            }
-            float gs[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                if constexpr (MODE == MODE_VJP_FIELDS)
-                    gs[q] = P.two_omega * (st.e[q].x * st.a[q].y + st.e[q].y * st.a[q].x);   // 2 omega Im(E Eadj)
-                else
-                    gs[q] = st.g[q];
-                if (!act || w + q >= w1) gs[q] = 0.0f;
-            }
+            for (int h = 0; h < NG; ++h) {
+                const int wg = w + h * kGroup;
+                if (wg >= w1) break;
+                float g[kGroup];
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                if (w + q < w1) {
-                    const int j = w + q - wc;
-                    double Z[NC];
-                    const Comp o = compose<TREE>(P, F, sZ + j, CH, Z);
-                    const float gd = gs[q] * (float)P.deps;
-                    const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
-                    const float cg2 = gd * (float)o.r2, cg3 = gd * (float)o.r3;
+                for (int q = 0; q < kGroup; ++q) {
+                    const int i = h * kGroup + q;
+                    if constexpr (MODE == MODE_VJP_FIELDS)
+                        g[q] = st.e[i].x * st.a[i].y + st.e[i].y * st.a[i].x;   // Im(E Eadj)
+                    else
+                        g[q] = st.g[i];
+                }
+                const uint32_t gc = st.gc[h];
+                if (!(gc & kCodeGeneral) && wg + kGroup <= w1) {
+                    if (gc != cur) {
+                        flush();
+                        cur = gc;
+                    }
+                    grun += (g[0] + g[1]) + (g[2] + g[3]);
+                } else {
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        if (c < P.nclass) {
-                            constexpr int fixed = tree_group(TREE, 0) >= 0;
-                            const int g = fixed ? tree_group(TREE, c) : P.cls_group[c];
-                            const float cc = (g == 0) ? cg0 : (g == 1) ? cg1 : (g == 2) ? cg2 : cg3;
-                            A[c] += cc * (float)Z[c];
-                            if (P.cls_wparam[c]) {
-                                const float2 zd = sZd[c * CH + j];
-                                Blo[c] += cc * zd.x;
-                                Bhi[c] += cc * zd.y;
+                    for (int q = 0; q < kGroup; ++q) {
+                        if (wg + q < w1) {
+                            const uint32_t c = step_code(wg + q);
+                            if (c & kCodeGeneral) {
+                                double Z[NC];
+                                load_zt(ztab, wg + q, Z);
+                                accumulate(compose<TREE>(P, F, Z), Z, g[q] * gscale, wg + q, true);
+                            } else {
+                                if (c != cur) {
+                                    flush();
+                                    cur = c;
+                                }
+                                grun += g[q];
                             }
                         }
                     }
                 }
             }
         };
-        const int ngrp = (w1 - w0 + U - 1) / U;
-        for (int gi = 0; gi < ngrp; gi += 2) {
-            if (gi + 1 < ngrp) load_set(sb, w0 + (gi + 1) * U);
-            process(sa, w0 + gi * U);
-            if (gi + 1 < ngrp) {
-                if (gi + 2 < ngrp) load_set(sa, w0 + (gi + 2) * U);
-                process(sb, w0 + (gi + 1) * U);
+        // The loads are issued unconditionally (reads past the plane return
+        // 0): a load under a branch makes the wait before the next set drain
+        // every outstanding load, which turns the double buffer back into
+        // load-wait-compute.
+        const int nset = (w1 - w0 + U - 1) / U;
+        for (int si = 0; si < nset; si += 2) {
+            load_set(sb, w0 + (si + 1) * U);
+            process(sa, w0 + si * U);
+            load_set(sa, w0 + (si + 2) * U);
+            process(sb, w0 + (si + 1) * U);
+        }
+        flush();
+
+        // ---- 3. partials of the column-axis bounds of each class (F_c times
+        // the w-bound sums), then the in-plane partials
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c < P.nclass && P.cls_wparam[c]) {
+                const DevClass cl = P.cls[c];
+                const float fs = act ? (float)F[c] : 0.0f;
+                emit(P, cl.flo, fs * Blo[c]);
+                emit(P, cl.fhi, fs * Bhi[c]);
             }
         }
-    }
-
-    // ---- end of the column: partials of the column-axis bounds of each class
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (c < P.nclass && P.cls_wparam[c] && T.wave_live) {
-            const DevClass cl = P.cls[c];
-            const float fs = act ? (float)F[c] : 0.0f;
-            emit(P, cl.flo, fs * Blo[c]);
-            emit(P, cl.fhi, fs * Bhi[c]);
-        }
-    }
-    // ---- in-plane partials: column sums to LDS, candidates split over the
-    // block's wavefronts, one atomic per (block, parameter field)
-    __shared__ float sA[NC * kBlock];
-    __shared__ float sG[(TYPES & T_GCART) ? (kBlock / 64) * 2 * kSegBucket : 1];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) sA[c * kBlock + tid] = act ? A[c] : 0.0f;
-    __syncthreads();
-    const int u0 = tui * TU, v0 = tvi * P.tv;
-    int next = 0;
-    bool first = true;
-    while (first || next < P.nprim) {
-        int n;
-        if (first && complete) {
-            n = nlist;
-            next = P.nprim;
-        } else {
+        for (int c = 0; c < NC; ++c) sA[c * kBlock + tid] = act ? A[c] : 0.0f;
+        s_lat[tid] = G.uc;
+        s_lat[kBlock + tid] = G.uw;
+        s_lat[2 * kBlock + tid] = G.vc;
+        s_lat[3 * kBlock + tid] = G.vw;
+        const SampleLat L{s_lat};
+        float* sgw = sG + ((TYPES & T_GCART) ? wave * 2 * kSegBucket : 0);
+        if (staged_all) {
             __syncthreads();
-            n = build_list(P.bbox, P.nprim, next, T.ulo, T.uhi, T.vlo, T.vhi, s_cand, s_cnt, &next);
-        }
-        first = false;
-        for (int j = wave; j < n; j += kBlock / 64) {
-            const int pi = uniform_int(s_cand[j]);
-            const DevPrim pr = P.prims[pi];
-            block_partials<TYPES, SIGS>(P, pr, sA + pr.cls * kBlock, u0, v0, comp, T, sG + wave * 2 * kSegBucket);
+            for (int j = wave; j < ncand; j += kBlock / 64)
+                block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, sgw);
+        } else {
+            for (int next = 0; next < P.nprim;) {
+                const int n = scan_candidates(P.bbox, P.nprim, next, G.T.ulo, G.T.uhi, G.T.vlo, G.T.vhi, s_cand,
+                                              s_cnt, &next);
+                for (int j0 = 0; j0 < n; j0 += kStageRec) {
+                    const int nj = min(kStageRec, n - j0);
+                    stage_cands(P.prec, s_cand, j0, nj, s_rec);
+                    for (int j = wave; j < nj; j += kBlock / 64)
+                        block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, sgw);
+                }
+            }
         }
     }
 }
@@ -904,13 +1219,10 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ dst, double v
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st) {
-    const int64_t nz = (int64_t)sp.ncomp * sp.nclass * sp.nw;
-    int64_t n = sp.nprim;
-    if (nz > n) n = nz;
-    if (sp.zero_n > n) n = sp.zero_n;
-    if (n < 1) n = 1;
-    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)nvariant);
-    hipLaunchKernelGGL(k_stage, grid, dim3(256), 0, st, sp);
+    const int64_t nz = (int64_t)sp.ncomp * ((sp.nw + kGroup - 1) / kGroup);
+    const int64_t n = std::max<int64_t>(1, std::max<int64_t>(nz, sp.zero_n));
+    const int64_t blocks = (sp.nprim + 3) / 4 + (n + 255) / 256;
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)blocks, (unsigned)nvariant), dim3(256), 0, st, sp);
     return hipGetLastError();
 }
 

@@ -54,15 +54,18 @@ struct sg_scene {
     double* d_consts = nullptr;
     double* d_p = nullptr;
     double* d_fval[2] = {nullptr, nullptr};
-    double4* d_bbox[2] = {nullptr, nullptr};
+    float4* d_bbox[2] = {nullptr, nullptr};
+    sg::PrimRec* d_prec[2] = {nullptr, nullptr};
     double* d_ztab[2] = {nullptr, nullptr};
+    uint32_t* d_code[2] = {nullptr, nullptr};   // column-step codes
+    uint32_t* d_gcode[2] = {nullptr, nullptr};  // group codes
     double* d_grad = nullptr;
     float* d_work[2] = {nullptr, nullptr};
     double* h_p = nullptr;            // pinned staging
     double* h_grad = nullptr;
     hipEvent_t p_evt = nullptr;
     bool p_evt_pending = false;
-    // tracing: events around the main column-kernel launches
+    // tracing: events around the column-kernel launches
     bool timing = false;
     struct Rec {
         int mode;

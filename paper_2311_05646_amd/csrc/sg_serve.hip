@@ -45,8 +45,11 @@ struct Buf {                 // device buffers of one admitted request
     float2* a = nullptr;
     double* p = nullptr;
     double* fval = nullptr;
-    double4* bbox = nullptr;
+    float4* bbox = nullptr;
+    PrimRec* prec = nullptr;
     double* ztab = nullptr;
+    uint32_t* code = nullptr;
+    uint32_t* gcode = nullptr;
     double* grad = nullptr;
     double* h_p = nullptr;   // pinned
     double* h_grad = nullptr;
@@ -117,7 +120,10 @@ void free_buf(Buf* b) {
     hipFree(b->p);
     hipFree(b->fval);
     hipFree(b->bbox);
+    hipFree(b->prec);
     hipFree(b->ztab);
+    hipFree(b->code);
+    hipFree(b->gcode);
     hipFree(b->grad);
     if (b->h_p) hipHostFree(b->h_p);
     if (b->h_grad) hipHostFree(b->h_grad);
@@ -131,8 +137,12 @@ bool alloc_buf(sg_scene* sc, Buf* b) {
     if (e == hipSuccess) e = hipMalloc((void**)&b->a, cm * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc((void**)&b->p, n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b->fval, nfield * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->bbox, std::max(1, sc->nprim) * sizeof(double4));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->bbox, std::max(1, sc->nprim) * sizeof(float4));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->prec, std::max(1, sc->nprim) * sizeof(PrimRec));
     if (e == hipSuccess) e = hipMalloc((void**)&b->ztab, (size_t)sc->ncomp * sc->nclass * sc->nw * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->code, (size_t)sc->ncomp * sc->nw * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&b->gcode, (size_t)sc->ncomp * ((sc->nw + kGroup - 1) / kGroup) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&b->grad, n * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_p, n * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_grad, n * sizeof(double));
@@ -242,7 +252,10 @@ bool launch_batch(sg_server* v, Lane& L) {
         StageParams sp = stage_params(sc, b->p);
         sp.fval[0] = b->fval;
         sp.bbox[0] = b->bbox;
+        sp.prec[0] = b->prec;
         sp.ztab[0] = b->ztab;
+        sp.code[0] = b->code;
+        sp.gcode[0] = b->gcode;
         sp.zero_ptr = b->grad;
         sp.zero_n = sc->n_params;
         if (launch_stage(sp, 1, st) != hipSuccess) return false;
@@ -264,7 +277,10 @@ bool launch_batch(sg_server* v, Lane& L) {
             KParams kp = column_params(sc);
             kp.fval = b->fval;
             kp.bbox = b->bbox;
+            kp.prec = b->prec;
             kp.ztab = b->ztab;
+            kp.code = b->code;
+            kp.gcode = b->gcode;
             kp.grad = b->grad;
             for (int c = 0; c < kMaxComp; ++c) {
                 const int cc = std::min(c, sc->ncomp - 1);
