@@ -115,6 +115,9 @@ def cpu_baseline(W, cfg, fields0, seconds_budget):
 
 
 def time_kernels(api, scene, p_dev, E, A, omega, reps):
+    """Column-kernel times of eps_build and eps_grad_vjp, each call repeated
+    back to back (interleaving them adds the write-back of eps to the VJP's
+    HBM traffic)."""
     import torch
     g = torch.empty(scene.n_params, dtype=torch.float64, device="cuda")
     e = torch.empty(scene.shape, dtype=torch.float32, device="cuda")
@@ -125,6 +128,8 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
     scene.set_timing(True)
     for _ in range(reps):
         api.eps_build(scene, p_dev, out=e)
+    torch.cuda.synchronize()
+    for _ in range(reps):
         api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
     torch.cuda.synchronize()
     ve, ne = scene.kernel_time("eps")
@@ -133,6 +138,28 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
     m = scene.shape[0] * scene.shape[1] * scene.shape[2] * scene.shape[3]
     return {"vjp_us": 1e3 * vv / nv, "vjp_GBps": 16.0 * m / (vv / nv * 1e-3) / 1e9,
             "eps_us": 1e3 * ve / ne, "eps_GBps": 4.0 * m / (ve / ne * 1e-3) / 1e9, "samples": m}
+
+
+def kernels_3d(api, W, gen, reps):
+    """Column-kernel bandwidth of eps_build and eps_grad_vjp on the 3D taper
+    (600x240x100) and the 3D polarization-splitting grating (400x400x80)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    also = {}
+    for name, mk in (("c3", W.make_c3), ("c4", W.make_c4)):
+        log(f"[bench] {name} kernels")
+        c = mk(with_fields=False)
+        sc = api.Scene(c["scene"])
+        E = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
+        A = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
+        pd = torch.tensor(c["p"], dtype=torch.float64, device=dev)
+        r = time_kernels(api, sc, pd, E, A, c["omega"], reps)
+        r["vjp_frac_of_peak"] = r["vjp_GBps"] / HBM_PEAK_GBS
+        r["n_params"] = sc.n_params
+        also[name] = r
+        del E, A, sc
+        torch.cuda.empty_cache()
+    return also
 
 
 def bench_serving(api, W, seconds=3.0, think_us=200.0):
@@ -211,6 +238,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true", help="also run the reference copy kernel (1 GiB)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--kernels-3d", action="store_true",
+                    help="only the 3D workloads' column-kernel loops (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the path shards by grid slab "
@@ -224,6 +253,12 @@ def main():
         from paper_2311_05646_amd import build
         build.build()
     from paper_2311_05646_amd import api
+
+    if args.kernels_3d:
+        gen = torch.Generator(device=torch.device("cuda", 0))
+        gen.manual_seed(W.BASE_SEED)
+        print(json.dumps({"3d": kernels_3d(api, W, gen, max(1, args.steps))}), flush=True)
+        return
 
     log("[bench] generating c2 inputs")
     cfg = W.make_c2()
@@ -320,21 +355,7 @@ def main():
                  "fd_alg_GBps": (20.0 * m + scene.n_params * 12.0 * m) / fd_s / 1e9}
 
     # ---- 3D workloads: kernel bandwidth (not the bench line's workload)
-    also = {}
-    for name, mk in (("c3", W.make_c3), ("c4", W.make_c4)):
-        log(f"[bench] {name} kernels")
-        c = mk(with_fields=False)
-        sc = api.Scene(c["scene"])
-        E = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
-        A = torch.complex(torch.randn(sc.shape, device=dev, generator=gen), torch.randn(sc.shape, device=dev, generator=gen))
-        pd = torch.tensor(c["p"], dtype=torch.float64, device=dev)
-        r = time_kernels(api, sc, pd, E, A, c["omega"], 20)
-        r["vjp_frac_of_peak"] = r["vjp_GBps"] / HBM_PEAK_GBS
-        r["n_params"] = sc.n_params
-        also[name] = r
-        del E, A, sc
-        torch.cuda.empty_cache()
-    out["3d"] = also
+    out["3d"] = kernels_3d(api, W, gen, 20)
 
     # ---- serving: continuous batching vs one-at-a-time launches
     log("[bench] serving")

@@ -72,6 +72,7 @@ static void free_scene(sg_scene* s) {
     hipFree(s->d_prims);
     hipFree(s->d_cls);
     hipFree(s->d_consts);
+    hipFree(s->d_gseg);
     hipFree(s->d_p);
     for (int i = 0; i < 2; ++i) {
         hipFree(s->d_fval[i]);
@@ -392,6 +393,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     }
     // device primitive records (primitives of the tree only, in index order)
     std::vector<DevPrim> prims;
+    std::vector<GSeg> gseg;     // piecewise-linear boundaries: segment of every u-sample center
     for (int i = 0; i < d->nprim; ++i) {
         if (!used[i]) continue;
         const sg_prim_desc& p = d->prims[i];
@@ -405,6 +407,26 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             const double k = sgm.kmode == SG_K_LOCAL ? sgm.k / wmax[axis] : sgm.k;
             return sigma_cut(sgm.kind) / k;
         };
+        r.gs0 = -1;
+        if (p.type == SG_PRIM_GCART) {
+            // largest j in [0, M-2] with x_j <= x (0 left of the first vertex),
+            // and t = (x - x_j) / (x_{j+1} - x_j) clamped to [0, 1]
+            const double* xv = d->consts + p.const_off;
+            const int M = p.nvert;
+            r.gs0 = (int32_t)gseg.size();
+            for (int c = 0; c < d->ncomp; ++c) {
+                const double* uc = lat.data() + s->lat_off[c][0];
+                for (int u = 0; u < s->nu; ++u) {
+                    int j = 0;
+                    while (j + 1 <= M - 2 && xv[j + 1] <= uc[u]) ++j;
+                    const double tt = (uc[u] - xv[j]) / (xv[j + 1] - xv[j]);
+                    GSeg g{};
+                    g.j = j;
+                    g.t = std::min(1.0, std::max(0.0, tt));
+                    gseg.push_back(g);
+                }
+            }
+        }
         if (p.type == SG_PRIM_BOX) {
             r.ubnd = p.bounded[0] != 0;
             r.vbnd = p.bounded[axis_v] != 0;
@@ -488,6 +510,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     alloc((void**)&s->d_prims, prims.size() * sizeof(DevPrim));
     alloc((void**)&s->d_cls, s->classes.size() * sizeof(DevClass));
     alloc((void**)&s->d_consts, std::max(1, d->nconst) * sizeof(double));
+    alloc((void**)&s->d_gseg, std::max<size_t>(1, gseg.size()) * sizeof(GSeg));
     alloc((void**)&s->d_p, std::max<int64_t>(1, d->n_params) * sizeof(double));
     alloc((void**)&s->d_grad, std::max<int64_t>(1, d->n_params) * sizeof(double));
     for (int v = 0; v < 2; ++v) {
@@ -509,6 +532,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         e = hipMemcpy(s->d_cls, s->classes.data(), s->classes.size() * sizeof(DevClass), hipMemcpyHostToDevice);
     if (e == hipSuccess && d->nconst)
         e = hipMemcpy(s->d_consts, d->consts, d->nconst * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !gseg.empty())
+        e = hipMemcpy(s->d_gseg, gseg.data(), gseg.size() * sizeof(GSeg), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         free_scene(s);
         return fail(e == hipErrorOutOfMemory ? SG_E_NOMEM : SG_E_DEVICE, "sg_scene_create: %s", hipGetErrorString(e));
@@ -649,6 +674,7 @@ KParams sg::column_params(sg_scene* s) {
     kp.cls = s->d_cls;
     kp.fref = s->d_fref;
     kp.consts = s->d_consts;
+    kp.gseg = s->d_gseg;
     kp.fval = s->d_fval[0];
     kp.bbox = s->d_bbox[0];
     kp.prec = s->d_prec[0];

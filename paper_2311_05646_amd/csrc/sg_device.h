@@ -256,11 +256,12 @@ __device__ __forceinline__ void gcart_segment(const double* __restrict__ xv, int
     t = fmin(1.0, fmax(0.0, tt));
 }
 
-// In-plane factor F(u, v) of a primitive (value only).
+// In-plane factor F(u, v) of a primitive (value only).  gs: the sample's entry
+// of the primitive's segment table (piecewise-linear boundaries only).
 template <int TYPES, int SIGS>
 __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __restrict__ fv,
                                              const double* __restrict__ cst,
-                                             double uc, double uw, double vc, double vw) {
+                                             double uc, double uw, double vc, double vw, const GSeg* gs) {
     if constexpr ((TYPES & T_BOX) != 0) {
         if (TYPES == T_BOX || pr.type == SG_PRIM_BOX) {
             double f = 1.0;
@@ -301,9 +302,9 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
             const int M = pr.nvert;
             const double rx = rect_v<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1]);
             if (rx == 0.0) return 0.0;
-            int j;
-            double t;
-            gcart_segment(cst + pr.c0, M, uc, j, t);
+            const GSeg sgm = *gs;
+            const int j = sgm.j;
+            const double t = sgm.t;
             const double* yp = fv + pr.f0 + 2;
             const double* ym = yp + M;
             const double fp = (1.0 - t) * yp[j] + t * yp[j + 1];

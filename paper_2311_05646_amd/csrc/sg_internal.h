@@ -54,11 +54,20 @@ struct DevPrim {
     int32_t fv0, fv1;      // BOX: fields of the v bounds
     int32_t sk0, sm0;      // sigma kind / k mode of argument 0 (u bound, boundary, x-range)
     int32_t sk1, sm1;      // sigma kind / k mode of argument 1 (v bound, GCART y boundary)
-    int32_t pad;
+    int32_t gs0;           // GCART: first entry of its segment table (component 0, u = 0); else -1
     double k0, k1;         // k_r (LOCAL) or k (FIXED)
     double reach0, reach1; // support half-width of each argument (um), for the support boxes
     double ax, ay;         // ELLIPSE aspect
     double iax, iay;       // 1 / aspect
+};
+
+// Segment of a piecewise-linear boundary (GCART) that a u-sample center falls
+// in, and its position t in [0, 1] along it.  The vertices' x are constants of
+// the scene, so the table is built once, per (primitive, component, u).
+struct GSeg {
+    int32_t j;
+    int32_t pad;
+    double t;
 };
 
 // Per-call copy of a primitive as the in-plane and partials kernels read it
@@ -130,6 +139,7 @@ struct KParams {
     const DevClass* cls;
     const sg_field* fref;
     const double* consts;
+    const GSeg* gseg;            // GCART segment tables
     const double* fval;
     const float4* bbox;
     const PrimRec* prec;

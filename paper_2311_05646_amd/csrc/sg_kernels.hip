@@ -261,19 +261,24 @@ __device__ int scan_candidates(const float4* __restrict__ bb, int nprim, int sta
                                double vlo, double vhi, int* s_cand, int* s_cnt, int* next) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NW = kBlock / 64;
+    // only the rows of kBlock boxes that hold primitives are read
+    const int rows = min(kScanPer, (nprim - start + kBlock - 1) / kBlock);
     float4 box[kScanPer];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         const int i = start + k * kBlock + tid;
-        box[k] = bb[min(i, nprim - 1)];
+        if (k < rows) box[k] = bb[min(i, nprim - 1)];
     }
     uint64_t m[kScanPer];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         const int i = start + k * kBlock + tid;
-        const float4 b = box[k];
-        const bool hit = (i < nprim) && ((double)b.x <= uhi) && ((double)b.y >= ulo) && ((double)b.z <= vhi) &&
-                         ((double)b.w >= vlo);
+        bool hit = false;
+        if (k < rows) {
+            const float4 b = box[k];
+            hit = (i < nprim) && ((double)b.x <= uhi) && ((double)b.y >= ulo) && ((double)b.z <= vhi) &&
+                  ((double)b.w >= vlo);
+        }
         m[k] = __ballot(hit);
         if (lane == 0) s_cnt[k * NW + wave] = __popcll(m[k]);
     }
@@ -328,9 +333,8 @@ __device__ __forceinline__ void stage_cands(const PrimRec* __restrict__ prec, co
 
 // In-plane factor F(u, v) of a staged candidate (value only).
 template <int TYPES, int SIGS>
-__device__ __forceinline__ double cand_value(const PrimRec& c, const double* __restrict__ fv,
-                                             const double* __restrict__ cst, double uc, double uw, double vc,
-                                             double vw) {
+__device__ __forceinline__ double cand_value(const KParams& P, const PrimRec& c, const double* __restrict__ fv,
+                                             int comp, int u, double uc, double uw, double vc, double vw) {
     const DevPrim& pr = c.pr;
     if constexpr ((TYPES & T_BOX) != 0) {
         if (TYPES == T_BOX || pr.type == SG_PRIM_BOX) {
@@ -351,7 +355,9 @@ __device__ __forceinline__ double cand_value(const PrimRec& c, const double* __r
             return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
-    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0) return prim_value<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, cst, uc, uw, vc, vw);
+    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0)
+        return prim_value<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
+                                                            P.gseg + pr.gs0 + (int64_t)comp * P.nu + u);
     return 0.0;
 }
 
@@ -359,10 +365,11 @@ __device__ __forceinline__ double cand_value(const PrimRec& c, const double* __r
 // candidate of the tile fits one staging round, the records stay in s_rec for
 // the partials (*staged_all; *ncand of them).
 template <int NC, int TYPES, int SIGS>
-__device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __restrict__ bbox, const PrimRec* __restrict__ prec,
-                             const double* __restrict__ fval, const Tile& T, double uc, double uw, double vc,
-                             double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC], int& ncand,
-                             bool& staged_all) {
+__device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __restrict__ bbox,
+                                             const PrimRec* __restrict__ prec, const double* __restrict__ fval,
+                                             const Tile& T, int comp, int u, double uc, double uw, double vc,
+                                             double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC],
+                                             int& ncand, bool& staged_all) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) F[c] = 0.0;
     ncand = 0;
@@ -380,7 +387,7 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
             if (!T.wave_live) continue;
             for (int j = 0; j < nj; ++j) {
                 if (!wave_meets(T, s_rec[j].bb)) continue;
-                const double f = cand_value<TYPES, SIGS>(s_rec[j], fval, P.consts, uc, uw, vc, vw);
+                const double f = cand_value<TYPES, SIGS>(P, s_rec[j], fval, comp, u, uc, uw, vc, vw);
                 add_to_class(F, s_rec[j].pr.cls, f);
             }
         }
@@ -546,18 +553,16 @@ constexpr int kSegBucket = 256;
 
 template <int SIGS>
 __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& pr, const float* sAc, const SampleLat& L,
-                               const Tile& T, float* sg) {
+                               const Tile& T, int comp, int u0, float* sg) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
+    const int TU = P.tu;
     const double* fv = P.fval;
     const int M = pr.nvert;
-    const double* xv = P.consts + pr.c0;
     const double* yp = fv + pr.f0 + 2;
     const double* ym = yp + M;
-    int jlo, jhi;
-    double tdum;
-    gcart_segment(xv, M, T.ulo, jlo, tdum);
-    gcart_segment(xv, M, T.uhi, jhi, tdum);
+    const GSeg* gs = P.gseg + pr.gs0 + (int64_t)comp * P.nu;
+    const int jlo = gs[u0].j, jhi = gs[min(u0 + TU, P.nu) - 1].j;   // segments of the tile's first / last sample
     const int nvx = jhi - jlo + 2;               // vertices jlo .. jhi + 1
     const bool bucket = nvx <= kSegBucket;
     if (bucket) {
@@ -579,8 +584,9 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
         if (a != 0.0f) {
             double rx, drx0, drx1;
             rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, xs0, xs1, rx, drx0, drx1);
-            double t01;
-            gcart_segment(xv, M, uc, j, t01);
+            const GSeg sgm = gs[min(u0 + (t & (TU - 1)), P.nu - 1)];
+            j = sgm.j;
+            const double t01 = sgm.t;
             const double fp = (1.0 - t01) * yp[j] + t01 * yp[j + 1];
             const double fm = (1.0 - t01) * ym[j] + t01 * ym[j + 1];
             const double ky = kval(pr.sm1, pr.k1, vw);
@@ -641,7 +647,7 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
 // the wavefront, and added with one atomic per parameter field.
 template <int TYPES, int SIGS>
 __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& cr, const float* sAc, const SampleLat& L,
-                               const Tile& T, float* sg) {
+                               const Tile& T, int comp, int u0, float* sg) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
     const DevPrim& pr = cr.pr;
@@ -721,7 +727,7 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
     }
     if constexpr ((TYPES & T_GCART) != 0) {
         if (type == SG_PRIM_GCART) {
-            gcart_partials<SIGS>(P, pr, sAc, L, T, sg);
+            gcart_partials<SIGS>(P, pr, sAc, L, T, comp, u0, sg);
             return;
         }
     }
@@ -870,7 +876,9 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 
     // Field loads: two register sets of U steps each, double-buffered.  The
     // buffer resource of a set starts at its first step, so every load of the
-    // set is (lane offset, immediate step offset).
+    // set is (lane offset, immediate step offset), and ends at the segment's
+    // end: the loads the double buffer issues past it return 0 without
+    // touching memory.
     const char* plane0 = nullptr;
     const char* plane1 = nullptr;
     if constexpr (MODE == MODE_VJP_FIELDS) {
@@ -888,9 +896,10 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     Set sa, sb;
     auto load_set = [&](Set& st, int w) {
         const int64_t off = (int64_t)w * step_bytes;
+        const int64_t len = min(plane_bytes - off, (int64_t)(w1 - w) * step_bytes);
         if constexpr (MODE == MODE_VJP_FIELDS) {
-            const __amdgpu_buffer_rsrc_t re = buffer_rsrc(plane0 + off, plane_bytes - off);
-            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(plane1 + off, plane_bytes - off);
+            const __amdgpu_buffer_rsrc_t re = buffer_rsrc(plane0 + off, len);
+            const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(plane1 + off, len);
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 st.e[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(re, lane_off,
@@ -899,7 +908,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                                                                                       (int)(q * step_bytes), 0));
             }
         } else if constexpr (MODE == MODE_VJP_GEPS) {
-            const __amdgpu_buffer_rsrc_t rg = buffer_rsrc(plane0 + off, plane_bytes - off);
+            const __amdgpu_buffer_rsrc_t rg = buffer_rsrc(plane0 + off, len);
 #pragma unroll
             for (int q = 0; q < U; ++q)
                 st.g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, lane_off,
@@ -914,13 +923,13 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     double F[NC], F2[NC];
     int ncand = 0;
     bool staged_all = false;
-    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.prec, P.fval, G.T, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt, s_rec, F,
-                                  ncand, staged_all);
+    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt,
+                                  s_rec, F, ncand, staged_all);
     if constexpr (MODE == MODE_FD) {
         int nc2;
         bool sa2;
-        inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.prec2, P.fval2, G.T, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt,
-                                      s_rec, F2, nc2, sa2);
+        inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.prec2, P.fval2, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
+                                      s_cnt, s_rec, F2, nc2, sa2);
     }
 
     // ---- 2. the column
@@ -1097,10 +1106,11 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         s_lat[3 * kBlock + tid] = G.vw;
         const SampleLat L{s_lat};
         float* sgw = sG + ((TYPES & T_GCART) ? wave * 2 * kSegBucket : 0);
+        const int u0 = G.u - (tid & (P.tu - 1));   // first u of the tile
         if (staged_all) {
             __syncthreads();
             for (int j = wave; j < ncand; j += kBlock / 64)
-                block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, sgw);
+                block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0, sgw);
         } else {
             for (int next = 0; next < P.nprim;) {
                 const int n = scan_candidates(P.bbox, P.nprim, next, G.T.ulo, G.T.uhi, G.T.vlo, G.T.vhi, s_cand,
@@ -1109,7 +1119,8 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                     const int nj = min(kStageRec, n - j0);
                     stage_cands(P.prec, s_cand, j0, nj, s_rec);
                     for (int j = wave; j < nj; j += kBlock / 64)
-                        block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, sgw);
+                        block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0,
+                                                    sgw);
                 }
             }
         }

@@ -52,6 +52,7 @@ struct sg_scene {
     sg::DevPrim* d_prims = nullptr;
     sg::DevClass* d_cls = nullptr;
     double* d_consts = nullptr;
+    sg::GSeg* d_gseg = nullptr;
     double* d_p = nullptr;
     double* d_fval[2] = {nullptr, nullptr};
     float4* d_bbox[2] = {nullptr, nullptr};
