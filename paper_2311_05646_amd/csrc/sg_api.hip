@@ -276,11 +276,35 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             used[pi] = 1;
         }
 
-    // column axis: y for 2D scenes made only of boxes, else z
+    // column axis: y for 2D scenes made only of boxes whose y-extents form at
+    // most kMaxClasses classes (the boxes' y factor then becomes the column
+    // factor), else z
     bool all_box = true;
     for (int i = 0; i < d->nprim; ++i)
         if (used[i] && d->prims[i].type != SG_PRIM_BOX) all_box = false;
-    const int col = (d->dim == 2 && all_box) ? 1 : 2;
+    bool y_classes_fit = true;
+    if (d->dim == 2 && all_box) {
+        int total = 0;
+        for (auto& g : groups) {
+            std::vector<ColSpec> seen;
+            for (int pi : g.prims) {
+                const sg_prim_desc& p = d->prims[pi];
+                ColSpec cs{};
+                cs.bounded = p.bounded[1] != 0;
+                if (cs.bounded) {
+                    cs.lo = d->fields[p.field_off + 2];
+                    cs.hi = d->fields[p.field_off + 3];
+                    cs.kind = p.sigma[1].kind;
+                    cs.kmode = p.sigma[1].kmode;
+                    cs.k = p.sigma[1].k;
+                }
+                if (std::find(seen.begin(), seen.end(), cs) == seen.end()) seen.push_back(cs);
+            }
+            total += (int)seen.size();
+        }
+        y_classes_fit = total <= kMaxClasses;
+    }
+    const int col = (d->dim == 2 && all_box && y_classes_fit) ? 1 : 2;
     const int axis_v = col == 2 ? 1 : 2;
 
     auto* s = new (std::nothrow) sg_scene;

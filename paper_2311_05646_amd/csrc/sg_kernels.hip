@@ -917,7 +917,12 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 #pragma unroll
         for (int h = 0; h < NG; ++h) st.gc[h] = group_code(w + h * kGroup);
     };
-    if constexpr (VJP) load_set(sa, w0);   // every segment holds at least one step
+    // both sets go out before the in-plane pass, so 2 U steps are in flight
+    // while it runs (every segment holds at least one step)
+    if constexpr (VJP) {
+        load_set(sa, w0);
+        load_set(sb, w0 + U);
+    }
 
     // ---- 1. in-plane sums
     double F[NC], F2[NC];
@@ -1080,10 +1085,10 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         // load-wait-compute.
         const int nset = (w1 - w0 + U - 1) / U;
         for (int si = 0; si < nset; si += 2) {
-            load_set(sb, w0 + (si + 1) * U);
             process(sa, w0 + si * U);
             load_set(sa, w0 + (si + 2) * U);
             process(sb, w0 + (si + 1) * U);
+            load_set(sb, w0 + (si + 3) * U);
         }
         flush();
 

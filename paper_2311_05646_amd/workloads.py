@@ -421,9 +421,73 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     return out
 
 
+def make_crowd(seed=BASE_SEED + 21, n_ell=50, n_box=30):
+    """A slab minus a crowd of small sigmoid ellipses and linear boxes packed
+    into a 0.34 um square, so that one in-plane tile holds far more candidate
+    primitives than one staging round.  Not one of the paper's devices."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    X = uniform_nodes(40, 0.025)
+    Y = uniform_nodes(36, 0.025)
+    Z = graded_nodes(raised_cosine_widths(6, 20.0, 30.0))
+    z0, z1 = float(Z[1]) + 0.004, float(Z[5]) - 0.006
+    p, prims = [], []
+
+    def par(v):
+        p.append(v)
+        return P(len(p) - 1)
+
+    u = lambda a, b: float(rng.uniform(a, b))
+    slab = box(x=(K(-1.0), K(2.0)), y=(K(-1.0), K(2.0)), z=(K(z0), K(z1)))
+    prims.append(slab)
+    for _ in range(n_ell):
+        prims.append(ellipse(par(u(0.08, 0.42)), par(u(0.08, 0.42)), par(u(0.02, 0.04)), aspect=(1.2, 1 / 1.2),
+                             z=(K(z0), K(z1)), sig=("sigmoid", "fixed", 120.0)))
+    for _ in range(n_box):
+        x0 = u(0.08, 0.36)
+        y0 = u(0.08, 0.36)
+        prims.append(box(x=(par(x0), par(x0 + u(0.03, 0.06))), y=(K(y0), K(y0 + u(0.03, 0.06))),
+                         z=(K(z0), K(z1))))
+    tree = {"op": "difference", "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}
+    scene = {"name": "crowd3d", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims, "tree": tree}
+    out = {"scene": scene, "p": np.array(p), "omega": _wl_omega(1.31), "h": 1e-7}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+def make_many(seed=BASE_SEED + 22, n_box=2300, n_free=200):
+    """More primitives than one candidate scan covers: the union of 2300 small
+    linear boxes on a 2D 300x40 grid; the x-edges of the first 200 are design
+    parameters, the rest are constants.  Not one of the paper's devices."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    X = uniform_nodes(300, 0.015)
+    Y = uniform_nodes(40, 0.02)
+    Z = np.array([0.0, 1.0])
+    p, prims = [], []
+    u = lambda a, b: float(rng.uniform(a, b))
+    for i in range(n_box):
+        x0 = u(0.1, 4.3)
+        x1 = x0 + u(0.05, 0.1)
+        y0 = u(0.1, 0.5)
+        y1 = y0 + u(0.08, 0.2)
+        if i < n_free:
+            p += [x0, x1]
+            xs = (P(len(p) - 2), P(len(p) - 1))
+        else:
+            xs = (K(x0), K(x1))
+        prims.append(box(x=xs, y=(K(y0), K(y1))))
+    tree = {"op": "union", "children": list(range(n_box))}
+    scene = {"name": "many2d", "dim": 2, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims, "tree": tree}
+    out = {"scene": scene, "p": np.array(p), "omega": _wl_omega(1.55), "h": 1e-5}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
 CONFIGS = {
     "c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4,
     "c2_small": make_c2_small, "c3_small": make_c3_small, "c4_small": make_c4_small,
+    "crowd3": make_crowd, "many2": make_many,
 }
 
 

@@ -12,8 +12,10 @@ from paper_2311_05646_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# crowd3: one tile holds more candidates than a staging round; many2: more
+# primitives than one candidate scan pass
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
-         "zoo2_intersection", "zoo3_intersection", "zoo2_difference"]
+         "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 
@@ -97,7 +99,7 @@ def test_device_p_and_grad(name):
     assert torch.equal(e1, e2)
 
 
-@pytest.mark.parametrize("name", ["c4_small", "zoo3_union", "c2_small"])
+@pytest.mark.parametrize("name", ["c4_small", "zoo3_union", "c2_small", "crowd3"])
 def test_launch_shape_independence(name):
     """eps does not depend on the tiling (bitwise); gradients only through the
     order of atomic additions."""
