@@ -40,9 +40,15 @@ def log(msg):
 
 
 def kernel_src_sha():
+    """Hash of the kernel sources with comments and blank space removed (a
+    comment edit leaves the profiled code, and so its counters, valid)."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        text = open(os.path.join(ROOT, f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

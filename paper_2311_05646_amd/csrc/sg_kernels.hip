@@ -1,19 +1,21 @@
 // gfx950 kernels of the shape-gradient path.
 //
-//  k_stage   p -> resolved primitive fields (a + b p[idx]), support boxes and
-//            the per-class extrusion tables Z(w), dZ/dlo, dZ/dhi; zeroes the
-//            gradient accumulator.
+//  k_stage   p -> resolved primitive fields (a + b p[idx]), support boxes,
+//            per-primitive records, the per-class extrusion tables Z(w),
+//            dZ/dlo, dZ/dhi and the column-step codes; zeroes the gradient
+//            accumulator.
 //  k_column  one thread per in-plane sample (u, v) of one component, walking
 //            a segment of its column (w).  In-plane factors F_h of the
-//            candidate primitives are computed once per column in FP64; each
-//            column step composes the classes (eq:union, eq:intersection,
-//            difference) and either stores eps (MODE_EPS), stores the FD
-//            difference plane (MODE_FD), or accumulates the reverse-mode
-//            column sums A_c = sum_w g * d eps / d s_c * Z_c(w) (MODE_VJP_*),
-//            with g = 2 omega Im(E Eadj) (eq:1) or an upstream dF/deps.  After
-//            the column the in-plane partials are multiplied by A_c and
-//            reduced across the wavefront; lane 0 adds one FP64 atomic per
-//            parameter field touched by the wavefront.
+//            candidate primitives are summed per extrusion class once per
+//            column in FP64; along the column the composition (eq:union,
+//            eq:intersection, difference) is evaluated once per run of steps
+//            with equal extrusion masks, and either eps is stored (MODE_EPS),
+//            the FD difference plane is stored (MODE_FD), or the reverse-mode
+//            column sums A_c = sum_w g * d eps / d s_c * Z_c(w) are accumulated
+//            (MODE_VJP_*) with g = 2 omega Im(E Eadj) (eq:1) or an upstream
+//            dF/deps.  After the column the in-plane partials are multiplied
+//            by A_c and reduced across the wavefront; lane 0 adds one FP64
+//            atomic per parameter field touched by the wavefront.
 //  k_gplane  g = 2 omega Im(E Eadj) plane (finite-difference baseline)
 //  k_dot     sum a * b (finite-difference baseline reduction)
 #include "sg_device.h"
