@@ -365,17 +365,21 @@ __device__ __forceinline__ double cand_value(const KParams& P, const PrimRec& c,
 
 // Sum of F_h over the candidates, per class, at (uc, vc).  When every
 // candidate of the tile fits one staging round, the records stay in s_rec for
-// the partials (*staged_all; *ncand of them).
-template <int NC, int TYPES, int SIGS>
+// the partials (*staged_all; *ncand of them).  after_stage() runs once, after
+// the first staging round and before any evaluation (the caller issues its
+// field loads there: vector loads return in order, so loads issued earlier
+// would hold up the scan's and the staging's).
+template <int NC, int TYPES, int SIGS, class Hook>
 __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __restrict__ bbox,
                                              const PrimRec* __restrict__ prec, const double* __restrict__ fval,
                                              const Tile& T, int comp, int u, double uc, double uw, double vc,
                                              double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC],
-                                             int& ncand, bool& staged_all) {
+                                             int& ncand, bool& staged_all, Hook&& after_stage) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) F[c] = 0.0;
     ncand = 0;
     staged_all = false;
+    bool hooked = false;
     for (int next = 0; next < P.nprim;) {
         const bool first = next == 0;
         const int n = scan_candidates(bbox, P.nprim, next, T.ulo, T.uhi, T.vlo, T.vhi, s_cand, s_cnt, &next);
@@ -386,6 +390,10 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
         for (int j0 = 0; j0 < n; j0 += kStageRec) {
             const int nj = min(kStageRec, n - j0);
             stage_cands(prec, s_cand, j0, nj, s_rec);
+            if (!hooked) {
+                after_stage();
+                hooked = true;
+            }
             if (!T.wave_live) continue;
             for (int j = 0; j < nj; ++j) {
                 if (!wave_meets(T, s_rec[j].bb)) continue;
@@ -394,6 +402,7 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
             }
         }
     }
+    if (!hooked) after_stage();
 }
 
 // Composition at one column step: root value s and, per group g, the
@@ -919,24 +928,27 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 #pragma unroll
         for (int h = 0; h < NG; ++h) st.gc[h] = group_code(w + h * kGroup);
     };
-    // both sets go out before the in-plane pass, so 2 U steps are in flight
-    // while it runs (every segment holds at least one step)
-    if constexpr (VJP) {
-        load_set(sa, w0);
-        load_set(sb, w0 + U);
-    }
+    // both sets go out once the candidates are staged, so 2 U steps are in
+    // flight while the in-plane sums are evaluated (every segment holds at
+    // least one step)
+    auto first_loads = [&]() {
+        if constexpr (VJP) {
+            load_set(sa, w0);
+            load_set(sb, w0 + U);
+        }
+    };
 
     // ---- 1. in-plane sums
     double F[NC], F2[NC];
     int ncand = 0;
     bool staged_all = false;
     inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt,
-                                  s_rec, F, ncand, staged_all);
+                                  s_rec, F, ncand, staged_all, first_loads);
     if constexpr (MODE == MODE_FD) {
         int nc2;
         bool sa2;
         inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.prec2, P.fval2, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
-                                      s_cnt, s_rec, F2, nc2, sa2);
+                                      s_cnt, s_rec, F2, nc2, sa2, [] {});
     }
 
     // ---- 2. the column
