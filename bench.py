@@ -121,16 +121,22 @@ def cpu_baseline(W, cfg, fields0, seconds_budget):
 
 
 def time_kernels(api, scene, p_dev, E, A, omega, reps):
-    """Column-kernel times of eps_build and eps_grad_vjp, each call repeated
-    back to back (interleaving them adds the write-back of eps to the VJP's
-    HBM traffic)."""
+    """Column-kernel times of eps_build, eps_grad_vjp and eps_grad_vjp_sparse,
+    each call repeated back to back (interleaving them adds the write-back of
+    eps to the VJP's HBM traffic).  The sparse VJP reads the fields only where
+    d eps / d p can be nonzero: its share of the samples and its rate over the
+    bytes it needs are reported apart from the dense kernel's bandwidth."""
     import torch
     g = torch.empty(scene.n_params, dtype=torch.float64, device="cuda")
+    gs = torch.empty(scene.n_params, dtype=torch.float64, device="cuda")
     e = torch.empty(scene.shape, dtype=torch.float32, device="cuda")
     for _ in range(3):
         api.eps_build(scene, p_dev, out=e)
         api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
+        api.eps_grad_vjp_sparse(scene, p_dev, E, A, omega, grad=gs)
     torch.cuda.synchronize()
+    reads = scene.sparse_reads()
+    sparse_rel = float(torch.linalg.norm(gs - g) / torch.linalg.norm(g))
     scene.set_timing(True)
     for _ in range(reps):
         api.eps_build(scene, p_dev, out=e)
@@ -138,12 +144,20 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
     for _ in range(reps):
         api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
     torch.cuda.synchronize()
+    for _ in range(reps):
+        api.eps_grad_vjp_sparse(scene, p_dev, E, A, omega, grad=gs)
+    torch.cuda.synchronize()
     ve, ne = scene.kernel_time("eps")
     vv, nv = scene.kernel_time("vjp")
+    vs, ns = scene.kernel_time("sparse")
     scene.set_timing(False)
     m = scene.shape[0] * scene.shape[1] * scene.shape[2] * scene.shape[3]
     return {"vjp_us": 1e3 * vv / nv, "vjp_GBps": 16.0 * m / (vv / nv * 1e-3) / 1e9,
-            "eps_us": 1e3 * ve / ne, "eps_GBps": 4.0 * m / (ve / ne * 1e-3) / 1e9, "samples": m}
+            "eps_us": 1e3 * ve / ne, "eps_GBps": 4.0 * m / (ve / ne * 1e-3) / 1e9, "samples": m,
+            "sparse": {"us": 1e3 * vs / ns, "speedup_vs_dense_vjp": vv / nv / (vs / ns),
+                       "samples_read": reads, "read_fraction": reads / m,
+                       "GBps_of_bytes_read": 16.0 * reads / (vs / ns * 1e-3) / 1e9,
+                       "rel_l2_vs_dense": sparse_rel}}
 
 
 def kernels_3d(api, W, gen, reps):
@@ -354,6 +368,7 @@ def main():
     fd_s = (time.perf_counter() - t) / reps
     rel = float(torch.linalg.norm(gfd - gvjp) / torch.linalg.norm(gvjp))
     vjp_only = time_kernels(api, scene, p_dev, E0, A0, cfg["omega"], 50)
+    out["sparse_vjp"] = vjp_only["sparse"]
     out["fd"] = {"evals_per_s": 1.0 / fd_s, "seconds_per_eval": fd_s, "scheme": "central", "h_um": cfg["h"],
                  "rel_l2_vs_vjp": rel,
                  "vjp_kernel_speedup": fd_s / (vjp_only["vjp_us"] * 1e-6),

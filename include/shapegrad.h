@@ -164,6 +164,25 @@ sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_d
                        const void* const* e_fwd, const void* const* e_adj, double omega,
                        double* grad, int grad_on_device, void* stream);
 
+/* Step 5, sparse form (Sec. "Single-polarization blazed grating coupler in 2D",
+ * item (iv): restrict the material Jacobian to where shapes are perturbed;
+ * Sec. "Discussion and Conclusion": track its nonzero entries along shape
+ * boundaries).  Same arguments and result as eps_grad_vjp, but the fields are
+ * read only where d eps / d p can be nonzero: at samples where some
+ * primitive's in-plane sigma argument lies inside its support (with the
+ * primitive's other factors nonzero), and on column steps where some
+ * extrusion class is nonzero.  Entries equal eps_grad_vjp's up to the order of
+ * the floating-point sums.  Scenes whose extrusion bounds carry parameters
+ * read every sample (those partials reach wherever a shape is present). */
+sg_status eps_grad_vjp_sparse(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                              const void* const* e_fwd, const void* const* e_adj, double omega,
+                              double* grad, int grad_on_device, void* stream);
+
+/* Number of (sample, column step) pairs whose E_fwd and E_adj values the
+ * scene's last eps_grad_vjp_sparse call read (16 bytes each); waits for the
+ * device. */
+sg_status sg_scene_sparse_reads(sg_scene* scene, int64_t* pairs);
+
 /* Reverse mode with an upstream dF/deps: grad_eps is C FP32 planes stored
  * contiguously ([C][Nz][Ny][Nx]); grad_k = sum grad_eps * d eps / d p_k. */
 sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
@@ -245,7 +264,7 @@ sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches
  * kernel before it).  sg_scene_set_timing(scene, 1) enables and clears the
  * records, 0 disables.  sg_scene_kernel_time() waits for the recorded launches
  * of one kind (mode: 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps,
- * 3 eps_grad_fd rasterization) and returns their summed duration (ms) and
+ * 3 eps_grad_fd rasterization, 4 eps_grad_vjp_sparse) and returns their summed duration (ms) and
  * count. */
 sg_status sg_scene_set_timing(sg_scene* scene, int enable);
 sg_status sg_scene_kernel_time(sg_scene* scene, int mode, double* total_ms, int64_t* launches);

@@ -64,11 +64,18 @@ class Scene:
 
     def kernel_time(self, mode):
         """(summed ms, launches) of the traced column kernels of one kind:
-        'eps', 'vjp', 'geps' or 'fd'."""
+        'eps', 'vjp', 'geps', 'fd' or 'sparse'."""
         t = C.c_double()
         n = C.c_int64()
         check(lib().sg_scene_kernel_time(self.handle, _lib.MODE[mode], C.byref(t), C.byref(n)))
         return t.value, n.value
+
+    def sparse_reads(self):
+        """(sample, column step) pairs whose fields the last eps_grad_vjp_sparse
+        call read."""
+        n = C.c_int64()
+        check(lib().sg_scene_sparse_reads(self.handle, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "handle", None):
@@ -134,6 +141,17 @@ def eps_grad_vjp(scene, p, E, A, omega, grad=None, stream=None):
     fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
     g, gp, gdev = _grad_out(scene, pdev, grad, dev)
     check(lib().eps_grad_vjp(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), gp, gdev, _stream(stream)))
+    return g
+
+
+def eps_grad_vjp_sparse(scene, p, E, A, omega, grad=None, stream=None):
+    """eps_grad_vjp that reads the fields only where d eps / d p can be nonzero."""
+    dev = torch.device("cuda", scene.device)
+    pp, pdev, keep = _p_arg(scene, p)
+    fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_vjp_sparse(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), gp, gdev,
+                                    _stream(stream)))
     return g
 
 
@@ -232,6 +250,13 @@ class Server:
         v = [C.c_int64() for _ in range(4)]
         check(lib().serve_counters(self.handle, *[C.byref(x) for x in v]))
         return dict(zip(("completed", "batches", "max_batch", "bytes_in_use"), [x.value for x in v]))
+
+    def sparse_reads(self):
+        """(sample, column step) pairs whose fields the last eps_grad_vjp_sparse
+        call read."""
+        n = C.c_int64()
+        check(lib().sg_scene_sparse_reads(self.handle, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "handle", None):

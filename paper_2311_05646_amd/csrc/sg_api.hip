@@ -84,6 +84,7 @@ static void free_scene(sg_scene* s) {
         hipFree(s->d_work[i]);
     }
     hipFree(s->d_grad);
+    hipFree(s->d_nread);
     if (s->h_p) hipHostFree(s->h_p);
     if (s->h_grad) hipHostFree(s->h_grad);
     if (s->p_evt) hipEventDestroy(s->p_evt);
@@ -814,7 +815,8 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     sg_status rc = check_call(ctx, s);
     if (rc != SG_OK) return rc;
     if (!grad && s->n_params > 0) return fail(SG_E_INVALID, "grad is NULL");
-    if (mode == MODE_VJP_FIELDS) {
+    const bool fields = mode == MODE_VJP_FIELDS || mode == MODE_VJP_SPARSE;
+    if (fields) {
         if (!e_fwd || !e_adj) return fail(SG_E_INVALID, "field pointer arrays are NULL");
         for (int c = 0; c < s->ncomp; ++c)
             if (!e_fwd[c] || !e_adj[c]) return fail(SG_E_INVALID, "field plane %d is NULL", c);
@@ -833,7 +835,20 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     HIP_OK(launch_stage(sp, 1, st));
     KParams kp = column_params(s);
     kp.grad = g;
-    if (mode == MODE_VJP_FIELDS) {
+    if (mode == MODE_VJP_SPARSE) {
+        // its segments split only the steps where some class is nonzero, and
+        // each segment's block repeats the tile's in-plane work: a quarter of
+        // the dense split (unless the caller fixed it)
+        if (s->nseg == 0) {
+            kp.nseg = (kp.nseg + 3) / 4;
+            kp.seglen = ((s->nw + kp.nseg - 1) / kp.nseg + kGroup - 1) / kGroup * kGroup;
+            kp.nseg = (s->nw + kp.seglen - 1) / kp.seglen;
+        }
+        if (!s->d_nread) HIP_OK(hipMalloc((void**)&s->d_nread, kReadSlots * sizeof(unsigned long long)));
+        HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_nread), 0.0, kReadSlots, st));
+        kp.nread = s->d_nread;
+    }
+    if (fields) {
         for (int c = 0; c < kMaxComp; ++c) {
             const int cc = std::min(c, s->ncomp - 1);
             kp.ef[c] = (const float2*)e_fwd[cc];
@@ -852,6 +867,25 @@ extern "C" sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* s, const double* p, int
                                   void* stream) {
     return vjp_common(ctx, s, p, p_on_device, MODE_VJP_FIELDS, e_fwd, e_adj, omega, nullptr, grad, grad_on_device,
                       stream);
+}
+
+extern "C" sg_status eps_grad_vjp_sparse(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,
+                                         const void* const* e_fwd, const void* const* e_adj, double omega,
+                                         double* grad, int grad_on_device, void* stream) {
+    return vjp_common(ctx, s, p, p_on_device, MODE_VJP_SPARSE, e_fwd, e_adj, omega, nullptr, grad, grad_on_device,
+                      stream);
+}
+
+extern "C" sg_status sg_scene_sparse_reads(sg_scene* s, int64_t* pairs) {
+    if (!s || !pairs) return fail(SG_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    HIP_OK(hipSetDevice(s->ctx->device));
+    unsigned long long v[kReadSlots] = {};
+    if (s->d_nread) HIP_OK(hipMemcpy(v, s->d_nread, sizeof(v), hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (int i = 0; i < kReadSlots; ++i) n += (int64_t)v[i];
+    *pairs = n;
+    return SG_OK;
 }
 
 extern "C" sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,

@@ -316,4 +316,78 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
     return 0.0;
 }
 
+// ---- where the in-plane derivatives can be nonzero (sparse reverse mode)
+// d sigma / d t vanishes outside |t| < sigma_cut(kind) for every kind; the
+// slack covers evaluation-order differences between the value code here and
+// the partials code, so a sample is never taken as dead where a partial is
+// nonzero.
+constexpr double kSupportSlack = 1e-9;
+template <int SIGS>
+__device__ __forceinline__ bool sig_live(int kind, double t) {
+    if constexpr (SIGS == S_LIN) return fabs(t) < 0.5 + kSupportSlack;
+    else return fabs(t) < sigma_cut(kind) + kSupportSlack;
+}
+
+// prim_value of a polygon or a piecewise-linear boundary, and in *live
+// whether some in-plane partial of the primitive can be nonzero at the sample:
+// a partial with respect to one sigma argument is that argument's sigma'
+// times the product of the other factors, so it needs the argument inside
+// its support and every other factor nonzero.  The value is the one
+// prim_value returns (same operations, no early exits).
+template <int TYPES, int SIGS>
+__device__ __forceinline__ double prim_value_live(const DevPrim& pr, const double* __restrict__ fv,
+                                                  double uc, double uw, double vc, double vw, const GSeg* gs,
+                                                  bool& live) {
+    if constexpr ((TYPES & T_POLY) != 0) {
+        if (pr.type == SG_PRIM_POLY) {
+            const int N = pr.nvert;
+            const double* xs = fv + pr.f0;
+            const double* ys = xs + N;
+            double f = 1.0;
+            int nzero = 0;
+            bool any = false, zlive = false;
+            for (int i = 0; i < N; ++i) {
+                const int j = (i + 1 == N) ? 0 : i + 1;
+                const double ex = xs[j] - xs[i], ey = ys[j] - ys[i];
+                const double L = sqrt(ex * ex + ey * ey);
+                const double t = pr.k0 * ((ex * (vc - ys[i]) - ey * (uc - xs[i])) / L);
+                const double sv = sig_v<SIGS>(pr.sk0, t);
+                const bool l = sig_live<SIGS>(pr.sk0, t);
+                if (sv == 0.0) {
+                    ++nzero;
+                    zlive = l;
+                }
+                any = any || l;
+                f *= sv;
+            }
+            live = (nzero == 0) ? any : (nzero == 1 && zlive);
+            return f;
+        }
+    }
+    if constexpr ((TYPES & T_GCART) != 0) {
+        if (pr.type == SG_PRIM_GCART) {
+            const int M = pr.nvert;
+            const double kx = kval(pr.sm0, pr.k0, uw);
+            const double ta = kx * (uc - fv[pr.f0]), tb = kx * (fv[pr.f0 + 1] - uc);
+            const double rx = sig_v<SIGS>(pr.sk0, ta) * sig_v<SIGS>(pr.sk0, tb);
+            const GSeg sgm = *gs;
+            const int j = sgm.j;
+            const double t = sgm.t;
+            const double* yp = fv + pr.f0 + 2;
+            const double* ym = yp + M;
+            const double fp = (1.0 - t) * yp[j] + t * yp[j + 1];
+            const double fm = (1.0 - t) * ym[j] + t * ym[j + 1];
+            const double ky = kval(pr.sm1, pr.k1, vw);
+            const double tp = ky * (fp - vc), tm = ky * (vc - fm);
+            const double sp = sig_v<SIGS>(pr.sk1, tp), sm = sig_v<SIGS>(pr.sk1, tm);
+            const bool lx = sig_live<SIGS>(pr.sk0, ta) || sig_live<SIGS>(pr.sk0, tb);
+            live = (lx && sp * sm != 0.0) ||
+                   (rx != 0.0 && ((sig_live<SIGS>(pr.sk1, tp) && sm != 0.0) || (sig_live<SIGS>(pr.sk1, tm) && sp != 0.0)));
+            return rx * sp * sm;
+        }
+    }
+    live = false;
+    return 0.0;
+}
+
 }  // namespace sg

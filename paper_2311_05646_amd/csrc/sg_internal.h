@@ -14,8 +14,12 @@ constexpr int kMaxClasses = 8;
 constexpr int kBlock = 256;        // threads (= in-plane samples) per block
 constexpr int kCandCap = 2048;     // candidate primitives listed in LDS per pass
 constexpr int kZStage = 512;       // extrusion-table entries staged in LDS per chunk
+constexpr int kReadSlots = 256;    // partial counters of the sparse VJP's read statistic
 
-enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3 };
+// MODE_VJP_SPARSE: the fused VJP reading only the samples whose in-plane
+// derivatives do not all vanish and the column steps with a class at nonzero
+// extrusion (same result as MODE_VJP_FIELDS up to summation order).
+enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3, MODE_VJP_SPARSE = 4 };
 // Column-step codes written by k_stage, one per (component, w): bits 0-7 hold
 // the mask of classes whose extrusion factor is exactly 1 when every class
 // factor is exactly 0 or 1 (and the w-bound derivatives of classes with
@@ -159,6 +163,7 @@ struct KParams {
     int32_t pad;
     const float* geps;
     double* grad;
+    unsigned long long* nread;   // MODE_VJP_SPARSE: (sample, step) pairs whose fields were read, kReadSlots partial counts
 };
 
 // kernel launchers (sg_kernels.hip)

@@ -363,20 +363,72 @@ __device__ __forceinline__ double cand_value(const KParams& P, const PrimRec& c,
     return 0.0;
 }
 
+// cand_value, and in *live whether some in-plane partial of the candidate can
+// be nonzero at the sample (see prim_value_live): for a box, a bound's sigma
+// argument inside its support with the other axis' factor nonzero; for an
+// ellipse, the sample inside the annulus where the partials code evaluates
+// sigma' (widened by a relative 1e-9).
+template <int TYPES, int SIGS>
+__device__ __forceinline__ double cand_value_live(const KParams& P, const PrimRec& c, const double* __restrict__ fv,
+                                                  int comp, int u, double uc, double uw, double vc, double vw,
+                                                  bool& live) {
+    const DevPrim& pr = c.pr;
+    if constexpr ((TYPES & T_BOX) != 0) {
+        if (TYPES == T_BOX || pr.type == SG_PRIM_BOX) {
+            double ru = 1.0, rv = 1.0;
+            bool lu = false, lv = false;
+            if (pr.ubnd) {
+                const double k = kval(pr.sm0, pr.k0, uw);
+                const double ta = k * (uc - c.f[0]), tb = k * (c.f[1] - uc);
+                ru = sig_v<SIGS>(pr.sk0, ta) * sig_v<SIGS>(pr.sk0, tb);
+                lu = sig_live<SIGS>(pr.sk0, ta) || sig_live<SIGS>(pr.sk0, tb);
+            }
+            if (pr.vbnd) {
+                const double k = kval(pr.sm1, pr.k1, vw);
+                const double ta = k * (vc - c.f[2]), tb = k * (c.f[3] - vc);
+                rv = sig_v<SIGS>(pr.sk1, ta) * sig_v<SIGS>(pr.sk1, tb);
+                lv = sig_live<SIGS>(pr.sk1, ta) || sig_live<SIGS>(pr.sk1, tb);
+            }
+            live = (lu && rv != 0.0) || (lv && ru != 0.0);
+            return ru * rv;
+        }
+    }
+    if constexpr ((TYPES & T_ELL) != 0) {
+        if (pr.type == SG_PRIM_ELLIPSE) {
+            const double dx = (uc - c.f[0]) * pr.iax, dy = (vc - c.f[1]) * pr.iay;
+            const double rho2 = dx * dx + dy * dy;
+            const double r = c.f[2];
+            const double rhi = r + pr.reach0, rlo = r - pr.reach0;
+            live = rhi > 0.0 && rho2 < rhi * rhi * (1.0 + kSupportSlack) &&
+                   !(rlo > 0.0 && rho2 <= rlo * rlo * (1.0 - kSupportSlack));
+            if (rhi <= 0.0 || rho2 >= rhi * rhi) return 0.0;
+            if (rlo > 0.0 && rho2 <= rlo * rlo) return 1.0;
+            return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
+        }
+    }
+    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0)
+        return prim_value_live<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, uc, uw, vc, vw,
+                                                                 P.gseg + pr.gs0 + (int64_t)comp * P.nu + u, live);
+    live = false;
+    return 0.0;
+}
+
 // Sum of F_h over the candidates, per class, at (uc, vc).  When every
 // candidate of the tile fits one staging round, the records stay in s_rec for
 // the partials (*staged_all; *ncand of them).  after_stage() runs once, after
 // the first staging round and before any evaluation (the caller issues its
 // field loads there: vector loads return in order, so loads issued earlier
-// would hold up the scan's and the staging's).
-template <int NC, int TYPES, int SIGS, class Hook>
+// would hold up the scan's and the staging's).  With PROBE, *live tells
+// whether some candidate's in-plane partials can be nonzero at the sample.
+template <int NC, int TYPES, int SIGS, bool PROBE = false, class Hook>
 __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __restrict__ bbox,
                                              const PrimRec* __restrict__ prec, const double* __restrict__ fval,
                                              const Tile& T, int comp, int u, double uc, double uw, double vc,
                                              double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC],
-                                             int& ncand, bool& staged_all, Hook&& after_stage) {
+                                             int& ncand, bool& staged_all, Hook&& after_stage, bool* live = nullptr) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) F[c] = 0.0;
+    if constexpr (PROBE) *live = false;
     ncand = 0;
     staged_all = false;
     bool hooked = false;
@@ -397,7 +449,14 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
             if (!T.wave_live) continue;
             for (int j = 0; j < nj; ++j) {
                 if (!wave_meets(T, s_rec[j].bb)) continue;
-                const double f = cand_value<TYPES, SIGS>(P, s_rec[j], fval, comp, u, uc, uw, vc, vw);
+                double f;
+                if constexpr (PROBE) {
+                    bool l;
+                    f = cand_value_live<TYPES, SIGS>(P, s_rec[j], fval, comp, u, uc, uw, vc, vw, l);
+                    *live = *live || l;
+                } else {
+                    f = cand_value<TYPES, SIGS>(P, s_rec[j], fval, comp, u, uc, uw, vc, vw);
+                }
                 add_to_class(F, s_rec[j].pr.cls, f);
             }
         }
@@ -817,6 +876,34 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, 
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, n, 0x00020000);
 }
 
+// First and last group of a component whose code is nonzero (some class at
+// nonzero extrusion, or a general step); ghi < glo when there is none.  Every
+// wavefront computes it (the codes are few and cached), up to 256 codes per
+// memory round trip.
+__device__ __forceinline__ void live_groups(const uint32_t* __restrict__ gc, int ngw, int& glo, int& ghi) {
+    const int lane = threadIdx.x & 63;
+    glo = ngw;
+    ghi = -1;
+    for (int base = 0; base < ngw; base += 256) {
+        uint32_t c[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = base + k * 64 + lane;
+            c[k] = (i < ngw) ? gc[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t m = __ballot(c[k] != 0u);
+            if (m != 0) {
+                glo = min(glo, base + k * 64 + __ffsll((unsigned long long)m) - 1);
+                ghi = max(ghi, base + k * 64 + 63 - __clzll((long long)m));
+            }
+        }
+    }
+    glo = uniform_int(glo);
+    ghi = uniform_int(ghi);
+}
+
 // One block = one in-plane tile of kBlock samples (tu x tv) of one component
 // and one segment [w0, w1) of the column (w0 a multiple of kGroup); one thread
 // per sample.
@@ -837,10 +924,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, 
 template <int MODE, int TREE, int TYPES, int SIGS>
 __device__ __forceinline__ void column_body(const KParams& P, int b) {
     constexpr int NC = tree_nc(TREE);
-    constexpr bool VJP = (MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
+    constexpr bool SPARSE = (MODE == MODE_VJP_SPARSE);
+    constexpr bool FIELDS = (MODE == MODE_VJP_FIELDS) || SPARSE;
+    constexpr bool VJP = FIELDS || (MODE == MODE_VJP_GEPS);
     constexpr int U = (MODE == MODE_VJP_GEPS) ? 8 : 4;      // steps per load set (multiple of kGroup)
     constexpr int NG = U / kGroup;
-    constexpr int EB = (MODE == MODE_VJP_FIELDS) ? 8 : 4;    // bytes per sample of the streamed planes
+    constexpr int EB = FIELDS ? 8 : 4;                       // bytes per sample of the streamed planes
     __shared__ int s_cand[kCandCap];
     __shared__ int s_cnt[kScanCnt];
     __shared__ PrimRec s_rec[kStageRec];
@@ -853,13 +942,26 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     const TileGeom G = tile_geom(P, b / P.nseg);
     const int comp = G.comp;
     const bool act = G.act;
-    const int w0 = seg * P.seglen;
-    const int w1 = min(w0 + P.seglen, P.nw);
+    const int ngw = (P.nw + kGroup - 1) / kGroup;
+    int w0 = seg * P.seglen;
+    int w1 = min(w0 + P.seglen, P.nw);
+    if constexpr (SPARSE) {
+        // the segments split the component's steps from its first to its last
+        // group with some class at nonzero extrusion; a block whose segment
+        // is empty has nothing to add
+        int glo, ghi;
+        live_groups(P.gcode + (int64_t)comp * ngw, ngw, glo, ghi);
+        if (ghi < glo) return;
+        const int lw0 = glo * kGroup, lw1 = min(P.nw, (ghi + 1) * kGroup);
+        const int slen = ((lw1 - lw0 + P.nseg - 1) / P.nseg + kGroup - 1) / kGroup * kGroup;
+        w0 = lw0 + seg * slen;
+        w1 = min(w0 + slen, lw1);
+        if (w0 >= w1) return;
+    }
     const int64_t b0 = (int64_t)G.uu + (int64_t)G.vv * P.sv;     // offset within a column plane
     const uint32_t lane_off = (uint32_t)b0 * EB;
     const int64_t plane_bytes = P.plane * EB;
     const int64_t step_bytes = P.sw * EB;
-    const int ngw = (P.nw + kGroup - 1) / kGroup;
     const ConstU32 gcode = const_space<ConstU32>(P.gcode + (int64_t)comp * ngw);
     const ConstU32 gcode2 = const_space<ConstU32>(P.gcode2 + (int64_t)comp * ngw);
     const ConstU32 code = const_space<ConstU32>(P.code + (int64_t)comp * P.nw);
@@ -892,7 +994,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     // touching memory.
     const char* plane0 = nullptr;
     const char* plane1 = nullptr;
-    if constexpr (MODE == MODE_VJP_FIELDS) {
+    if constexpr (FIELDS) {
         plane0 = reinterpret_cast<const char*>(P.ef[comp]);
         plane1 = reinterpret_cast<const char*>(P.ea[comp]);
     } else if constexpr (MODE == MODE_VJP_GEPS) {
@@ -905,17 +1007,36 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         uint32_t gc[NG];
     };
     Set sa, sb;
+    // Sparse: the lane offset the loads use (dead lanes of a live wavefront
+    // read the first live lane's address, which adds no cache lines), the
+    // group codes of the next set (prefetched one set ahead, so the zero-length
+    // resource of a set whose groups all have every class at zero extrusion is
+    // known without a wait), and the steps read.
+    uint32_t lane_ld = lane_off;
+    uint32_t nextc[NG];
+    int nsteps = 0;
     auto load_set = [&](Set& st, int w) {
         const int64_t off = (int64_t)w * step_bytes;
-        const int64_t len = min(plane_bytes - off, (int64_t)(w1 - w) * step_bytes);
-        if constexpr (MODE == MODE_VJP_FIELDS) {
+        int64_t len = min(plane_bytes - off, (int64_t)(w1 - w) * step_bytes);
+        if constexpr (SPARSE) {
+            bool dead = true;
+#pragma unroll
+            for (int h = 0; h < NG; ++h) {
+                st.gc[h] = nextc[h];
+                dead = dead && (nextc[h] == 0u);
+                nextc[h] = group_code(w + U + h * kGroup);
+            }
+            if (dead) len = 0;
+            if (len > 0) nsteps += min(U, w1 - w);
+        }
+        if constexpr (FIELDS) {
             const __amdgpu_buffer_rsrc_t re = buffer_rsrc(plane0 + off, len);
             const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(plane1 + off, len);
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                st.e[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(re, lane_off,
+                st.e[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(re, lane_ld,
                                                                                       (int)(q * step_bytes), 0));
-                st.a[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(ra, lane_off,
+                st.a[q] = __builtin_bit_cast(v2f, __builtin_amdgcn_raw_buffer_load_b64(ra, lane_ld,
                                                                                       (int)(q * step_bytes), 0));
             }
         } else if constexpr (MODE == MODE_VJP_GEPS) {
@@ -925,14 +1046,16 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                 st.g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, lane_off,
                                                                                         (int)(q * step_bytes), 0));
         }
+        if constexpr (!SPARSE) {
 #pragma unroll
-        for (int h = 0; h < NG; ++h) st.gc[h] = group_code(w + h * kGroup);
+            for (int h = 0; h < NG; ++h) st.gc[h] = group_code(w + h * kGroup);
+        }
     };
     // both sets go out once the candidates are staged, so 2 U steps are in
     // flight while the in-plane sums are evaluated (every segment holds at
     // least one step)
     auto first_loads = [&]() {
-        if constexpr (VJP) {
+        if constexpr (VJP && !SPARSE) {
             load_set(sa, w0);
             load_set(sb, w0 + U);
         }
@@ -942,8 +1065,9 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     double F[NC], F2[NC];
     int ncand = 0;
     bool staged_all = false;
-    inplane_sums<NC, TYPES, SIGS>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand, s_cnt,
-                                  s_rec, F, ncand, staged_all, first_loads);
+    bool live = true;    // sparse: some in-plane partial of the sample can be nonzero
+    inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
+                                          s_cnt, s_rec, F, ncand, staged_all, first_loads, &live);
     if constexpr (MODE == MODE_FD) {
         int nc2;
         bool sa2;
@@ -1021,7 +1145,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) A[c] = Blo[c] = Bhi[c] = 0.0f;
         // g of one step times gscale is d F / d eps at that sample, times deps
-        const float gscale = ((MODE == MODE_VJP_FIELDS) ? P.two_omega : 1.0f) * (float)P.deps;
+        const float gscale = (FIELDS ? P.two_omega : 1.0f) * (float)P.deps;
         // A_c += gd * r_(group of c) * Z_c (and the w-bound partials on general steps)
         auto accumulate = [&](const Comp& o, const double (&Z)[NC], float gd, int w, bool general) {
             const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
@@ -1060,7 +1184,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const int i = h * kGroup + q;
-                    if constexpr (MODE == MODE_VJP_FIELDS)
+                    if constexpr (FIELDS)
                         g[q] = st.e[i].x * st.a[i].y + st.e[i].y * st.a[i].x;   // Im(E Eadj)
                     else
                         g[q] = st.g[i];
@@ -1097,14 +1221,46 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         // 0): a load under a branch makes the wait before the next set drain
         // every outstanding load, which turns the double buffer back into
         // load-wait-compute.
-        const int nset = (w1 - w0 + U - 1) / U;
-        for (int si = 0; si < nset; si += 2) {
-            process(sa, w0 + si * U);
-            load_set(sa, w0 + (si + 2) * U);
-            process(sb, w0 + (si + 1) * U);
-            load_set(sb, w0 + (si + 3) * U);
+        bool stream = true;
+        uint64_t lm = 0;    // sparse: live lanes of the wavefront
+        if constexpr (SPARSE) {
+            // columns with column-axis parameters feed their bound partials
+            // wherever F_c is nonzero: every sample is read then
+            bool wpar = false;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) wpar = wpar || (c < P.nclass && P.cls_wparam[c]);
+            live = act && (live || wpar);
+            lm = __ballot(live);
+            stream = lm != 0;
+            if (stream) {
+                const int lead = uniform_int(__ffsll((unsigned long long)lm) - 1);
+                const uint32_t lead_off = (uint32_t)__builtin_amdgcn_readlane((int)lane_off, lead);
+                lane_ld = live ? lane_off : lead_off;
+#pragma unroll
+                for (int h = 0; h < NG; ++h) nextc[h] = group_code(w0 + h * kGroup);
+                load_set(sa, w0);
+                load_set(sb, w0 + U);
+            }
         }
-        flush();
+        if (stream) {
+            const int nset = (w1 - w0 + U - 1) / U;
+            for (int si = 0; si < nset; si += 2) {
+                process(sa, w0 + si * U);
+                load_set(sa, w0 + (si + 2) * U);
+                process(sb, w0 + (si + 1) * U);
+                load_set(sb, w0 + (si + 3) * U);
+            }
+            flush();
+        }
+        if constexpr (SPARSE) {
+            // spread over kReadSlots counters: one address taking an atomic
+            // from every wavefront of the grid serializes them
+            if (P.nread != nullptr && (tid & 63) == 0 && nsteps > 0)
+                atomicAdd(P.nread + ((blockIdx.x * (kBlock / 64) + wave) & (kReadSlots - 1)),
+                          (unsigned long long)__popcll(lm) * (unsigned long long)nsteps);
+            // nothing to add from a block with no live sample
+            if (!__syncthreads_or(live ? 1 : 0)) return;
+        }
 
         // ---- 3. partials of the column-axis bounds of each class (F_c times
         // the w-bound sums), then the in-plane partials
@@ -1118,7 +1274,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
             }
         }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sA[c * kBlock + tid] = act ? A[c] : 0.0f;
+        for (int c = 0; c < NC; ++c) sA[c * kBlock + tid] = (act && live) ? A[c] : 0.0f;
         s_lat[tid] = G.uc;
         s_lat[kBlock + tid] = G.uw;
         s_lat[2 * kBlock + tid] = G.vc;
@@ -1329,6 +1485,7 @@ hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hip
         case MODE_EPS: return launch_mode<MODE_EPS>(tree, variant, kp, st);
         case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(tree, variant, kp, st);
         case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(tree, variant, kp, st);
+        case MODE_VJP_SPARSE: return launch_mode<MODE_VJP_SPARSE>(tree, variant, kp, st);
         default: return launch_mode<MODE_FD>(tree, variant, kp, st);
     }
 }

@@ -62,6 +62,7 @@ struct sg_scene {
     uint32_t* d_gcode[2] = {nullptr, nullptr};  // group codes
     double* d_grad = nullptr;
     float* d_work[2] = {nullptr, nullptr};
+    unsigned long long* d_nread = nullptr;   // sparse VJP: (sample, step) pairs read
     double* h_p = nullptr;            // pinned staging
     double* h_grad = nullptr;
     hipEvent_t p_evt = nullptr;

@@ -28,7 +28,8 @@ def _declared():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for n in ("eps_build", "eps_grad_vjp", "eps_grad_vjp_geps", "eps_grad_fd", "sg_scene_create"):
+    for n in ("eps_build", "eps_grad_vjp", "eps_grad_vjp_sparse", "eps_grad_vjp_geps", "eps_grad_fd",
+              "sg_scene_create"):
         assert n in names
 
 

@@ -102,6 +102,22 @@ def test_vjp_sampled_params(name, nk):
 
 
 @pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def test_vjp_sparse_full_size(name):
+    """The sparse VJP equals the dense one (pinned to the oracle above) up to
+    the order of its sums, at full size and in the launch configuration the
+    benchmark times."""
+    cfg, sc, E, A, Ed, Ad = _setup(name)
+    g_dense = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    g_sparse = api().eps_grad_vjp_sparse(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    reads = sc.sparse_reads()
+    total = int(np.prod(sc.shape))
+    print(f"[fullsize] {name} sparse vs dense rel {rel(g_sparse, g_dense):.3e}, "
+          f"read {reads} of {total} samples", flush=True)
+    assert rel(g_sparse, g_dense) <= 1e-6
+    assert 0 < reads <= total
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
 def test_fd_matches_vjp_full_size(name):
     cfg, sc, E, A, Ed, Ad = _setup(name)
     g_vjp = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])

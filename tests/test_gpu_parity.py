@@ -43,6 +43,32 @@ def test_vjp_fields(name):
 
 
 @pytest.mark.parametrize("name", CASES)
+def test_vjp_sparse(name):
+    """The sparse VJP against the oracle, and against the dense VJP: the
+    samples and steps it skips carry exactly zero partials, so the two differ
+    only in the order of the floating-point sums (its column segments split
+    the steps where some class is nonzero, so its FP32 column sums group the
+    steps differently; the same bound as for a change of launch shape)."""
+    cfg = config(name)
+    print(f"[sparse] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    Ed, Ad = to_dev(E), to_dev(A)
+    got = api().eps_grad_vjp_sparse(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    reads = sc.sparse_reads()
+    dense = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], S.sensitivity(E, A, cfg["omega"]))
+    total = int(np.prod(sc.shape))
+    print(f"[sparse] {name}: read {reads} of {total} samples", flush=True)
+    assert rel(got, ref) <= GRAD_TOL
+    assert rel(got, dense) <= 1e-6
+    assert 0 < reads <= total
+    # shapes cover a small part of these grids
+    if name in ("c2_small", "c3_small", "c4_small"):
+        assert reads < total
+
+
+@pytest.mark.parametrize("name", CASES)
 def test_vjp_geps(name):
     cfg = config(name)
     print(f"[geps] {name}", flush=True)
@@ -114,6 +140,7 @@ def test_launch_shape_independence(name):
             sc.set_launch(bx, seg)
             assert torch.equal(api().eps_build(sc, cfg["p"]).cpu(), base_e), (bx, seg)
             assert rel(api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"]), base_g) <= 1e-6, (bx, seg)
+            assert rel(api().eps_grad_vjp_sparse(sc, cfg["p"], Ed, Ad, cfg["omega"]), base_g) <= 1e-6, (bx, seg)
     sc.set_launch(0, 0)
 
 
