@@ -76,9 +76,15 @@ enum {
  *                                               constant beyond the end vertices;
  *                                               consts: x_1 < ... < x_M; sigma[0] x-range,
  *                                               sigma[1] y boundary, sigma[2] z
+ *   SG_PRIM_POLAR   x0 y0 R0 c_1..c_N s_1..s_N z0 z1   (nvert = N, 1 <= N <= 29)
+ *                                               GeneralPolar2D with the Fourier radius of
+ *                                               eq:PSGCboundary: sigma_k(R(theta) - r), r and theta
+ *                                               the polar coordinates about (x0, y0),
+ *                                               R = R0 + sum_n c_n cos(n theta + pi) + s_n sin(n theta + pi);
+ *                                               sigma[0] boundary (FIXED k), sigma[2] z
  * z0 z1 are the extrusion along z (Rect1D in z), used when bounded[2] != 0.
  * In 2D scenes (dim = 2) nothing may be bounded along z. */
-enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3 };
+enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3, SG_PRIM_POLAR = 4 };
 
 /* sigma_k kinds (Tab. nonlinearfunctions).  sigmoid and erf are taken as exactly
  * 0 / 1 beyond |k x| = 24 / 6 (tails below 4e-11 / 2e-17). */
@@ -261,8 +267,11 @@ sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches
 /* Kernel tracing.  With timing enabled the scene records a pair of HIP events
  * on the call's stream around every launch of its column kernel (the kernel
  * that evaluates eps or its reverse mode; a call also runs a small staging
- * kernel before it).  sg_scene_set_timing(scene, 1) enables and clears the
- * records, 0 disables.  sg_scene_kernel_time() waits for the recorded launches
+ * kernel before it).  sg_scene_set_timing(scene, k) with k >= 1 clears the
+ * records and then brackets the 1st, (k+1)-th, (2k+1)-th ... launch of each
+ * kind (an event pair adds a few microseconds of device time to its launch,
+ * so a period above 1 keeps a timed loop close to its untimed speed); 0
+ * disables.  sg_scene_kernel_time() waits for the recorded launches
  * of one kind (mode: 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps,
  * 3 eps_grad_fd rasterization, 4 eps_grad_vjp_sparse) and returns their summed duration (ms) and
  * count. */

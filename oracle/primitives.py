@@ -170,7 +170,51 @@ def gcart(prim, vals, pts):
     return f * zv, out
 
 
-EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart}
+def polar(prim, vals, pts):
+    """GeneralPolar2D with the Fourier radius of eq:PSGCboundary (Tab.
+    autodiffgeo; Sec. "Experimental choice of nonlinear function for Prop. 2"):
+    sigma_k(R(theta) - r) with r, theta the polar coordinates of the sample
+    about (x0, y0) and R(theta) = R0 + sum_n c_n cos(n theta + pi) + s_n
+    sin(n theta + pi), n = 1..N.  theta = atan2(y - y0, x - x0) (the paper's
+    arctan of the ratio, over the full turn).  Fields x0 y0 R0 c_1..c_N
+    s_1..s_N z0 z1; nvert = N.  At the center (r = 0) theta is taken as 0 and
+    the center partials as 0."""
+    N = prim["nvert"]
+    x0, y0, R0 = vals[0], vals[1], vals[2]
+    cs = [vals[3 + n] for n in range(N)]
+    ss = [vals[3 + N + n] for n in range(N)]
+    (xc, xw), (yc, _) = pts["x"], pts["y"]
+    dx, dy = xc - x0, yc - y0
+    r = np.hypot(dx, dy)
+    th = np.arctan2(dy, dx)
+    R = R0 * np.ones(np.broadcast(xc, yc).shape)
+    dR = np.zeros_like(R)            # d R / d theta
+    basis_c, basis_s = [], []
+    for n in range(1, N + 1):
+        bc, bs = np.cos(n * th + np.pi), np.sin(n * th + np.pi)
+        basis_c.append(bc)
+        basis_s.append(bs)
+        R = R + cs[n - 1] * bc + ss[n - 1] * bs
+        dR = dR + n * (-cs[n - 1] * bs + ss[n - 1] * bc)
+    kind = prim["sigma"][0][0]
+    k = kval(prim["sigma"][0], xw)
+    t = k * (R - r)
+    f = sigma(kind, t)
+    df = k * dsigma(kind, t)           # d f / d (R - r)
+    safe = np.where(r > 0.0, r, 1.0)
+    # d r / d x0 = -dx / r, d theta / d x0 = dy / r^2 (and the y0 pair)
+    d_x0 = np.where(r > 0.0, dR * dy / (safe * safe) + dx / safe, 0.0)
+    d_y0 = np.where(r > 0.0, -dR * dx / (safe * safe) + dy / safe, 0.0)
+    zv, zparts = _z_factor(prim, vals, pts, 3 + 2 * N)
+    g = df * zv
+    out = [(0, g * d_x0), (1, g * d_y0), (2, g)]
+    out += [(3 + n, g * basis_c[n]) for n in range(N)]
+    out += [(3 + N + n, g * basis_s[n]) for n in range(N)]
+    out += [(fi, f * d) for fi, d in zparts]
+    return f * zv, out
+
+
+EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart, "polar": polar}
 
 
 def evaluate(prim, vals, pts):
@@ -204,6 +248,13 @@ def bbox(prim, vals, wmax):
         lo[0], hi[0] = x0 - rr * ax, x0 + rr * ax
         lo[1], hi[1] = y0 - rr * ay, y0 + rr * ay
         zf = 3
+    elif t == "polar":
+        # R(theta) <= R0 + sum |c_n| + |s_n|
+        N = prim["nvert"]
+        rmax = max(vals[2] + sum(abs(v) for v in vals[3:3 + 2 * N]), 0.0) + reach(prim["sigma"][0], 0)
+        lo[0], hi[0] = vals[0] - rmax, vals[0] + rmax
+        lo[1], hi[1] = vals[1] - rmax, vals[1] + rmax
+        zf = 3 + 2 * N
     elif t == "poly":
         N = prim["nvert"]
         rr = reach(prim["sigma"][0], 0)

@@ -57,10 +57,11 @@ class Scene:
     def set_launch(self, block_x=0, col_segments=0):
         check(lib().sg_scene_set_launch(self.handle, int(block_x), int(col_segments)))
 
-    def set_timing(self, enable=True):
-        """Trace the column kernel of every later call (HIP events on the
-        call's stream); enabling clears earlier records."""
-        check(lib().sg_scene_set_timing(self.handle, int(bool(enable))))
+    def set_timing(self, enable=True, every=1):
+        """Trace the column kernel of later calls (HIP events on the call's
+        stream): every `every`-th launch of each kind; enabling clears
+        earlier records."""
+        check(lib().sg_scene_set_timing(self.handle, int(every) if enable else 0))
 
     def kernel_time(self, mode):
         """(summed ms, launches) of the traced column kernels of one kind:

@@ -114,6 +114,7 @@ static int expected_nfield(const sg_prim_desc& p) {
         case SG_PRIM_ELLIPSE: return 5;
         case SG_PRIM_POLY: return 2 * p.nvert + 2;
         case SG_PRIM_GCART: return 2 * p.nvert + 4;
+        case SG_PRIM_POLAR: return 2 * p.nvert + 5;
         default: return -1;
     }
 }
@@ -124,6 +125,7 @@ static int zfield(const sg_prim_desc& p) {
         case SG_PRIM_BOX: return 4;
         case SG_PRIM_ELLIPSE: return 3;
         case SG_PRIM_POLY: return 2 * p.nvert;
+        case SG_PRIM_POLAR: return 2 * p.nvert + 3;
         default: return 2 * p.nvert + 2;
     }
 }
@@ -176,6 +178,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         if (nf < 0) return fail(SG_E_INVALID, "primitive %d: unknown type %d", i, p.type);
         if (p.type == SG_PRIM_POLY && (p.nvert < 3 || p.nvert > 64)) return fail(SG_E_INVALID, "poly %d: nvert", i);
         if (p.type == SG_PRIM_GCART && (p.nvert < 2 || p.nvert > 100000)) return fail(SG_E_INVALID, "gcart %d: nvert", i);
+        if (p.type == SG_PRIM_POLAR && (p.nvert < 1 || p.nvert > 29)) return fail(SG_E_INVALID, "polar %d: order", i);
         if (p.nfield != nf) return fail(SG_E_INVALID, "primitive %d: nfield %d, expected %d", i, p.nfield, nf);
         if (p.field_off < 0 || p.field_off + nf > d->nfield) return fail(SG_E_INVALID, "primitive %d: fields", i);
         const int nc = p.type == SG_PRIM_ELLIPSE ? 2 : (p.type == SG_PRIM_GCART ? p.nvert : 0);
@@ -188,7 +191,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             if (used && bnd && !valid_sigma(p.sigma[a])) return fail(SG_E_INVALID, "primitive %d: sigma[%d]", i, a);
         }
         if (d->dim == 2 && p.bounded[2]) return fail(SG_E_INVALID, "primitive %d: bounded along z in a 2D scene", i);
-        if ((p.type == SG_PRIM_ELLIPSE || p.type == SG_PRIM_POLY) && p.sigma[0].kmode != SG_K_FIXED)
+        if ((p.type == SG_PRIM_ELLIPSE || p.type == SG_PRIM_POLY || p.type == SG_PRIM_POLAR) &&
+            p.sigma[0].kmode != SG_K_FIXED)
             return fail(SG_E_INVALID, "primitive %d: radial/oblique boundary needs a FIXED k", i);
         if (p.type == SG_PRIM_ELLIPSE) {
             const double ax = d->consts[p.const_off], ay = d->consts[p.const_off + 1];
@@ -504,10 +508,10 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
                 if (p.type == SG_PRIM_GCART) smask |= sigma_bit(p.sigma[1].kind);
             }
         }
-        const int vt[3] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL};
-        const int vs[3] = {S_LIN, S_LIN, S_LIN | S_SIGMOID};
+        const int vt[4] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL, T_BOX | T_POLAR};
+        const int vs[4] = {S_LIN, S_LIN, S_LIN | S_SIGMOID, S_LIN | S_SIGMOID};
         s->variant = VAR_ALL;
-        for (int v = 0; v < 3; ++v)
+        for (int v = 0; v < 4; ++v)
             if ((tmask & ~vt[v]) == 0 && (smask & ~vs[v]) == 0) { s->variant = v; break; }
         // op-tree layout
         auto plain_union = [&](int g) { return groups[g].op == SG_OP_UNION || groups[g].nmember == 1; };
@@ -559,6 +563,18 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         e = hipMemcpy(s->d_consts, d->consts, d->nconst * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess && !gseg.empty())
         e = hipMemcpy(s->d_gseg, gseg.data(), gseg.size() * sizeof(GSeg), hipMemcpyHostToDevice);
+    // static extrusion tables: one stage launch with no primitive, on the null
+    // stream, finished before the scene is returned
+    s->static_w = true;
+    for (const DevClass& c : s->classes)
+        if (c.bounded && (s->fields[c.flo].idx >= 0 || s->fields[c.fhi].idx >= 0)) s->static_w = false;
+    if (e == hipSuccess && s->static_w) {
+        StageParams sp = stage_params(s, s->d_p);
+        sp.nprim = 0;
+        sp.tables = 1;
+        e = launch_stage(sp, 1, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    }
     if (e != hipSuccess) {
         free_scene(s);
         return fail(e == hipErrorOutOfMemory ? SG_E_NOMEM : SG_E_DEVICE, "sg_scene_create: %s", hipGetErrorString(e));
@@ -637,6 +653,7 @@ StageParams sg::stage_params(sg_scene* s, const double* dp) {
         sp.ww[c] = s->d_lat + s->lat_off[cc][5];
     }
     sp.nfield = (int)s->nfield;
+    sp.tables = s->static_w ? 0 : 1;
     sp.zero_ptr = nullptr;
     sp.zero_n = 0;
     return sp;
@@ -707,11 +724,11 @@ KParams sg::column_params(sg_scene* s) {
     kp.fval2 = s->d_fval[1];
     kp.bbox2 = s->d_bbox[1];
     kp.prec2 = s->d_prec[1];
-    kp.ztab2 = s->d_ztab[1];
+    kp.ztab2 = s->d_ztab[s->static_w ? 0 : 1];
     kp.code = s->d_code[0];
-    kp.code2 = s->d_code[1];
+    kp.code2 = s->d_code[s->static_w ? 0 : 1];
     kp.gcode = s->d_gcode[0];
-    kp.gcode2 = s->d_gcode[1];
+    kp.gcode2 = s->d_gcode[s->static_w ? 0 : 1];
     return kp;
 }
 
@@ -747,7 +764,7 @@ static hipError_t take_event(sg_scene* s, hipEvent_t* e) {
 
 // Launches the column kernel, bracketed by events when tracing is on.
 static sg_status run_column(sg_scene* s, int mode, const KParams& kp, hipStream_t st) {
-    if (!s->timing) {
+    if (!s->timing || (s->launches[mode & 7]++ % s->timing) != 0) {
         HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));
         return SG_OK;
     }
@@ -771,7 +788,9 @@ extern "C" sg_status sg_scene_set_timing(sg_scene* s, int enable) {
         s->evpool.push_back(r.b);
     }
     s->recs.clear();
-    s->timing = enable != 0;
+    if (enable < 0) return fail(SG_E_INVALID, "sg_scene_set_timing: negative period");
+    s->timing = enable;
+    for (auto& n : s->launches) n = 0;
     return SG_OK;
 }
 

@@ -30,7 +30,7 @@ __host__ __device__ inline double sigma_cut(int kind) {
 // kinds a kernel instantiation handles.  Scenes are dispatched to the smallest
 // instantiation that covers them, so the common kernels carry no code for
 // primitives or transcendental functions they never see.
-enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_ALL = 15 };
+enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_POLAR = 16, T_ALL = 31 };
 enum : int { S_SIGMOID = 1, S_ERF = 2, S_SIN = 4, S_LIN = 8, S_QUAD = 16, S_ALL = 31 };
 
 // ---- one function per kind: value, and value + d/dt
@@ -256,6 +256,35 @@ __device__ __forceinline__ void gcart_segment(const double* __restrict__ xv, int
     t = fmin(1.0, fmax(0.0, tt));
 }
 
+// Fourier radius of eq:PSGCboundary at the sample's polar angle about the
+// center, R(theta) = R0 - sum_n (c_n cos n theta + s_n sin n theta) (the pi
+// shift flips both signs), with cos n theta, sin n theta by repeated rotation
+// from cos theta = dx / r, sin theta = dy / r (theta = 0 at the center); and
+// the sigma argument k (R - r).  *dR gets d R / d theta when asked for.
+__device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __restrict__ fv, double uc, double vc,
+                                            double* r_out = nullptr, double* c1_out = nullptr,
+                                            double* s1_out = nullptr, double* dR = nullptr) {
+    const int N = pr.nvert;
+    const double* f = fv + pr.f0;
+    const double dx = uc - f[0], dy = vc - f[1];
+    const double r = sqrt(dx * dx + dy * dy);
+    const double c1 = r > 0.0 ? dx / r : 1.0, s1 = r > 0.0 ? dy / r : 0.0;
+    double R = f[2], d = 0.0, cn = 1.0, sn = 0.0;
+    for (int n = 1; n <= N; ++n) {
+        const double c = cn * c1 - sn * s1;
+        sn = sn * c1 + cn * s1;
+        cn = c;
+        const double a = f[2 + n], b = f[2 + N + n];
+        R -= a * cn + b * sn;
+        d += (double)n * (a * sn - b * cn);
+    }
+    if (r_out) *r_out = r;
+    if (c1_out) *c1_out = c1;
+    if (s1_out) *s1_out = s1;
+    if (dR) *dR = d;
+    return pr.k0 * (R - r);
+}
+
 // In-plane factor F(u, v) of a primitive (value only).  gs: the sample's entry
 // of the primitive's segment table (piecewise-linear boundaries only).
 template <int TYPES, int SIGS>
@@ -312,6 +341,9 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
             const double ky = kval(pr.sm1, pr.k1, vw);
             return rx * sig_v<SIGS>(pr.sk1, ky * (fp - vc)) * sig_v<SIGS>(pr.sk1, ky * (vc - fm));
         }
+    }
+    if constexpr ((TYPES & T_POLAR) != 0) {
+        if (pr.type == SG_PRIM_POLAR) return sig_v<SIGS>(pr.sk0, polar_arg(pr, fv, uc, vc));
     }
     return 0.0;
 }
@@ -384,6 +416,13 @@ __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const doubl
             live = (lx && sp * sm != 0.0) ||
                    (rx != 0.0 && ((sig_live<SIGS>(pr.sk1, tp) && sm != 0.0) || (sig_live<SIGS>(pr.sk1, tm) && sp != 0.0)));
             return rx * sp * sm;
+        }
+    }
+    if constexpr ((TYPES & T_POLAR) != 0) {
+        if (pr.type == SG_PRIM_POLAR) {
+            const double t = polar_arg(pr, fv, uc, vc);
+            live = sig_live<SIGS>(pr.sk0, t);
+            return sig_v<SIGS>(pr.sk0, t);
         }
     }
     live = false;

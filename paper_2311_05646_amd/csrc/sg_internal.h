@@ -30,7 +30,7 @@ constexpr uint32_t kCodeGeneral = 1u << 16;
 constexpr int kGroup = 4;    // the stage kernel and the stream kernel's group paths assume 4
 enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
 // kernel feature variants (primitive types x in-plane sigma kinds), smallest first
-enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_ALL = 3 };
+enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_POLAR_SIGMOID = 3, VAR_ALL = 4 };
 // op-tree layouts compiled into the column kernel: one union over 1 or 2
 // extrusion classes; the difference of two unions over (1, 1) or (1, 2)
 // classes; anything else through the generic composition (4 or 8 classes).
@@ -51,7 +51,7 @@ struct DevPrim {
     int32_t type;          // SG_PRIM_*
     int32_t cls;           // extrusion class
     int32_t f0;            // first field of the primitive (flat field array)
-    int32_t nvert;         // POLY / GCART vertices
+    int32_t nvert;         // POLY / GCART vertices, POLAR Fourier order
     int32_t c0;            // first constant
     int32_t ubnd, vbnd;    // BOX: bounded along u / v
     int32_t fu0, fu1;      // BOX: fields of the u bounds
@@ -117,7 +117,7 @@ struct StageParams {
     const double* wc[kMaxComp];  // column-axis sample centers / widths per component
     const double* ww[kMaxComp];
     int32_t nfield;
-    int32_t pad;
+    int32_t tables;              // write the extrusion tables and codes (0: the scene's are static)
     double* zero_ptr;            // zeroed by variant 0 (gradient accumulator)
     int64_t zero_n;
 };

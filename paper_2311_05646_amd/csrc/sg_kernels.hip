@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             case SG_PRIM_BOX: nf = 6; break;
             case SG_PRIM_ELLIPSE: nf = 5; break;
             case SG_PRIM_POLY: nf = 2 * pr.nvert + 2; break;
+            case SG_PRIM_POLAR: nf = 2 * pr.nvert + 5; break;
             default: nf = 2 * pr.nvert + 4; break;
         }
         // lane i resolves fields f0 + i, f0 + i + 64, ...; the first one stays
@@ -125,6 +126,13 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             }
             if (__ballot(open) != 0) b = make_double4(-inf, inf, -inf, inf);
             else b = make_double4(wave_min(xlo), wave_max(xhi), wave_min(ylo), wave_max(yhi));
+        } else if (pr.type == SG_PRIM_POLAR) {
+            // R(theta) <= R0 + sum_n |c_n| + |s_n|: a square about the center
+            double av = (lane >= 3 && lane < 3 + 2 * pr.nvert) ? fabs(v0) : 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) av += __shfl_xor(av, o, 64);
+            const double R = fmax(r2 + av, 0.0) + pr.reach0;
+            b = make_double4(r0 - R, r0 + R, r1 - R, r1 + R);
         } else {  // GCART
             const int M = pr.nvert;
             double ymax = -inf, ymin = inf;
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
     // extrusion tables, step codes and group codes: one thread per
     // (component, group of kGroup column steps)
     const int ngw = (sp.nw + kGroup - 1) / kGroup;
-    if (t < (int64_t)sp.ncomp * ngw) {
+    if (sp.tables && t < (int64_t)sp.ncomp * ngw) {
         const int g = (int)(t % ngw);
         const int comp = (int)(t / ngw);
         const int wb = g * kGroup;
@@ -357,8 +365,8 @@ __device__ __forceinline__ double cand_value(const KParams& P, const PrimRec& c,
             return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
-    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0)
-        return prim_value<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
+    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR)) != 0)
+        return prim_value<TYPES & (T_POLY | T_GCART | T_POLAR), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
                                                             P.gseg + pr.gs0 + (int64_t)comp * P.nu + u);
     return 0.0;
 }
@@ -406,8 +414,8 @@ __device__ __forceinline__ double cand_value_live(const KParams& P, const PrimRe
             return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
-    if constexpr ((TYPES & (T_POLY | T_GCART)) != 0)
-        return prim_value_live<TYPES & (T_POLY | T_GCART), SIGS>(pr, fv, uc, uw, vc, vw,
+    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR)) != 0)
+        return prim_value_live<TYPES & (T_POLY | T_GCART | T_POLAR), SIGS>(pr, fv, uc, uw, vc, vw,
                                                                  P.gseg + pr.gs0 + (int64_t)comp * P.nu + u, live);
     live = false;
     return 0.0;
@@ -711,13 +719,97 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
     }
 }
 
+// Partials of a Fourier-radius boundary, times the column sums, over the
+// kBlock samples of the tile handled by this wavefront.  d (R - r) / d x0 =
+// R'(theta) sin(theta) / r + cos(theta) (and the y0 pair), d / d R0 = 1,
+// d / d c_n = -cos n theta, d / d s_n = -sin n theta.  The coefficient sums go
+// through polar_emit, which combines candidates that share a coefficient's
+// parameter (a global shape coefficient) in the block's LDS.
+constexpr int kPolarSlots = 64;     // >= 2 x the largest Fourier order
+
+// Adds the wavefront sum of v for coefficient field `field` (slot = its
+// position among the coefficients): into the block's LDS slot when the slot
+// holds, or can be claimed for, the field's parameter; else to grad directly.
+__device__ __forceinline__ void polar_emit(const KParams& P, int field, int slot, float v, double* s_pacc,
+                                           int* s_pkey) {
+    const sg_field r = P.fref[field];
+    if (r.idx < 0) return;
+    if (__ballot(v != 0.0f) == 0) return;
+    const float sum = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) {
+        const int idx = (int)r.idx;
+        int k = s_pkey[slot];
+        if (k == -2) {
+            const int old = atomicCAS(&s_pkey[slot], -2, idx);
+            k = (old == -2) ? idx : old;
+        }
+        if (k == idx) atomicAdd(&s_pacc[slot], r.b * (double)sum);
+        else atomicAdd(P.grad + idx, r.b * (double)sum);
+    }
+}
+
+template <int SIGS>
+__device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& pr, const float* sAc,
+                                               const SampleLat& L, double* s_pacc, int* s_pkey) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int N = pr.nvert;
+    float g[Q], c1[Q], s1[Q];
+    float sx = 0.0f, sy = 0.0f, sR = 0.0f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int t = q * 64 + lane;
+        const float a = sAc[t];
+        g[q] = 0.0f;
+        c1[q] = 1.0f;
+        s1[q] = 0.0f;
+        if (a != 0.0f) {
+            double r, c, s, dR;
+            const double arg = polar_arg(pr, P.fval, L.uc(t), L.vc(t), &r, &c, &s, &dR);
+            double sv, ds;
+            sig_vd<SIGS>(pr.sk0, arg, sv, ds);
+            const double gg = (double)a * pr.k0 * ds;     // a * d F / d (R - r)
+            if (r > 0.0) {
+                sx += (float)(gg * (dR * s / r + c));
+                sy += (float)(gg * (-dR * c / r + s));
+            }
+            sR += (float)gg;
+            g[q] = (float)gg;
+            c1[q] = (float)c;
+            s1[q] = (float)s;
+        }
+    }
+    emit(P, pr.f0, sx);
+    emit(P, pr.f0 + 1, sy);
+    emit(P, pr.f0 + 2, sR);
+    float cn[Q], sn[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        cn[q] = 1.0f;
+        sn[q] = 0.0f;
+    }
+    for (int n = 1; n <= N; ++n) {
+        float pc = 0.0f, ps = 0.0f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float c = cn[q] * c1[q] - sn[q] * s1[q];
+            sn[q] = sn[q] * c1[q] + cn[q] * s1[q];
+            cn[q] = c;
+            pc -= g[q] * cn[q];
+            ps -= g[q] * sn[q];
+        }
+        polar_emit(P, pr.f0 + 2 + n, n - 1, pc, s_pacc, s_pkey);
+        polar_emit(P, pr.f0 + 2 + N + n, N + n - 1, ps, s_pacc, s_pkey);
+    }
+}
+
 // One candidate primitive, handled by one wavefront for all kBlock samples of
 // the block's tile (kBlock / 64 samples per lane): in-plane partials times the
 // class column sums sAc[sample], summed over the lane's samples, reduced over
 // the wavefront, and added with one atomic per parameter field.
 template <int TYPES, int SIGS>
 __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& cr, const float* sAc, const SampleLat& L,
-                               const Tile& T, int comp, int u0, float* sg) {
+                               const Tile& T, int comp, int u0, float* sg, double* s_pacc, int* s_pkey) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
     const DevPrim& pr = cr.pr;
@@ -798,6 +890,12 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
     if constexpr ((TYPES & T_GCART) != 0) {
         if (type == SG_PRIM_GCART) {
             gcart_partials<SIGS>(P, pr, sAc, L, T, comp, u0, sg);
+            return;
+        }
+    }
+    if constexpr ((TYPES & T_POLAR) != 0) {
+        if (type == SG_PRIM_POLAR) {
+            polar_partials<SIGS>(P, pr, sAc, L, s_pacc, s_pkey);
             return;
         }
     }
@@ -936,6 +1034,8 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     __shared__ float sA[VJP ? NC * kBlock : 1];
     __shared__ double s_lat[VJP ? 4 * kBlock : 1];
     __shared__ float sG[(VJP && (TYPES & T_GCART)) ? (kBlock / 64) * 2 * kSegBucket : 1];
+    __shared__ double s_pacc[(VJP && (TYPES & T_POLAR)) ? kPolarSlots : 1];
+    __shared__ int s_pkey[(VJP && (TYPES & T_POLAR)) ? kPolarSlots : 1];
     const int tid = threadIdx.x, wave = tid >> 6;
 
     const int seg = b % P.nseg;
@@ -1282,10 +1382,18 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         const SampleLat L{s_lat};
         float* sgw = sG + ((TYPES & T_GCART) ? wave * 2 * kSegBucket : 0);
         const int u0 = G.u - (tid & (P.tu - 1));   // first u of the tile
+        if constexpr ((TYPES & T_POLAR) != 0) {
+            // coefficient slots: unclaimed (the barrier below, or the scan's, orders this before use)
+            if (tid < kPolarSlots) {
+                s_pkey[tid] = -2;
+                s_pacc[tid] = 0.0;
+            }
+        }
         if (staged_all) {
             __syncthreads();
             for (int j = wave; j < ncand; j += kBlock / 64)
-                block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0, sgw);
+                block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0, sgw,
+                                            s_pacc, s_pkey);
         } else {
             for (int next = 0; next < P.nprim;) {
                 const int n = scan_candidates(P.bbox, P.nprim, next, G.T.ulo, G.T.uhi, G.T.vlo, G.T.vhi, s_cand,
@@ -1295,9 +1403,14 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                     stage_cands(P.prec, s_cand, j0, nj, s_rec);
                     for (int j = wave; j < nj; j += kBlock / 64)
                         block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0,
-                                                    sgw);
+                                                    sgw, s_pacc, s_pkey);
                 }
             }
+        }
+        if constexpr ((TYPES & T_POLAR) != 0) {
+            // one atomic per combined coefficient parameter
+            __syncthreads();
+            if (tid < kPolarSlots && s_pkey[tid] >= 0 && s_pacc[tid] != 0.0) atomicAdd(P.grad + s_pkey[tid], s_pacc[tid]);
         }
     }
 }
@@ -1405,7 +1518,7 @@ __global__ __launch_bounds__(256) void k_fill(double* __restrict__ dst, double v
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st) {
-    const int64_t nz = (int64_t)sp.ncomp * ((sp.nw + kGroup - 1) / kGroup);
+    const int64_t nz = sp.tables ? (int64_t)sp.ncomp * ((sp.nw + kGroup - 1) / kGroup) : 0;
     const int64_t n = std::max<int64_t>(1, std::max<int64_t>(nz, sp.zero_n));
     const int64_t blocks = (sp.nprim + 3) / 4 + (n + 255) / 256;
     hipLaunchKernelGGL(k_stage, dim3((unsigned)blocks, (unsigned)nvariant), dim3(256), 0, st, sp);
@@ -1466,6 +1579,9 @@ hipError_t launch_column_batch(int tree, int variant, const KParams* plist, cons
         case VAR_ELL_SIGMOID:
             return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, plist, first, nreq, blocks,
                                                                                           st);
+        case VAR_POLAR_SIGMOID:
+            return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, plist, first, nreq,
+                                                                                            blocks, st);
         default: return launch_batch_variant<MODE_VJP_FIELDS, T_ALL, S_ALL>(tree, plist, first, nreq, blocks, st);
     }
 }
@@ -1476,6 +1592,7 @@ static hipError_t launch_mode(int tree, int variant, const KParams& kp, hipStrea
         case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(tree, kp, st);
         case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(tree, kp, st);
         case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, kp, st);
+        case VAR_POLAR_SIGMOID: return launch_variant<MODE, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, kp, st);
         default: return launch_variant<MODE, T_ALL, S_ALL>(tree, kp, st);
     }
 }

@@ -61,6 +61,10 @@ struct sg_scene {
     uint32_t* d_code[2] = {nullptr, nullptr};   // column-step codes
     uint32_t* d_gcode[2] = {nullptr, nullptr};  // group codes
     double* d_grad = nullptr;
+    // no extrusion bound references a parameter: the extrusion tables and
+    // step / group codes (index 0) are computed once, at scene creation, and
+    // serve every call and both FD evaluation points
+    bool static_w = false;
     float* d_work[2] = {nullptr, nullptr};
     unsigned long long* d_nread = nullptr;   // sparse VJP: (sample, step) pairs read
     double* h_p = nullptr;            // pinned staging
@@ -68,7 +72,8 @@ struct sg_scene {
     hipEvent_t p_evt = nullptr;
     bool p_evt_pending = false;
     // tracing: events around the column-kernel launches
-    bool timing = false;
+    int timing = 0;                   // record every timing-th launch of each kind (0: off)
+    int64_t launches[8] = {};         // column-kernel launches per kind since timing was set
     struct Rec {
         int mode;
         hipEvent_t a, b;

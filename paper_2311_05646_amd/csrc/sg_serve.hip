@@ -253,9 +253,11 @@ bool launch_batch(sg_server* v, Lane& L) {
         sp.fval[0] = b->fval;
         sp.bbox[0] = b->bbox;
         sp.prec[0] = b->prec;
-        sp.ztab[0] = b->ztab;
-        sp.code[0] = b->code;
-        sp.gcode[0] = b->gcode;
+        if (!sc->static_w) {
+            sp.ztab[0] = b->ztab;
+            sp.code[0] = b->code;
+            sp.gcode[0] = b->gcode;
+        }
         sp.zero_ptr = b->grad;
         sp.zero_n = sc->n_params;
         if (launch_stage(sp, 1, st) != hipSuccess) return false;
@@ -278,9 +280,11 @@ bool launch_batch(sg_server* v, Lane& L) {
             kp.fval = b->fval;
             kp.bbox = b->bbox;
             kp.prec = b->prec;
-            kp.ztab = b->ztab;
-            kp.code = b->code;
-            kp.gcode = b->gcode;
+            if (!sc->static_w) {
+                kp.ztab = b->ztab;
+                kp.code = b->code;
+                kp.gcode = b->gcode;
+            }
             kp.grad = b->grad;
             for (int c = 0; c < kMaxComp; ++c) {
                 const int cc = std::min(c, sc->ncomp - 1);

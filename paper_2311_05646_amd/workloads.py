@@ -23,7 +23,7 @@ Scene description (plain Python data, consumed by the C-ABI marshalling in
                "children": [prim index | tree, ...]},
     }
 
-    prim = {"type": "box"|"ellipse"|"poly"|"gcart",
+    prim = {"type": "box"|"ellipse"|"poly"|"gcart"|"polar",
             "fields": [(a, b, idx), ...],   # value = a + b * p[idx]; idx < 0: a
             "consts": [float, ...],         # gcart vertex x's; ellipse aspect
             "nvert": int,
@@ -36,6 +36,8 @@ Field order per type (paper Tab. ``autodiffgeo``):
     poly    : x_1..x_N y_1..y_N z0 z1 (CCW)        sigma: boundary, -, z
     gcart   : xs xe y+_1..y+_M y-_1..y-_M z0 z1    sigma: x-range, y, z
               consts: vertex x_1 < ... < x_M
+    polar   : x0 y0 R0 c_1..c_N s_1..s_N z0 z1     sigma: boundary, -, z
+              (nvert = N, the Fourier order)
 
 sigma kinds: sigmoid, erf, sin, linear, quadratic (paper Tab.
 ``nonlinearfunctions``); kmode "local" means k = k_r / (sample width along the
@@ -109,6 +111,16 @@ def gcart(xs, xe, xv, yp, ym, z=None, sig_x=LIN, sig_y=LIN, sig_z=LIN):
     return {"type": "gcart", "fields": [xs, xe] + list(yp) + list(ym) + zf,
             "consts": [float(v) for v in xv], "nvert": len(xv),
             "bounded": [True, True, z is not None], "sigma": [tuple(sig_x), tuple(sig_y), tuple(sig_z)]}
+
+
+def polar(x0, y0, R0, cs, ss, z=None, sig=("sigmoid", "fixed", 50.0), sig_z=LIN):
+    """GeneralPolar2D with a Fourier radius: R(theta) = R0 + sum_n c_n cos(n theta
+    + pi) + s_n sin(n theta + pi), n = 1..N (the scatterer parameterization of
+    the polarization-splitting grating coupler)."""
+    assert len(cs) == len(ss) and len(cs) >= 1
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "polar", "fields": [x0, y0, R0] + list(cs) + list(ss) + zf, "consts": [], "nvert": len(cs),
+            "bounded": [True, True, z is not None], "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
 
 
 # ----------------------------------------------------------------- grids
@@ -298,6 +310,58 @@ def c4_scene(rng, nside=40, nx=None, ny=None, nz=80, pitch=0.25, r_lo=0.06, r_hi
     return scene, np.array(p)
 
 
+def psgc_scene(rng, nside=40, nx=None, ny=None, nz=80, pitch=0.25, r_lo=0.06, r_hi=0.11, order=6, coef=0.012,
+               shared=True, jitter=0.02, dx=0.025, kr=4.0 * math.sqrt(2.0)):
+    """Slab minus a nside x nside lattice of Fourier-radius scatterers
+    (eq:PSGCboundary, order N), each with its own R0; the 2N coefficients are
+    global parameters shared by every scatterer (shared=True) or each
+    scatterer's own (shared=False); c_n, s_n ~ N(0, coef / n)."""
+    nx = nside * int(round(pitch / dx)) if nx is None else nx
+    ny = nside * int(round(pitch / dx)) if ny is None else ny
+    X = uniform_nodes(nx, dx)
+    Y = uniform_nodes(ny, dx)
+    Z = uniform_nodes(nz, 0.025)
+    zc = Z[nz // 2]
+    zr = (K(zc - 0.1095), K(zc + 0.1105))
+    k = kr / dx
+    prims = [box(x=None, y=None, z=zr)]
+    p = []
+
+    def coeffs():
+        q = len(p)
+        p.extend(rng.normal(0.0, coef / n) for n in list(range(1, order + 1)) * 2)
+        return [P(q + i) for i in range(order)], [P(q + order + i) for i in range(order)]
+
+    if shared:
+        cs, ss = coeffs()
+    for i in range(nside):
+        for j in range(nside):
+            cx = pitch / 2 + pitch * i + rng.uniform(-jitter, jitter)
+            cy = pitch / 2 + pitch * j + rng.uniform(-jitter, jitter)
+            p.append(rng.uniform(r_lo, r_hi))
+            r0 = P(len(p) - 1)
+            if not shared:
+                cs, ss = coeffs()
+            prims.append(polar(K(cx), K(cy), r0, cs, ss, z=zr, sig=("sigmoid", "fixed", k)))
+    scene = {"name": "psgc", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "difference",
+                      "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}}
+    return scene, np.array(p)
+
+
+def make_psgc(seed=BASE_SEED + 5, with_fields=True, **kw):
+    """Polarization-splitting grating coupler with the paper's scatterer
+    parameterization: 400x400x80 at 25 nm, 40x40 Fourier-radius scatterers
+    (order 6) with their own R0 and 12 global shape coefficients (n = 1612)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = psgc_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.31), "h": 1e-7}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
 def make_c4(seed=BASE_SEED + 3, with_fields=True, **kw):
     """3D polarization-splitting grating: 400x400x80 at 25 nm; slab minus a
     40x40 lattice of elliptical holes, (x, y, r) per hole (4800 params)."""
@@ -349,6 +413,14 @@ def make_c3_small(seed=BASE_SEED + 12):
 
 def make_c4_small(seed=BASE_SEED + 13):
     return make_c4(seed, nside=4, nx=45, ny=43, nz=12)
+
+
+def make_psgc_small(seed=BASE_SEED + 14, **kw):
+    return make_psgc(seed, nside=3, nx=31, ny=29, nz=12, **kw)
+
+
+def make_psgc_small_local(seed=BASE_SEED + 15):
+    return make_psgc_small(seed, shared=False)
 
 
 def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
@@ -404,14 +476,18 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     prims.append(box(x=(par(0.80 + u(-.02, .02)), K(1.25)), y=(K(0.20), K(0.70)),
                      z=None if dim == 2 else (K(zc - 0.1), K(zc + 0.1)),
                      sig=(("linear", "local", 1.0), ("sin", "local", 1.2), LIN)))
+    # Fourier-radius scatterer, quadratic sigma
+    prims.append(polar(par(1.08 + u(-.01, .01)), par(0.26 + u(-.01, .01)), par(0.10),
+                       [par(u(-0.015, 0.015)) for _ in range(3)], [par(u(-0.015, 0.015)) for _ in range(3)],
+                       z=zr, sig=("quadratic", "fixed", 30.0)))
     if root == "union":
-        tree = {"op": "union", "children": [{"op": "union", "children": [0, 1, 2, 3]},
+        tree = {"op": "union", "children": [{"op": "union", "children": [0, 1, 2, 3, 6]},
                                             {"op": "intersection", "children": [4, 5]}]}
     elif root == "difference":
-        tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4]},
+        tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4, 6]},
                                                  {"op": "union", "children": [1, 5]}]}
     else:
-        tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5]},
+        tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5, 6]},
                                                    {"op": "union", "children": [4]}]}
     scene = {"name": f"zoo{dim}d_{root}", "dim": dim, "nodes": [X, Y, Z],
              "components": ("x", "y", "z"), "eps_bg": 2.25, "eps_fg": 11.7,
@@ -488,6 +564,7 @@ CONFIGS = {
     "c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4,
     "c2_small": make_c2_small, "c3_small": make_c3_small, "c4_small": make_c4_small,
     "crowd3": make_crowd, "many2": make_many,
+    "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
 }
 
 

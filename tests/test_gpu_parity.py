@@ -13,9 +13,11 @@ from paper_2311_05646_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 # crowd3: one tile holds more candidates than a staging round; many2: more
-# primitives than one candidate scan pass
+# primitives than one candidate scan pass; psgc3_small(_local): Fourier-radius
+# scatterers with global (shared) or per-scatterer shape coefficients
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
-         "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2"]
+         "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
+         "psgc3_small", "psgc3_small_local"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 
