@@ -165,12 +165,13 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
 def kernels_3d(api, W, gen, reps):
     """Column-kernel bandwidth of eps_build and eps_grad_vjp on the 3D taper
     (600x240x100), the 3D polarization-splitting grating with elliptical holes
-    (400x400x80) and the same grating with Fourier-radius scatterers whose 12
-    shape coefficients are global parameters."""
+    (400x400x80), the same grating with Fourier-radius scatterers whose 12
+    shape coefficients are global parameters, and the taper with its
+    100-term sine-series boundary."""
     import torch
     dev = torch.device("cuda", 0)
     also = {}
-    for name, mk in (("c3", W.make_c3), ("c4", W.make_c4), ("psgc3", W.make_psgc)):
+    for name, mk in (("c3", W.make_c3), ("c4", W.make_c4), ("psgc3", W.make_psgc), ("taper3_sine", W.make_taper_sine)):
         log(f"[bench] {name} kernels")
         c = mk(with_fields=False)
         sc = api.Scene(c["scene"])

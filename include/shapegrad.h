@@ -82,9 +82,19 @@ enum {
  *                                               the polar coordinates about (x0, y0),
  *                                               R = R0 + sum_n c_n cos(n theta + pi) + s_n sin(n theta + pi);
  *                                               sigma[0] boundary (FIXED k), sigma[2] z
+ *   SG_PRIM_SERIES  xs xe v_1..v_K z0 z1        (nvert = K, 1 <= K <= 4096)
+ *                                               two-sided boundary with the sine series of
+ *                                               eq:taper_boundary: Rect1D(x; xs, xe)
+ *                                               sigma_k(f(x) - (y - yc)) sigma_k(f(x) + (y - yc)),
+ *                                               f = w_in/2 + (w_out - w_in)/2 (x - x0)/L
+ *                                                 + env(x) sum_i v_i sin(i pi (x - x0)/L),
+ *                                               env = 0.1 + 0.45 (1 - cos(2 pi (x - x0)/L));
+ *                                               consts: x0 L w_in w_out yc; sigma[0] x-range,
+ *                                               sigma[1] y boundary, sigma[2] z
  * z0 z1 are the extrusion along z (Rect1D in z), used when bounded[2] != 0.
  * In 2D scenes (dim = 2) nothing may be bounded along z. */
-enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3, SG_PRIM_POLAR = 4 };
+enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3, SG_PRIM_POLAR = 4,
+       SG_PRIM_SERIES = 5 };
 
 /* sigma_k kinds (Tab. nonlinearfunctions).  sigmoid and erf are taken as exactly
  * 0 / 1 beyond |k x| = 24 / 6 (tails below 4e-11 / 2e-17). */

@@ -214,7 +214,42 @@ def polar(prim, vals, pts):
     return f * zv, out
 
 
-EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart, "polar": polar}
+def series(prim, vals, pts):
+    """Two-sided GeneralCartesian2D whose boundary is the taper's sine series
+    (eq:taper_boundary): Rect1D(x; xs, xe) sigma_k(f(x) - (y - yc))
+    sigma_k(f(x) + (y - yc)), f(x) = w_in / 2 + (w_out - w_in) / 2 (x - x0) / L
+    + envelope(x) sum_i v_i sin(i pi (x - x0) / L), envelope(x) = 0.1 + 0.45
+    (1 - cos(2 pi (x - x0) / L)).  Fields xs xe v_1..v_K z0 z1; consts x0 L
+    w_in w_out yc; nvert = K."""
+    K = prim["nvert"]
+    x0, L, w_in, w_out, yc = [float(c) for c in prim["consts"]]
+    v = vals[2:2 + K]
+    (xc, xw), (yc_s, yw) = pts["x"], pts["y"]
+    shape = np.broadcast(xc, yc_s).shape
+    xb = np.broadcast_to(xc, shape)
+    u = (xb - x0) / L
+    env = 0.1 + 0.45 * (1.0 - np.cos(2.0 * np.pi * u))
+    basis = [env * np.sin(i * np.pi * u) for i in range(1, K + 1)]
+    f = w_in / 2.0 + (w_out - w_in) / 2.0 * u
+    for i in range(K):
+        f = f + v[i] * basis[i]
+    yr = yc_s - yc
+    sy = prim["sigma"][1]
+    ky = kval(sy, yw)
+    tp, tm = ky * (f - yr), ky * (f + yr)
+    sp, sm = sigma(sy[0], tp), sigma(sy[0], tm)
+    dsp, dsm = ky * dsigma(sy[0], tp), ky * dsigma(sy[0], tm)
+    rx, drx0, drx1 = rect1d(prim["sigma"][0], xc, xw, vals[0], vals[1])
+    zv, zparts = _z_factor(prim, vals, pts, 2 + K)
+    fy = sp * sm
+    gf = rx * (dsp * sm + sp * dsm) * zv        # d s / d f
+    out = [(0, drx0 * fy * zv), (1, drx1 * fy * zv)]
+    out += [(2 + i, gf * basis[i]) for i in range(K)]
+    out += [(fi, rx * fy * d) for fi, d in zparts]
+    return rx * fy * zv, out
+
+
+EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart, "polar": polar, "series": series}
 
 
 def evaluate(prim, vals, pts):
@@ -255,6 +290,16 @@ def bbox(prim, vals, wmax):
         lo[0], hi[0] = vals[0] - rmax, vals[0] + rmax
         lo[1], hi[1] = vals[1] - rmax, vals[1] + rmax
         zf = 3 + 2 * N
+    elif t == "series":
+        # |f| <= the larger end of the linear ramp over [xs, xe] + sum |v_i| (envelope <= 1)
+        K = prim["nvert"]
+        x0, L, w_in, w_out, yc = [float(c) for c in prim["consts"]]
+        ramp = [abs(w_in / 2.0 + (w_out - w_in) / 2.0 * (x - x0) / L) for x in (vals[0], vals[1])]
+        R = max(ramp) + sum(abs(x) for x in vals[2:2 + K]) + reach(prim["sigma"][1], 1)
+        rx = reach(prim["sigma"][0], 0)
+        lo[0], hi[0] = vals[0] - rx, vals[1] + rx
+        lo[1], hi[1] = yc - R, yc + R
+        zf = 2 + K
     elif t == "poly":
         N = prim["nvert"]
         rr = reach(prim["sigma"][0], 0)

@@ -115,6 +115,7 @@ static int expected_nfield(const sg_prim_desc& p) {
         case SG_PRIM_POLY: return 2 * p.nvert + 2;
         case SG_PRIM_GCART: return 2 * p.nvert + 4;
         case SG_PRIM_POLAR: return 2 * p.nvert + 5;
+        case SG_PRIM_SERIES: return p.nvert + 4;
         default: return -1;
     }
 }
@@ -126,6 +127,7 @@ static int zfield(const sg_prim_desc& p) {
         case SG_PRIM_ELLIPSE: return 3;
         case SG_PRIM_POLY: return 2 * p.nvert;
         case SG_PRIM_POLAR: return 2 * p.nvert + 3;
+        case SG_PRIM_SERIES: return p.nvert + 2;
         default: return 2 * p.nvert + 2;
     }
 }
@@ -179,12 +181,13 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         if (p.type == SG_PRIM_POLY && (p.nvert < 3 || p.nvert > 64)) return fail(SG_E_INVALID, "poly %d: nvert", i);
         if (p.type == SG_PRIM_GCART && (p.nvert < 2 || p.nvert > 100000)) return fail(SG_E_INVALID, "gcart %d: nvert", i);
         if (p.type == SG_PRIM_POLAR && (p.nvert < 1 || p.nvert > 29)) return fail(SG_E_INVALID, "polar %d: order", i);
+        if (p.type == SG_PRIM_SERIES && (p.nvert < 1 || p.nvert > 4096)) return fail(SG_E_INVALID, "series %d: terms", i);
         if (p.nfield != nf) return fail(SG_E_INVALID, "primitive %d: nfield %d, expected %d", i, p.nfield, nf);
         if (p.field_off < 0 || p.field_off + nf > d->nfield) return fail(SG_E_INVALID, "primitive %d: fields", i);
-        const int nc = p.type == SG_PRIM_ELLIPSE ? 2 : (p.type == SG_PRIM_GCART ? p.nvert : 0);
+        const int nc = p.type == SG_PRIM_ELLIPSE ? 2 : p.type == SG_PRIM_GCART ? p.nvert : p.type == SG_PRIM_SERIES ? 5 : 0;
         if (p.nconst != nc || p.const_off < 0 || p.const_off + nc > d->nconst)
             return fail(SG_E_INVALID, "primitive %d: consts", i);
-        const int nsig = p.type == SG_PRIM_BOX || p.type == SG_PRIM_GCART ? 3 : 1;
+        const int nsig = p.type == SG_PRIM_BOX || p.type == SG_PRIM_GCART || p.type == SG_PRIM_SERIES ? 3 : 1;
         for (int a = 0; a < 3; ++a) {
             const bool used = (a < nsig) || (a == 2);
             const bool bnd = p.type == SG_PRIM_BOX ? p.bounded[a] != 0 : (a < 2 || p.bounded[2] != 0);
@@ -198,6 +201,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             const double ax = d->consts[p.const_off], ay = d->consts[p.const_off + 1];
             if (!(ax > 0) || !(ay > 0)) return fail(SG_E_INVALID, "ellipse %d: aspect must be > 0", i);
         }
+        if (p.type == SG_PRIM_SERIES && !(d->consts[p.const_off + 1] > 0.0))
+            return fail(SG_E_INVALID, "series %d: L must be > 0", i);
         if (p.type == SG_PRIM_GCART)
             for (int j = 0; j + 1 < p.nvert; ++j)
                 if (!(d->consts[p.const_off + j + 1] > d->consts[p.const_off + j]))
@@ -477,7 +482,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             r.sm0 = p.sigma[0].kmode;
             r.k0 = p.sigma[0].k;
             r.reach0 = reach(p.sigma[0], 0);
-            if (p.type == SG_PRIM_GCART) {
+            if (p.type == SG_PRIM_GCART || p.type == SG_PRIM_SERIES) {
                 r.sk1 = p.sigma[1].kind;
                 r.sm1 = p.sigma[1].kmode;
                 r.k1 = p.sigma[1].k;
@@ -505,7 +510,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
                 if (p.bounded[axis_v]) smask |= sigma_bit(p.sigma[axis_v].kind);
             } else {
                 smask |= sigma_bit(p.sigma[0].kind);
-                if (p.type == SG_PRIM_GCART) smask |= sigma_bit(p.sigma[1].kind);
+                if (p.type == SG_PRIM_GCART || p.type == SG_PRIM_SERIES) smask |= sigma_bit(p.sigma[1].kind);
             }
         }
         const int vt[4] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL, T_BOX | T_POLAR};

@@ -30,7 +30,7 @@ __host__ __device__ inline double sigma_cut(int kind) {
 // kinds a kernel instantiation handles.  Scenes are dispatched to the smallest
 // instantiation that covers them, so the common kernels carry no code for
 // primitives or transcendental functions they never see.
-enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_POLAR = 16, T_ALL = 31 };
+enum : int { T_BOX = 1, T_ELL = 2, T_POLY = 4, T_GCART = 8, T_POLAR = 16, T_SERIES = 32, T_ALL = 63 };
 enum : int { S_SIGMOID = 1, S_ERF = 2, S_SIN = 4, S_LIN = 8, S_QUAD = 16, S_ALL = 31 };
 
 // ---- one function per kind: value, and value + d/dt
@@ -285,6 +285,31 @@ __device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __r
     return pr.k0 * (R - r);
 }
 
+// Half-width f(x) of the taper's sine-series boundary (eq:taper_boundary):
+// phi = pi (x - x0) / L, sin i phi by repeated rotation from (cos phi, sin phi),
+// envelope 0.1 + 0.45 (1 - cos 2 phi) = 0.1 + 0.9 sin^2 phi.  cst: x0 L w_in w_out yc.
+__device__ __forceinline__ double series_f(const DevPrim& pr, const double* __restrict__ fv,
+                                           const double* __restrict__ cst, double uc, double* env_out = nullptr,
+                                           double* s1_out = nullptr, double* c1_out = nullptr) {
+    const double x0 = cst[0], L = cst[1], w_in = cst[2], w_out = cst[3];
+    const double u = (uc - x0) / L;
+    double s1, c1;
+    sincospi(u, &s1, &c1);
+    const double env = 0.1 + 0.9 * s1 * s1;
+    const double* v = fv + pr.f0 + 2;
+    double sum = 0.0, si = s1, ci = c1;
+    for (int i = 0; i < pr.nvert; ++i) {
+        sum += v[i] * si;
+        const double sn = si * c1 + ci * s1;
+        ci = ci * c1 - si * s1;
+        si = sn;
+    }
+    if (env_out) *env_out = env;
+    if (s1_out) *s1_out = s1;
+    if (c1_out) *c1_out = c1;
+    return 0.5 * w_in + 0.5 * (w_out - w_in) * u + env * sum;
+}
+
 // In-plane factor F(u, v) of a primitive (value only).  gs: the sample's entry
 // of the primitive's segment table (piecewise-linear boundaries only).
 template <int TYPES, int SIGS>
@@ -345,6 +370,16 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
     if constexpr ((TYPES & T_POLAR) != 0) {
         if (pr.type == SG_PRIM_POLAR) return sig_v<SIGS>(pr.sk0, polar_arg(pr, fv, uc, vc));
     }
+    if constexpr ((TYPES & T_SERIES) != 0) {
+        if (pr.type == SG_PRIM_SERIES) {
+            const double rx = rect_v<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, uw), uc, fv[pr.f0], fv[pr.f0 + 1]);
+            if (rx == 0.0) return 0.0;
+            const double* c = cst + pr.c0;
+            const double f = series_f(pr, fv, c, uc);
+            const double ky = kval(pr.sm1, pr.k1, vw), yr = vc - c[4];
+            return rx * sig_v<SIGS>(pr.sk1, ky * (f - yr)) * sig_v<SIGS>(pr.sk1, ky * (f + yr));
+        }
+    }
     return 0.0;
 }
 
@@ -368,6 +403,7 @@ __device__ __forceinline__ bool sig_live(int kind, double t) {
 // prim_value returns (same operations, no early exits).
 template <int TYPES, int SIGS>
 __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const double* __restrict__ fv,
+                                                  const double* __restrict__ cst,
                                                   double uc, double uw, double vc, double vw, const GSeg* gs,
                                                   bool& live) {
     if constexpr ((TYPES & T_POLY) != 0) {
@@ -423,6 +459,23 @@ __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const doubl
             const double t = polar_arg(pr, fv, uc, vc);
             live = sig_live<SIGS>(pr.sk0, t);
             return sig_v<SIGS>(pr.sk0, t);
+        }
+    }
+    if constexpr ((TYPES & T_SERIES) != 0) {
+        if (pr.type == SG_PRIM_SERIES) {
+            // same factors and operations as prim_value; the partials follow the GCART pattern
+            const double kx = kval(pr.sm0, pr.k0, uw);
+            const double ta = kx * (uc - fv[pr.f0]), tb = kx * (fv[pr.f0 + 1] - uc);
+            const double rx = sig_v<SIGS>(pr.sk0, ta) * sig_v<SIGS>(pr.sk0, tb);
+            const double* c = cst + pr.c0;
+            const double f = series_f(pr, fv, c, uc);
+            const double ky = kval(pr.sm1, pr.k1, vw), yr = vc - c[4];
+            const double tp = ky * (f - yr), tm = ky * (f + yr);
+            const double sp = sig_v<SIGS>(pr.sk1, tp), sm = sig_v<SIGS>(pr.sk1, tm);
+            const bool lx = sig_live<SIGS>(pr.sk0, ta) || sig_live<SIGS>(pr.sk0, tb);
+            live = (lx && sp * sm != 0.0) ||
+                   (rx != 0.0 && ((sig_live<SIGS>(pr.sk1, tp) && sm != 0.0) || (sig_live<SIGS>(pr.sk1, tm) && sp != 0.0)));
+            return rx == 0.0 ? 0.0 : rx * sp * sm;
         }
     }
     live = false;

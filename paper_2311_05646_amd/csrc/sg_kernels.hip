@@ -61,11 +61,13 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             case SG_PRIM_ELLIPSE: nf = 5; break;
             case SG_PRIM_POLY: nf = 2 * pr.nvert + 2; break;
             case SG_PRIM_POLAR: nf = 2 * pr.nvert + 5; break;
+            case SG_PRIM_SERIES: nf = pr.nvert + 4; break;
             default: nf = 2 * pr.nvert + 4; break;
         }
         // lane i resolves fields f0 + i, f0 + i + 64, ...; the first one stays
         // in the lane for the boxes' and ellipses' record fields
         double v0 = 0.0, b0 = 0.0;
+        double vabs = 0.0;    // SERIES: sum of |v_i| over this lane's sine coefficients
         int idx0 = -1;
         for (int i = lane; i < nf; i += 64) {
             const sg_field r = sp.fref[pr.f0 + i];
@@ -76,6 +78,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
                 v = r.a + r.b * pv;
             }
             fv[pr.f0 + i] = v;
+            if (i >= 2 && i < 2 + pr.nvert) vabs += fabs(v);
             if (i == lane) {
                 v0 = v;
                 idx0 = r.idx;
@@ -126,6 +129,15 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             }
             if (__ballot(open) != 0) b = make_double4(-inf, inf, -inf, inf);
             else b = make_double4(wave_min(xlo), wave_max(xhi), wave_min(ylo), wave_max(yhi));
+        } else if (pr.type == SG_PRIM_SERIES) {
+            // |f| <= the larger end of the linear ramp over [xs, xe] + sum |v_i| (envelope <= 1)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) vabs += __shfl_xor(vabs, o, 64);
+            const double* c = sp.consts + pr.c0;
+            const double ra = fabs(0.5 * c[2] + 0.5 * (c[3] - c[2]) * (r0 - c[0]) / c[1]);
+            const double rb = fabs(0.5 * c[2] + 0.5 * (c[3] - c[2]) * (r1 - c[0]) / c[1]);
+            const double R = fmax(ra, rb) + vabs + pr.reach1;
+            b = make_double4(r0 - pr.reach0, r1 + pr.reach0, c[4] - R, c[4] + R);
         } else if (pr.type == SG_PRIM_POLAR) {
             // R(theta) <= R0 + sum_n |c_n| + |s_n|: a square about the center
             double av = (lane >= 3 && lane < 3 + 2 * pr.nvert) ? fabs(v0) : 0.0;
@@ -365,8 +377,8 @@ __device__ __forceinline__ double cand_value(const KParams& P, const PrimRec& c,
             return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
-    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR)) != 0)
-        return prim_value<TYPES & (T_POLY | T_GCART | T_POLAR), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
+    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR | T_SERIES)) != 0)
+        return prim_value<TYPES & (T_POLY | T_GCART | T_POLAR | T_SERIES), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
                                                             P.gseg + pr.gs0 + (int64_t)comp * P.nu + u);
     return 0.0;
 }
@@ -414,8 +426,8 @@ __device__ __forceinline__ double cand_value_live(const KParams& P, const PrimRe
             return sig_v<SIGS>(pr.sk0, pr.k0 * (r - sqrt(rho2)));
         }
     }
-    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR)) != 0)
-        return prim_value_live<TYPES & (T_POLY | T_GCART | T_POLAR), SIGS>(pr, fv, uc, uw, vc, vw,
+    if constexpr ((TYPES & (T_POLY | T_GCART | T_POLAR | T_SERIES)) != 0)
+        return prim_value_live<TYPES & (T_POLY | T_GCART | T_POLAR | T_SERIES), SIGS>(pr, fv, P.consts, uc, uw, vc, vw,
                                                                  P.gseg + pr.gs0 + (int64_t)comp * P.nu + u, live);
     live = false;
     return 0.0;
@@ -803,6 +815,70 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
     }
 }
 
+// Partials of the taper's sine-series boundary, times the column sums, over
+// the kBlock samples of the tile handled by this wavefront: the x-range pair
+// like a Rect1D, and d F / d v_i = (d F / d f) envelope(x) sin(i phi), the
+// sines by repeated FP32 rotation (error linear in i), one reduction per term;
+// a wavefront whose samples all have d F / d f = 0 skips the terms.
+template <int SIGS>
+__device__ __forceinline__ void series_partials(const KParams& P, const DevPrim& pr, const float* sAc,
+                                                const SampleLat& L) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const double* fv = P.fval;
+    const double* c = P.consts + pr.c0;
+    float w[Q], s1[Q], c1[Q];
+    float sxs = 0.0f, sxe = 0.0f;
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int t = q * 64 + lane;
+        const float a = sAc[t];
+        w[q] = 0.0f;
+        s1[q] = 0.0f;
+        c1[q] = 1.0f;
+        if (a != 0.0f) {
+            const double uc = L.uc(t), vc = L.vc(t);
+            double rx, drx0, drx1;
+            rect_vd<SIGS>(pr.sk0, kval(pr.sm0, pr.k0, L.uw(t)), uc, fv[pr.f0], fv[pr.f0 + 1], rx, drx0, drx1);
+            double env, sn, cs;
+            const double f = series_f(pr, fv, c, uc, &env, &sn, &cs);
+            const double ky = kval(pr.sm1, pr.k1, L.vw(t)), yr = vc - c[4];
+            double sp, dsp, sm, dsm;
+            sig_vd<SIGS>(pr.sk1, ky * (f - yr), sp, dsp);
+            sig_vd<SIGS>(pr.sk1, ky * (f + yr), sm, dsm);
+            const double ad = (double)a;
+            sxs += (float)(ad * drx0 * sp * sm);
+            sxe += (float)(ad * drx1 * sp * sm);
+            const double gf = ad * rx * ky * (dsp * sm + sp * dsm);    // a * d F / d f
+            w[q] = (float)(gf * env);
+            s1[q] = (float)sn;
+            c1[q] = (float)cs;
+            any = any || (w[q] != 0.0f);
+        }
+    }
+    emit(P, pr.f0, sxs);
+    emit(P, pr.f0 + 1, sxe);
+    if (__ballot(any) == 0) return;
+    float si[Q], ci[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        si[q] = s1[q];
+        ci[q] = c1[q];
+    }
+    for (int i = 0; i < pr.nvert; ++i) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            acc += w[q] * si[q];
+            const float sn = si[q] * c1[q] + ci[q] * s1[q];
+            ci[q] = ci[q] * c1[q] - si[q] * s1[q];
+            si[q] = sn;
+        }
+        emit(P, pr.f0 + 2 + i, acc);
+    }
+}
+
 // One candidate primitive, handled by one wavefront for all kBlock samples of
 // the block's tile (kBlock / 64 samples per lane): in-plane partials times the
 // class column sums sAc[sample], summed over the lane's samples, reduced over
@@ -896,6 +972,12 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
     if constexpr ((TYPES & T_POLAR) != 0) {
         if (type == SG_PRIM_POLAR) {
             polar_partials<SIGS>(P, pr, sAc, L, s_pacc, s_pkey);
+            return;
+        }
+    }
+    if constexpr ((TYPES & T_SERIES) != 0) {
+        if (type == SG_PRIM_SERIES) {
+            series_partials<SIGS>(P, pr, sAc, L);
             return;
         }
     }

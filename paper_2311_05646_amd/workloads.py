@@ -23,7 +23,7 @@ Scene description (plain Python data, consumed by the C-ABI marshalling in
                "children": [prim index | tree, ...]},
     }
 
-    prim = {"type": "box"|"ellipse"|"poly"|"gcart"|"polar",
+    prim = {"type": "box"|"ellipse"|"poly"|"gcart"|"polar"|"series",
             "fields": [(a, b, idx), ...],   # value = a + b * p[idx]; idx < 0: a
             "consts": [float, ...],         # gcart vertex x's; ellipse aspect
             "nvert": int,
@@ -38,6 +38,8 @@ Field order per type (paper Tab. ``autodiffgeo``):
               consts: vertex x_1 < ... < x_M
     polar   : x0 y0 R0 c_1..c_N s_1..s_N z0 z1     sigma: boundary, -, z
               (nvert = N, the Fourier order)
+    series  : xs xe v_1..v_K z0 z1                 sigma: x-range, y, z
+              consts: x0 L w_in w_out yc (nvert = K)
 
 sigma kinds: sigmoid, erf, sin, linear, quadratic (paper Tab.
 ``nonlinearfunctions``); kmode "local" means k = k_r / (sample width along the
@@ -121,6 +123,16 @@ def polar(x0, y0, R0, cs, ss, z=None, sig=("sigmoid", "fixed", 50.0), sig_z=LIN)
     zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
     return {"type": "polar", "fields": [x0, y0, R0] + list(cs) + list(ss) + zf, "consts": [], "nvert": len(cs),
             "bounded": [True, True, z is not None], "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
+
+
+def series(xs, xe, vs, x0, L, w_in, w_out, yc, z=None, sig_x=LIN, sig_y=LIN, sig_z=LIN):
+    """Two-sided boundary yc +- f(x) with the taper's sine series: f = w_in / 2 +
+    (w_out - w_in) / 2 (x - x0) / L + envelope(x) sum_i v_i sin(i pi (x - x0) / L)."""
+    assert len(vs) >= 1 and L > 0
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "series", "fields": [xs, xe] + list(vs) + zf,
+            "consts": [float(x0), float(L), float(w_in), float(w_out), float(yc)], "nvert": len(vs),
+            "bounded": [True, True, z is not None], "sigma": [tuple(sig_x), tuple(sig_y), tuple(sig_z)]}
 
 
 # ----------------------------------------------------------------- grids
@@ -270,6 +282,38 @@ def c3_scene(rng, nx=600, ny=240, nz=100, nvert=96, w_in=0.5, w_out=8.0,
     return scene, np.array(pu + pl)
 
 
+def taper_sine_scene(rng, nx=600, ny=240, nz=100, nterm=100, w_in=0.5, w_out=8.0, x_a=1.013, x_b=22.013,
+                     y_m=4.807, amp=0.08):
+    """The 3D taper of c3 with the paper's own parameterization of the taper
+    boundary (eq:taper_boundary): yc +- f(x), f a linear ramp from w_in / 2 to
+    w_out / 2 plus an enveloped sine series of nterm terms, v_i ~ N(0, amp / i)."""
+    X = uniform_nodes(nx, 0.04)
+    Y = uniform_nodes(ny, 0.04)
+    Z = graded_nodes(raised_cosine_widths(nz, 10.0, 40.0, coarse_at_ends=True))
+    zc = Z[nz // 2]
+    zr = (K(zc - 0.108), K(zc + 0.112))
+    xin = box(x=(K(-0.5), K(x_a)), y=(K(y_m - w_in / 2), K(y_m + w_in / 2)), z=zr)
+    xout = box(x=(K(x_b), K(X[-1] + 0.5)), y=(K(y_m - w_out / 2), K(y_m + w_out / 2)), z=zr)
+    p = [rng.normal(0.0, amp / i) for i in range(1, nterm + 1)]
+    taper = series(K(x_a), K(x_b), [P(i) for i in range(nterm)], x0=x_a, L=x_b - x_a, w_in=w_in, w_out=w_out,
+                   yc=y_m, z=zr)
+    scene = {"name": "taper_sine", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": nterm, "prims": [xin, taper, xout],
+             "tree": {"op": "union", "children": [0, 1, 2]}}
+    return scene, np.array(p)
+
+
+def make_taper_sine(seed=BASE_SEED + 6, with_fields=True, **kw):
+    """3D taper (600x240x100) with the sine-series boundary of eq:taper_boundary,
+    100 global parameters: every one reaches every column of the boundary."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = taper_sine_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.31), "h": 1e-8}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
 def make_c3(seed=BASE_SEED + 2, with_fields=True, **kw):
     """3D non-adiabatic taper: 600x240x100, dz graded 10-40 nm; x-monotone
     two-sided taper through 96 vertices per side (192 params) unioned with
@@ -415,6 +459,11 @@ def make_c4_small(seed=BASE_SEED + 13):
     return make_c4(seed, nside=4, nx=45, ny=43, nz=12)
 
 
+def make_taper_sine_small(seed=BASE_SEED + 16):
+    return make_taper_sine(seed, nx=70, ny=30, nz=10, nterm=12, w_in=0.2, w_out=0.7, x_a=0.213, x_b=2.413,
+                           y_m=0.607, amp=0.03)
+
+
 def make_psgc_small(seed=BASE_SEED + 14, **kw):
     return make_psgc(seed, nside=3, nx=31, ny=29, nz=12, **kw)
 
@@ -480,14 +529,18 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     prims.append(polar(par(1.08 + u(-.01, .01)), par(0.26 + u(-.01, .01)), par(0.10),
                        [par(u(-0.015, 0.015)) for _ in range(3)], [par(u(-0.015, 0.015)) for _ in range(3)],
                        z=zr, sig=("quadratic", "fixed", 30.0)))
+    # sine-series boundary, sin sigma across, sigmoid x-range
+    prims.append(series(par(0.12), K(0.62), [par(u(-0.006, 0.006)) for _ in range(4)], x0=0.1, L=0.5,
+                        w_in=0.04, w_out=0.08, yc=0.85, z=zr,
+                        sig_x=("sigmoid", "local", 4.0), sig_y=("sin", "local", 1.3)))
     if root == "union":
-        tree = {"op": "union", "children": [{"op": "union", "children": [0, 1, 2, 3, 6]},
+        tree = {"op": "union", "children": [{"op": "union", "children": [0, 1, 2, 3, 6, 7]},
                                             {"op": "intersection", "children": [4, 5]}]}
     elif root == "difference":
-        tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4, 6]},
+        tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4, 6, 7]},
                                                  {"op": "union", "children": [1, 5]}]}
     else:
-        tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5, 6]},
+        tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5, 6, 7]},
                                                    {"op": "union", "children": [4]}]}
     scene = {"name": f"zoo{dim}d_{root}", "dim": dim, "nodes": [X, Y, Z],
              "components": ("x", "y", "z"), "eps_bg": 2.25, "eps_fg": 11.7,
@@ -565,6 +618,7 @@ CONFIGS = {
     "c2_small": make_c2_small, "c3_small": make_c3_small, "c4_small": make_c4_small,
     "crowd3": make_crowd, "many2": make_many,
     "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
+    "taper3_sine": make_taper_sine, "taper3_sine_small": make_taper_sine_small,
 }
 
 

@@ -63,7 +63,7 @@ def test_marshal_scene_tree_postfix():
     from paper_2311_05646_amd import _lib, workloads as W
     cfg = W.make_zoo(dim=3, root="difference")
     s, keep = _lib.marshal_scene(cfg["scene"])
-    assert s.nnode == 3 and s.nprim == 7
+    assert s.nnode == 3 and s.nprim == 8
     root = s.nodes_op[s.nnode - 1]
     assert root.op == _lib.OP["difference"] and root.nchild == 2
     assert [s.children[root.child_off + i] for i in range(2)] == [-1, -2]

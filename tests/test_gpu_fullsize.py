@@ -143,6 +143,21 @@ def test_vjp_psgc_full_size():
     assert rel(fd, got) <= 1e-4
 
 
+def test_vjp_taper_sine_full_size():
+    """The taper's 100 sine-series coefficients at full size (each reaches the
+    whole boundary, too many samples for the oracle one by one): the fused
+    gradient against the GPU finite-difference Jacobian, and the sparse VJP
+    against the dense one."""
+    cfg, sc, E, A, Ed, Ad = _setup("taper3_sine")
+    got = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    fd = api().eps_grad_fd(sc, cfg["p"], Ed, Ad, cfg["omega"], cfg["h"])
+    sparse = api().eps_grad_vjp_sparse(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    print(f"[fullsize] taper3_sine fd vs vjp rel {rel(fd, got):.3e}, sparse vs dense {rel(sparse, got):.3e}",
+          flush=True)
+    assert rel(fd, got) <= 1e-4
+    assert rel(sparse, got) <= 1e-6
+
+
 @pytest.mark.parametrize("name", ["c2", "c3", "c4"])
 def test_fd_matches_vjp_full_size(name):
     cfg, sc, E, A, Ed, Ad = _setup(name)

@@ -14,10 +14,12 @@ pytestmark = pytest.mark.gpu
 
 # crowd3: one tile holds more candidates than a staging round; many2: more
 # primitives than one candidate scan pass; psgc3_small(_local): Fourier-radius
-# scatterers with global (shared) or per-scatterer shape coefficients
+# scatterers with global (shared) or per-scatterer shape coefficients;
+# taper3_sine_small: the taper's sine-series boundary (every parameter reaches
+# every column of it)
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
          "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
-         "psgc3_small", "psgc3_small_local"]
+         "psgc3_small", "psgc3_small_local", "taper3_sine_small"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 

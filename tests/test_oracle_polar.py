@@ -7,7 +7,11 @@ radius of eq:PSGCboundary):
   formula, evaluated by hand, puts it (sigma = 1/2 there);
 * rotating the sample about the center by phi and the coefficients by n phi
   (R'(theta) = R(theta - phi)) leaves the value unchanged, in every quadrant;
-* every analytic partial matches central differences of the value."""
+* every analytic partial matches central differences of the value;
+and of the taper's sine-series boundary (eq:taper_boundary): with no sine
+terms and equal end widths it is a box; at mid-length (envelope 1) the
+boundary sits where the series, evaluated by hand, puts it; its partials
+match central differences."""
 import numpy as np
 import pytest
 
@@ -89,4 +93,51 @@ def test_partials_match_central_differences(kind):
         vp[fi] += h
         vm[fi] -= h
         fd = (prm.polar(pr, vp, pts)[0] - prm.polar(pr, vm, pts)[0]) / (2 * h)
+        assert np.max(np.abs(fd - d)) < 1e-5 * max(1.0, np.max(np.abs(d))), fi
+
+
+# ---- the taper's sine-series boundary (eq:taper_boundary, eq:taper_eps)
+def _series(vs, w_in=0.5, w_out=0.5, kind="linear"):
+    return W.series(W.K(-1.0), W.K(5.0), [W.K(v) for v in vs], x0=0.3, L=2.0, w_in=w_in, w_out=w_out, yc=0.4,
+                    sig_x=(kind, "local", 1.0), sig_y=(kind, "local", 1.0))
+
+
+def test_series_straight_guide_is_a_box():
+    # no sine terms and equal widths: a box yc +- w/2 over [xs, xe]
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(-1.5, 5.5, 600), rng.uniform(-0.2, 1.0, 600)
+    pr = _series([0.0, 0.0, 0.0], w_in=0.5, w_out=0.5)
+    bx = W.box(x=(W.K(-1.0), W.K(5.0)), y=(W.K(0.4 - 0.25), W.K(0.4 + 0.25)))
+    pts = _pts(x, y, 0.03)
+    fs, _ = prm.series(pr, _vals(pr), pts)
+    fb, _ = prm.box(bx, _vals(bx), pts)
+    assert np.max(np.abs(fs - fb)) < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["linear", "sigmoid"])
+def test_series_boundary_at_mid_length(kind):
+    # x = x0 + L/2: envelope 1, sin(i pi / 2) = 1, 0, -1, 0, 1: f = ramp + v1 - v3 + v5
+    vs = [0.03, 0.02, -0.011, 0.05, 0.007]
+    w_in, w_out = 0.5, 1.3
+    f = w_in / 2 + (w_out - w_in) / 4 + vs[0] - vs[2] + vs[4]
+    pr = _series(vs, w_in, w_out, kind)
+    val, _ = prm.series(pr, _vals(pr), _pts([1.3, 1.3], [0.4 + f, 0.4 - f], 0.03))
+    assert np.max(np.abs(val - 0.5)) < 1e-12
+
+
+def test_series_partials_match_central_differences():
+    rng = np.random.default_rng(6)
+    K = 7
+    vals0 = [0.0, 4.0] + list(rng.normal(0, 0.02, K)) + [0.0, 0.0]
+    pr = _series([0.0] * K, 0.5, 1.1, "sigmoid")
+    x = rng.uniform(0.0, 4.2, 400)
+    y = 0.4 + rng.choice([-1.0, 1.0], 400) * (0.25 + 0.3 * (x - 0.3) / 2.0) + rng.uniform(-0.08, 0.08, 400)
+    pts = _pts(x, y, 0.03)
+    _, parts = prm.series(pr, vals0, pts)
+    h = 1e-6
+    for fi, d in parts[:2 + K]:
+        vp, vm = list(vals0), list(vals0)
+        vp[fi] += h
+        vm[fi] -= h
+        fd = (prm.series(pr, vp, pts)[0] - prm.series(pr, vm, pts)[0]) / (2 * h)
         assert np.max(np.abs(fd - d)) < 1e-5 * max(1.0, np.max(np.abs(d))), fi
