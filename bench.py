@@ -33,8 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TIMING_EVERY = 7
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_2311_05646_amd/csrc/sg_kernels.hip", "paper_2311_05646_amd/csrc/sg_device.h",
-                  "paper_2311_05646_amd/csrc/sg_internal.h"]
+KERNEL_SOURCES = ["paper_2311_05646_amd/csrc/sg_kernels.hip", "paper_2311_05646_amd/csrc/sg_column.h",
+                  "paper_2311_05646_amd/csrc/sg_device.h", "paper_2311_05646_amd/csrc/sg_internal.h"]
 
 
 def log(msg):

@@ -9,10 +9,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshapegrad.so")
-SOURCES = ["sg_api.hip", "sg_kernels.hip", "sg_serve.hip"]
+SOURCES = ["sg_api.hip", "sg_kernels.hip", "sg_serve.hip", "sg_mode_eps.hip", "sg_mode_vjp.hip", "sg_mode_geps.hip",
+           "sg_mode_fd.hip", "sg_mode_sparse.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-munsafe-fp-atomics",
     # never let the compiler form packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -20,15 +21,30 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
+    """Compiles every translation unit (in parallel: the column kernel's modes
+    are separate units) and links the shared library."""
+    import concurrent.futures
+    import tempfile
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libshapegrad.so")
+    with tempfile.TemporaryDirectory(prefix="sg_build_") as od:
+        objs = [os.path.join(od, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[HIPCC] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1))
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for cmd, r in zip(cmds, ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds)):
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+                if r.returncode != 0:
+                    sys.stderr.write(r.stdout + r.stderr)
+                    raise RuntimeError("hipcc failed building libshapegrad.so")
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        r = subprocess.run(link, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("linking libshapegrad.so failed")
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,0 +1,8 @@
+// Column-kernel instantiations for MODE_EPS (eps_build).
+#include "sg_column.h"
+
+namespace sg {
+
+template hipError_t launch_mode<MODE_EPS>(int, int, const KParams&, hipStream_t);
+
+}  // namespace sg

@@ -1,0 +1,8 @@
+// Column-kernel instantiations for MODE_VJP_GEPS (eps_grad_vjp_geps).
+#include "sg_column.h"
+
+namespace sg {
+
+template hipError_t launch_mode<MODE_VJP_GEPS>(int, int, const KParams&, hipStream_t);
+
+}  // namespace sg
