@@ -214,6 +214,20 @@ sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_de
                       const void* const* e_fwd, const void* const* e_adj, double omega,
                       double h, int scheme, double* grad, int grad_on_device, void* stream);
 
+/* Finite-difference baseline restricted to where each parameter acts (Sec.
+ * "Single-polarization blazed grating coupler in 2D", item (iv); the tracked
+ * finite differences of Sec. "Discussion and Conclusion"): same arguments and
+ * result as eps_grad_fd up to the order of the sums, but for each k only the
+ * in-plane tiles that the support boxes of the primitives referencing p_k
+ * meet (at p + h e_k or the other point), and only the column steps where a
+ * class is nonzero, are re-rasterized; the difference is multiplied by
+ * g = 2*omega*Im(E Eadj) in the same pass (no difference plane).  Parameters
+ * that an extrusion bound references re-rasterize every tile.  Uses one
+ * C-plane FP32 work buffer owned by the scene. */
+sg_status eps_grad_fd_sparse(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                             const void* const* e_fwd, const void* const* e_adj, double omega,
+                             double h, int scheme, double* grad, int grad_on_device, void* stream);
+
 /* Synthetic fields: n complex64 values each of E_fwd and E_adj (device), from
  * Philox4x32-10 (Salmon et al., SC'11) with counter (i mod 2^32, i div 2^32, 0, 0)
  * and key (seed mod 2^32, seed div 2^32); u_k = (x_k + 1/2) 2^-32 and two
@@ -283,7 +297,7 @@ sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches
  * so a period above 1 keeps a timed loop close to its untimed speed); 0
  * disables.  sg_scene_kernel_time() waits for the recorded launches
  * of one kind (mode: 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps,
- * 3 eps_grad_fd rasterization, 4 eps_grad_vjp_sparse) and returns their summed duration (ms) and
+ * 3 eps_grad_fd rasterization, 4 eps_grad_vjp_sparse, 5 eps_grad_fd_sparse) and returns their summed duration (ms) and
  * count. */
 sg_status sg_scene_set_timing(sg_scene* scene, int enable);
 sg_status sg_scene_kernel_time(sg_scene* scene, int mode, double* total_ms, int64_t* launches);

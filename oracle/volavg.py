@@ -10,6 +10,12 @@ compares against).
 * eps_boxes      -- exact set algebra for box-only scenes whose unions have
                     pairwise disjoint members and whose differences have the
                     subtrahend inside the minuend (what the generators build).
+* fourier_polygon, fourier_fraction_derivative -- the star-shaped region
+                    r < R(theta) of eq:PSGCboundary: its polygon, and the
+                    derivative of each cell's covered fraction with respect to
+                    one Fourier coefficient (the h -> 0 limit of the exact
+                    volume-averaged finite difference; parity unpinned beyond
+                    the test against clip_fraction differences).
 """
 import numpy as np
 
@@ -187,3 +193,45 @@ def supersample(inside, xs, xw, ys, yw, S):
     X = xs[None, :, None, None] + xw[None, :, None, None] * u[None, None, None, :]
     Y = ys[:, None, None, None] + yw[:, None, None, None] * u[None, None, :, None]
     return inside(X, Y).mean(axis=(2, 3))
+
+
+def fourier_radius(R0, cs, ss, th):
+    """R(theta) = R0 + sum_n c_n cos(n theta + pi) + s_n sin(n theta + pi)."""
+    R = R0 + 0.0 * th
+    for n in range(1, len(cs) + 1):
+        R = R + cs[n - 1] * np.cos(n * th + np.pi) + ss[n - 1] * np.sin(n * th + np.pi)
+    return R
+
+
+def fourier_polygon(x0, y0, R0, cs, ss, nvert=1000):
+    """Vertices (CCW) of r = R(theta) about (x0, y0) at nvert equal angles."""
+    th = 2.0 * np.pi * np.arange(nvert) / nvert
+    R = fourier_radius(R0, cs, ss, th)
+    return np.stack([x0 + R * np.cos(th), y0 + R * np.sin(th)], axis=1)
+
+
+def fourier_fraction_derivative(x0, y0, R0, cs, ss, which, xnodes, ynodes, nsamp=200000):
+    """d (covered fraction of each cell) / d coefficient for the region
+    r < R(theta): the area inside a cell changes at the boundary points that
+    lie in it, by R(theta) dR/dcoef dtheta (area = 1/2 int R^2 dtheta), summed
+    with the midpoint rule over nsamp angles and divided by the cell area.
+    which = ("c", n) or ("s", n) or ("R0", 0).  -> (Ny, Nx) on the cell lattice
+    given by the node arrays."""
+    th = 2.0 * np.pi * (np.arange(nsamp) + 0.5) / nsamp
+    R = fourier_radius(R0, cs, ss, th)
+    kind, n = which
+    if kind == "R0":
+        dR = np.ones_like(th)
+    elif kind == "c":
+        dR = np.cos(n * th + np.pi)
+    else:
+        dR = np.sin(n * th + np.pi)
+    x, y = x0 + R * np.cos(th), y0 + R * np.sin(th)
+    ix = np.searchsorted(xnodes, x, side="right") - 1
+    iy = np.searchsorted(ynodes, y, side="right") - 1
+    nx, ny = len(xnodes) - 1, len(ynodes) - 1
+    ok = (ix >= 0) & (ix < nx) & (iy >= 0) & (iy < ny)
+    out = np.zeros((ny, nx))
+    np.add.at(out, (iy[ok], ix[ok]), (R * dR)[ok] * (2.0 * np.pi / nsamp))
+    area = np.diff(ynodes)[:, None] * np.diff(xnodes)[None, :]
+    return out / area

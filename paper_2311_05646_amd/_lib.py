@@ -20,7 +20,7 @@ KMODE = {"local": 0, "fixed": 1}
 OP = {"union": 0, "intersection": 1, "difference": 2}
 AXIS = {"x": 0, "y": 1, "z": 2}
 FD_SCHEME = {"central": 0, "forward": 1}
-MODE = {"eps": 0, "vjp": 1, "geps": 2, "fd": 3, "sparse": 4}
+MODE = {"eps": 0, "vjp": 1, "geps": 2, "fd": 3, "sparse": 4, "fd_sparse": 5}
 
 
 class sg_field(C.Structure):
@@ -81,6 +81,7 @@ SIGNATURES = {
     "eps_grad_vjp_sparse": (_S, [_P, _P, _P, _I, _P, _P, _D, _P, _I, _P]),
     "sg_scene_sparse_reads": (_S, [_P, C.POINTER(C.c_int64)]),
     "eps_grad_fd": (_S, [_P, _P, _P, _I, _P, _P, _D, _D, _I, _P, _I, _P]),
+    "eps_grad_fd_sparse": (_S, [_P, _P, _P, _I, _P, _P, _D, _D, _I, _P, _I, _P]),
     "sg_scene_set_timing": (_S, [_P, _I]),
     "sg_scene_kernel_time": (_S, [_P, _I, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "sg_util_copy": (_S, [_P, _P, C.c_int64, _P]),

@@ -177,6 +177,18 @@ def eps_grad_fd(scene, p, E, A, omega, h, scheme="central", grad=None, stream=No
     return g
 
 
+def eps_grad_fd_sparse(scene, p, E, A, omega, h, scheme="central", grad=None, stream=None):
+    """eps_grad_fd re-rasterizing, per parameter, only the tiles and steps its
+    primitives reach, fused with the reduction."""
+    dev = torch.device("cuda", scene.device)
+    pp, pdev, keep = _p_arg(scene, p)
+    fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_fd_sparse(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), float(h),
+                                   _lib.FD_SCHEME[scheme], gp, gdev, _stream(stream)))
+    return g
+
+
 def util_copy(dst, src, stream=None):
     n = src.numel() * src.element_size()
     check(lib().sg_util_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n, _stream(stream)))

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshapegrad.so")
 SOURCES = ["sg_api.hip", "sg_kernels.hip", "sg_serve.hip", "sg_mode_eps.hip", "sg_mode_vjp.hip", "sg_mode_geps.hip",
-           "sg_mode_fd.hip", "sg_mode_sparse.hip"]
+           "sg_mode_fd.hip", "sg_mode_sparse.hip", "sg_mode_fdsparse.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -85,6 +85,8 @@ static void free_scene(sg_scene* s) {
     }
     hipFree(s->d_grad);
     hipFree(s->d_nread);
+    hipFree(s->d_kprim_off);
+    hipFree(s->d_kprim);
     if (s->h_p) hipHostFree(s->h_p);
     if (s->h_grad) hipHostFree(s->h_grad);
     if (s->p_evt) hipEventDestroy(s->p_evt);
@@ -497,6 +499,31 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         }
         prims.push_back(r);
     }
+    // parameter -> primitives (device order) and parameter -> extrusion bound
+    {
+        std::vector<std::vector<int32_t>> lists(std::max<int64_t>(1, d->n_params));
+        int dev = 0;
+        for (int i = 0; i < d->nprim; ++i) {
+            if (!used[i]) continue;
+            const sg_prim_desc& p = d->prims[i];
+            for (int f = 0; f < p.nfield; ++f) {
+                const int64_t k = d->fields[p.field_off + f].idx;
+                if (k >= 0 && (lists[k].empty() || lists[k].back() != dev)) lists[k].push_back(dev);
+            }
+            ++dev;
+        }
+        s->kprim_off.assign(1, 0);
+        for (const auto& l : lists) {
+            s->kprim.insert(s->kprim.end(), l.begin(), l.end());
+            s->kprim_off.push_back((int32_t)s->kprim.size());
+        }
+        s->k_wbound.assign(std::max<int64_t>(1, d->n_params), 0);
+        for (const DevClass& c : s->classes) {
+            if (!c.bounded) continue;
+            for (int f : {c.flo, c.fhi})
+                if (s->fields[f].idx >= 0) s->k_wbound[s->fields[f].idx] = 1;
+        }
+    }
     s->nprim = (int)prims.size();
     // smallest kernel variant covering the primitive types and in-plane sigma kinds
     {
@@ -542,6 +569,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     alloc((void**)&s->d_lat, lat.size() * sizeof(double));
     alloc((void**)&s->d_fref, std::max<int64_t>(1, d->nfield) * sizeof(sg_field));
     alloc((void**)&s->d_prims, prims.size() * sizeof(DevPrim));
+    alloc((void**)&s->d_kprim_off, s->kprim_off.size() * sizeof(int32_t));
+    alloc((void**)&s->d_kprim, std::max<size_t>(1, s->kprim.size()) * sizeof(int32_t));
     alloc((void**)&s->d_cls, s->classes.size() * sizeof(DevClass));
     alloc((void**)&s->d_consts, std::max(1, d->nconst) * sizeof(double));
     alloc((void**)&s->d_gseg, std::max<size_t>(1, gseg.size()) * sizeof(GSeg));
@@ -562,6 +591,10 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     if (e == hipSuccess && d->nfield)
         e = hipMemcpy(s->d_fref, d->fields, d->nfield * sizeof(sg_field), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->d_prims, prims.data(), prims.size() * sizeof(DevPrim), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(s->d_kprim_off, s->kprim_off.data(), s->kprim_off.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !s->kprim.empty())
+        e = hipMemcpy(s->d_kprim, s->kprim.data(), s->kprim.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(s->d_cls, s->classes.data(), s->classes.size() * sizeof(DevClass), hipMemcpyHostToDevice);
     if (e == hipSuccess && d->nconst)
@@ -918,9 +951,9 @@ extern "C" sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* s, const double* p
                       stream);
 }
 
-extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,
-                                 const void* const* e_adj, double omega, double h, int scheme, double* grad,
-                                 int grad_on_device, void* stream) {
+static sg_status fd_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,
+                           const void* const* e_adj, double omega, double h, int scheme, double* grad,
+                           int grad_on_device, void* stream, bool sparse) {
     sg_status rc = check_call(ctx, s);
     if (rc != SG_OK) return rc;
     if (!grad && s->n_params > 0) return fail(SG_E_INVALID, "grad is NULL");
@@ -932,7 +965,7 @@ extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int 
     std::lock_guard<std::mutex> lk(s->mu);
     hipStream_t st = (hipStream_t)stream;
     const int64_t total = (int64_t)s->ncomp * s->plane;
-    for (int v = 0; v < 2; ++v)
+    for (int v = 0; v < (sparse ? 1 : 2); ++v)
         if (!s->d_work[v]) HIP_OK(hipMalloc((void**)&s->d_work[v], total * sizeof(float) + 64));
     const double* dp;
     if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
@@ -947,18 +980,51 @@ extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int 
     }
     HIP_OK(launch_gplane(ef, ea, s->ncomp, s->plane, (float)(2.0 * omega), s->d_work[0], st));
     KParams kp = column_params(s);
-    kp.out = s->d_work[1];
     const double scale = scheme == SG_FD_CENTRAL ? 1.0 / (2.0 * h) : 1.0 / h;
+    if (sparse) {
+        kp.geps = s->d_work[0];
+        kp.grad = g;
+        kp.kprim_off = s->d_kprim_off;
+        kp.kprim = s->d_kprim;
+        kp.fd_scale = scale;
+        if (s->nseg == 0) {     // as the sparse VJP: the segments split only the live steps
+            kp.nseg = (kp.nseg + 3) / 4;
+            kp.seglen = ((s->nw + kp.nseg - 1) / kp.nseg + kGroup - 1) / kGroup * kGroup;
+            kp.nseg = (s->nw + kp.seglen - 1) / kp.seglen;
+        }
+    } else {
+        kp.out = s->d_work[1];
+    }
     for (int64_t k = 0; k < s->n_params; ++k) {
+        // (sparse) a parameter no field references has a zero derivative
+        if (sparse && s->kprim_off[k + 1] == s->kprim_off[k] && !s->k_wbound[k]) continue;
         StageParams sp = stage_params(s, dp);
         sp.pert_idx = k;
         sp.delta[0] = h;
         sp.delta[1] = scheme == SG_FD_CENTRAL ? -h : 0.0;
         HIP_OK(launch_stage(sp, 2, st));
-        if ((rc = run_column(s, MODE_FD, kp, st)) != SG_OK) return rc;
-        HIP_OK(launch_dot(s->d_work[0], s->d_work[1], total, scale, g + k, st));
+        if (sparse) {
+            kp.fd_k = (int32_t)k;
+            kp.fd_all = s->k_wbound[k];
+            if ((rc = run_column(s, MODE_FD_SPARSE, kp, st)) != SG_OK) return rc;
+        } else {
+            if ((rc = run_column(s, MODE_FD, kp, st)) != SG_OK) return rc;
+            HIP_OK(launch_dot(s->d_work[0], s->d_work[1], total, scale, g + k, st));
+        }
     }
     return finish_grad(s, grad, grad_on_device, st);
+}
+
+extern "C" sg_status eps_grad_fd(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,
+                                 const void* const* e_adj, double omega, double h, int scheme, double* grad,
+                                 int grad_on_device, void* stream) {
+    return fd_common(ctx, s, p, p_on_device, e_fwd, e_adj, omega, h, scheme, grad, grad_on_device, stream, false);
+}
+
+extern "C" sg_status eps_grad_fd_sparse(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,
+                                        const void* const* e_fwd, const void* const* e_adj, double omega, double h,
+                                        int scheme, double* grad, int grad_on_device, void* stream) {
+    return fd_common(ctx, s, p, p_on_device, e_fwd, e_adj, omega, h, scheme, grad, grad_on_device, stream, true);
 }
 
 // ------------------------------------------------------------------ utilities

@@ -893,6 +893,7 @@ template <int MODE, int TREE, int TYPES, int SIGS>
 __device__ __forceinline__ void column_body(const KParams& P, int b) {
     constexpr int NC = tree_nc(TREE);
     constexpr bool SPARSE = (MODE == MODE_VJP_SPARSE);
+    constexpr bool FDM = (MODE == MODE_FD || MODE == MODE_FD_SPARSE);     // two evaluation points
     constexpr bool FIELDS = (MODE == MODE_VJP_FIELDS) || SPARSE;
     constexpr bool VJP = FIELDS || (MODE == MODE_VJP_GEPS);
     constexpr int U = (MODE == MODE_VJP_GEPS) ? 8 : 4;      // steps per load set (multiple of kGroup)
@@ -915,12 +916,34 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     const int ngw = (P.nw + kGroup - 1) / kGroup;
     int w0 = seg * P.seglen;
     int w1 = min(w0 + P.seglen, P.nw);
-    if constexpr (SPARSE) {
+    if constexpr (SPARSE || MODE == MODE_FD_SPARSE) {
+        if constexpr (MODE == MODE_FD_SPARSE) {
+            // a tile that no primitive referencing the parameter reaches, at
+            // either evaluation point, has no difference
+            if (!P.fd_all) {
+                const Tile& T = G.T;
+                bool hit = false;
+                const int j1 = P.kprim_off[P.fd_k + 1];
+                for (int j = P.kprim_off[P.fd_k]; j < j1 && !hit; ++j) {
+                    const int pi = P.kprim[j];
+                    const float4 a = P.bbox[pi], c = P.bbox2[pi];
+                    hit = ((double)a.x <= T.uhi && (double)a.y >= T.ulo && (double)a.z <= T.vhi && (double)a.w >= T.vlo) ||
+                          ((double)c.x <= T.uhi && (double)c.y >= T.ulo && (double)c.z <= T.vhi && (double)c.w >= T.vlo);
+                }
+                if (!hit) return;
+            }
+        }
         // the segments split the component's steps from its first to its last
-        // group with some class at nonzero extrusion; a block whose segment
-        // is empty has nothing to add
+        // group with some class at nonzero extrusion (at either evaluation
+        // point); a block whose segment is empty has nothing to add
         int glo, ghi;
         live_groups(P.gcode + (int64_t)comp * ngw, ngw, glo, ghi);
+        if constexpr (MODE == MODE_FD_SPARSE) {
+            int glo2, ghi2;
+            live_groups(P.gcode2 + (int64_t)comp * ngw, ngw, glo2, ghi2);
+            glo = min(glo, glo2);
+            ghi = max(ghi, ghi2);
+        }
         if (ghi < glo) return;
         const int lw0 = glo * kGroup, lw1 = min(P.nw, (ghi + 1) * kGroup);
         const int slen = ((lw1 - lw0 + P.nseg - 1) / P.nseg + kGroup - 1) / kGroup * kGroup;
@@ -940,18 +963,18 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     const ConstF64 ztab = const_space<ConstF64>(P.ztab + zcomp);
     const ConstF64 ztab2 = const_space<ConstF64>(P.ztab2 + zcomp);
 
-    // combined code of a group / step (both evaluations for MODE_FD)
+    // combined code of a group / step (both evaluations for the FD modes)
     auto combine = [&](uint32_t c0, uint32_t c1) -> uint32_t {
-        if constexpr (MODE == MODE_FD)
+        if constexpr (FDM)
             return ((c0 | c1) & kCodeGeneral) ? kCodeGeneral : ((c0 & 0xFFu) | ((c1 & 0xFFu) << 8));
         else
             return c0;
     };
     auto group_code = [&](int w) -> uint32_t {
         const int gi = min(w / kGroup, ngw - 1);
-        return combine(gcode[gi], (MODE == MODE_FD) ? gcode2[gi] : 0u);
+        return combine(gcode[gi], FDM ? gcode2[gi] : 0u);
     };
-    auto step_code = [&](int w) -> uint32_t { return combine(code[w], (MODE == MODE_FD) ? code2[w] : 0u); };
+    auto step_code = [&](int w) -> uint32_t { return combine(code[w], FDM ? code2[w] : 0u); };
     auto load_zt = [&](ConstF64 zt, int w, double (&Z)[NC]) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) Z[c] = (c < P.nclass) ? zt[3 * ((int64_t)c * P.nw + w)] : 0.0;
@@ -1038,7 +1061,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     bool live = true;    // sparse: some in-plane partial of the sample can be nonzero
     inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
                                           s_cnt, s_rec, F, ncand, staged_all, first_loads, &live);
-    if constexpr (MODE == MODE_FD) {
+    if constexpr (FDM) {
         int nc2;
         bool sa2;
         inplane_sums<NC, TYPES, SIGS>(P, P.bbox2, P.prec2, P.fval2, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
@@ -1046,7 +1069,68 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     }
 
     // ---- 2. the column
-    if constexpr (MODE == MODE_EPS || MODE == MODE_FD) {
+    if constexpr (MODE == MODE_FD_SPARSE) {
+        // sum over the column segment of g * deps (s(p + h) - s(p - h)), the
+        // difference rounded to FP32 as the plane of MODE_FD stores it; g is
+        // read kChunk steps at a time with every load of a chunk in flight
+        constexpr int kChunk = 32;
+        auto diff = [&](const double (&Z)[NC], const double (&Z2)[NC]) -> float {
+            return (float)(P.deps * (compose<TREE>(P, F, Z).s - compose<TREE>(P, F2, Z2).s));
+        };
+        const char* gb = reinterpret_cast<const char*>(P.geps + (int64_t)comp * P.plane);
+        const int64_t g_bytes = P.plane * 4;
+        const int64_t g_step = P.sw * 4;
+        const uint32_t g_lane = (uint32_t)b0 * 4;
+        double acc = 0.0;
+        uint32_t cur = 0xFFFFFFFFu;
+        float run_out = 0.0f;
+        for (int wc = w0; wc < w1; wc += kChunk) {
+            const int64_t off = (int64_t)wc * g_step;
+            const __amdgpu_buffer_rsrc_t rg = buffer_rsrc(gb + off, min(g_bytes - off, (int64_t)(w1 - wc) * g_step));
+            float g[kChunk];
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+                g[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, g_lane, (int)(q * g_step), 0));
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+                const int w = wc + q;
+                if (w < w1) {
+                    const uint32_t c = step_code(w);
+                    float d;
+                    if (c & kCodeGeneral) {
+                        double Z[NC], Z2[NC];
+                        load_zt(ztab, w, Z);
+                        load_zt(ztab2, w, Z2);
+                        d = diff(Z, Z2);
+                    } else {
+                        if (c != cur) {
+                            double Z[NC], Z2[NC];
+                            mask_z<NC>(c & 0xFFu, Z);
+                            mask_z<NC>((c >> 8) & 0xFFu, Z2);
+                            run_out = diff(Z, Z2);
+                            cur = c;
+                        }
+                        d = run_out;
+                    }
+                    acc += (double)g[q] * (double)d;
+                }
+            }
+        }
+        if (!act) acc = 0.0;
+        // block sum, one atomic per block
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        __shared__ double s_fd[kBlock / 64];
+        if ((tid & 63) == 0) s_fd[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) t += s_fd[i];
+            if (t != 0.0) atomicAdd(P.grad + P.fd_k, t * P.fd_scale);
+        }
+        return;
+    } else if constexpr (MODE == MODE_EPS || MODE == MODE_FD) {
         auto value = [&](const double (&Z)[NC], const double (&Z2)[NC]) -> float {
             const double s = compose<TREE>(P, F, Z).s;
             if constexpr (MODE == MODE_EPS) {
@@ -1071,7 +1155,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                 if (gc != cur) {
                     double Z[NC], Z2[NC];
                     mask_z<NC>(gc & 0xFFu, Z);
-                    if constexpr (MODE == MODE_FD) mask_z<NC>((gc >> 8) & 0xFFu, Z2);
+                    if constexpr (FDM) mask_z<NC>((gc >> 8) & 0xFFu, Z2);
                     run_out = value(Z, Z2);
                     cur = gc;
                 }
@@ -1086,13 +1170,13 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                         if (c & kCodeGeneral) {
                             double Z[NC], Z2[NC];
                             load_zt(ztab, w + q, Z);
-                            if constexpr (MODE == MODE_FD) load_zt(ztab2, w + q, Z2);
+                            if constexpr (FDM) load_zt(ztab2, w + q, Z2);
                             out[q] = value(Z, Z2);
                         } else {
                             if (c != cur) {
                                 double Z[NC], Z2[NC];
                                 mask_z<NC>(c & 0xFFu, Z);
-                                if constexpr (MODE == MODE_FD) mask_z<NC>((c >> 8) & 0xFFu, Z2);
+                                if constexpr (FDM) mask_z<NC>((c >> 8) & 0xFFu, Z2);
                                 run_out = value(Z, Z2);
                                 cur = c;
                             }
@@ -1367,5 +1451,6 @@ extern template hipError_t launch_mode<MODE_VJP_FIELDS>(int, int, const KParams&
 extern template hipError_t launch_mode<MODE_VJP_GEPS>(int, int, const KParams&, hipStream_t);
 extern template hipError_t launch_mode<MODE_FD>(int, int, const KParams&, hipStream_t);
 extern template hipError_t launch_mode<MODE_VJP_SPARSE>(int, int, const KParams&, hipStream_t);
+extern template hipError_t launch_mode<MODE_FD_SPARSE>(int, int, const KParams&, hipStream_t);
 
 }  // namespace sg

@@ -19,7 +19,11 @@ constexpr int kReadSlots = 256;    // partial counters of the sparse VJP's read 
 // MODE_VJP_SPARSE: the fused VJP reading only the samples whose in-plane
 // derivatives do not all vanish and the column steps with a class at nonzero
 // extrusion (same result as MODE_VJP_FIELDS up to summation order).
-enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3, MODE_VJP_SPARSE = 4 };
+// MODE_FD_SPARSE: one parameter's central / forward difference restricted to
+// the tiles its primitives' support boxes meet (at either evaluation point)
+// and to the steps where a class is nonzero, multiplied by the g plane and
+// reduced in the same pass (no difference plane).
+enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3, MODE_VJP_SPARSE = 4, MODE_FD_SPARSE = 5 };
 // Column-step codes written by k_stage, one per (component, w): bits 0-7 hold
 // the mask of classes whose extrusion factor is exactly 1 when every class
 // factor is exactly 0 or 1 (and the w-bound derivatives of classes with
@@ -164,6 +168,13 @@ struct KParams {
     const float* geps;
     double* grad;
     unsigned long long* nread;   // MODE_VJP_SPARSE: (sample, step) pairs whose fields were read, kReadSlots partial counts
+    // MODE_FD_SPARSE: the perturbed parameter, its primitives (kprim[kprim_off[k] ..
+    // kprim_off[k + 1]]), whether an extrusion bound references it (every tile
+    // then takes part), and the difference scale 1 / (2h) or 1 / h
+    int32_t fd_k, fd_all;
+    const int32_t* kprim_off;
+    const int32_t* kprim;
+    double fd_scale;
 };
 
 // kernel launchers (sg_kernels.hip)

@@ -319,6 +319,7 @@ hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hip
         case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(tree, variant, kp, st);
         case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(tree, variant, kp, st);
         case MODE_VJP_SPARSE: return launch_mode<MODE_VJP_SPARSE>(tree, variant, kp, st);
+        case MODE_FD_SPARSE: return launch_mode<MODE_FD_SPARSE>(tree, variant, kp, st);
         default: return launch_mode<MODE_FD>(tree, variant, kp, st);
     }
 }

@@ -1,0 +1,8 @@
+// Column-kernel instantiations for MODE_FD_SPARSE (eps_grad_fd_sparse).
+#include "sg_column.h"
+
+namespace sg {
+
+template hipError_t launch_mode<MODE_FD_SPARSE>(int, int, const KParams&, hipStream_t);
+
+}  // namespace sg

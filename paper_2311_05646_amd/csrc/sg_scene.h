@@ -67,6 +67,12 @@ struct sg_scene {
     bool static_w = false;
     float* d_work[2] = {nullptr, nullptr};
     unsigned long long* d_nread = nullptr;   // sparse VJP: (sample, step) pairs read
+    // sparse FD: the primitives (device order) whose fields reference each
+    // parameter, CSR; and the parameters an extrusion bound references
+    std::vector<int32_t> kprim_off, kprim;
+    std::vector<char> k_wbound;
+    int32_t* d_kprim_off = nullptr;
+    int32_t* d_kprim = nullptr;
     double* h_p = nullptr;            // pinned staging
     double* h_grad = nullptr;
     hipEvent_t p_evt = nullptr;

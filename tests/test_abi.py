@@ -29,7 +29,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("eps_build", "eps_grad_vjp", "eps_grad_vjp_sparse", "eps_grad_vjp_geps", "eps_grad_fd",
-              "sg_scene_create"):
+              "eps_grad_fd_sparse", "sg_scene_create"):
         assert n in names
 
 

@@ -96,6 +96,27 @@ def test_fd(name, scheme):
     assert rel(got, ref) <= GRAD_TOL
 
 
+@pytest.mark.parametrize("name", ["c1", "c2_small", "c3_small", "c4_small", "zoo3_union", "zoo2_difference",
+                                  "psgc3_small", "taper3_sine_small"])
+@pytest.mark.parametrize("scheme", ["central", "forward"])
+def test_fd_sparse(name, scheme):
+    """The tile-skipping FD equals the plain FD (the tiles and steps it skips
+    have an exactly zero difference; it multiplies and sums in FP64 where the
+    plain FD's dot accumulates FP32 products within a block), and the
+    oracle's gradient within the FD tolerance."""
+    cfg = config(name)
+    print(f"[fd-sparse-{scheme}] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    E, A = fields_c64(cfg)
+    Ed, Ad = to_dev(E), to_dev(A)
+    h = cfg["h"] if scheme == "central" else min(cfg["h"], 1e-7)
+    got = api().eps_grad_fd_sparse(sc, cfg["p"], Ed, Ad, cfg["omega"], h, scheme=scheme)
+    plain = api().eps_grad_fd(sc, cfg["p"], Ed, Ad, cfg["omega"], h, scheme=scheme)
+    ref = S.grad_analytic(cfg["scene"], cfg["p"], S.sensitivity(E, A, cfg["omega"]))
+    assert rel(got, plain) <= 1e-6
+    assert rel(got, ref) <= GRAD_TOL
+
+
 def test_c1_matches_the_standard_method():
     """c1 is the paper's plain method: volume-averaged eps and its central FD
     gradient.  For cuboids with linear sigma the GPU AutoDiffGeo gradient is the

@@ -141,3 +141,28 @@ def test_series_partials_match_central_differences():
         vm[fi] -= h
         fd = (prm.series(pr, vp, pts)[0] - prm.series(pr, vm, pts)[0]) / (2 * h)
         assert np.max(np.abs(fd - d)) < 1e-5 * max(1.0, np.max(np.abs(d))), fi
+
+
+def test_fourier_fraction_derivative_matches_clipped_differences():
+    # the boundary-integral derivative of each cell's covered fraction equals
+    # central differences of the exact polygon clip (fine polygon, small h)
+    from oracle import volavg as V
+    xn = np.linspace(-0.3, 0.3, 13)
+    yn = np.linspace(-0.3, 0.3, 13)
+    xs, ys = 0.5 * (xn[1:] + xn[:-1]), 0.5 * (yn[1:] + yn[:-1])
+    xw, yw = np.diff(xn), np.diff(yn)
+    cs, ss = [0.01, -0.006, 0.004], [0.003, 0.005, -0.002]
+    h = 1e-4
+    for which, idx in ((("c", 1), 0), (("s", 2), 1), (("R0", 0), None)):
+        def frac(dv):
+            c2, s2, r0 = list(cs), list(ss), 0.17
+            if which[0] == "c":
+                c2[idx] += dv
+            elif which[0] == "s":
+                s2[idx] += dv
+            else:
+                r0 += dv
+            return V.clip_fraction_grid(V.fourier_polygon(0.01, -0.02, r0, c2, s2, 3000), xs, xw, ys, yw)
+        fd = (frac(h) - frac(-h)) / (2 * h)
+        an = V.fourier_fraction_derivative(0.01, -0.02, 0.17, cs, ss, which, xn, yn, 400000)
+        assert np.max(np.abs(fd - an)) < 2e-3 * np.max(np.abs(fd)), which
