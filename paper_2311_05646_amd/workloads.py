@@ -406,6 +406,33 @@ def make_psgc(seed=BASE_SEED + 5, with_fields=True, **kw):
     return out
 
 
+def make_prop2_plane(kind, k_r, seed=BASE_SEED + 7, nside=3, pitch=0.6, dx=0.03, order=6, coef=0.02):
+    """The Prop. 2 study plane: a 2D cross-section (Ez) of a slab with an
+    nside x nside lattice of etched Fourier-radius scatterers sharing global
+    coefficients (p[0] = c_1, ..., p[2 order - 1] = s_N) and each with its own
+    R0; sigma kind `kind` with k = k_r / dx (FIXED).  Fields N(0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    n = int(round(nside * pitch / dx))
+    X = uniform_nodes(n, dx)
+    Y = uniform_nodes(n, dx)
+    p = [rng.normal(0.0, coef / m) for m in list(range(1, order + 1)) * 2]
+    cs = [P(i) for i in range(order)]
+    ss = [P(order + i) for i in range(order)]
+    prims = [box(x=None, y=None)]
+    for i in range(nside):
+        for j in range(nside):
+            cx = pitch / 2 + pitch * i + rng.uniform(-0.03, 0.03)
+            cy = pitch / 2 + pitch * j + rng.uniform(-0.03, 0.03)
+            p.append(rng.uniform(0.16, 0.22))
+            prims.append(polar(K(cx), K(cy), P(len(p) - 1), cs, ss, sig=(kind, "fixed", k_r / dx)))
+    scene = {"name": "prop2", "dim": 2, "nodes": [X, Y, np.array([0.0, 1.0])], "components": ("z",),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "difference", "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}}
+    out = {"scene": scene, "p": np.array(p), "omega": _wl_omega(1.31), "h": 1e-7, "dx": dx}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
 def make_c4(seed=BASE_SEED + 3, with_fields=True, **kw):
     """3D polarization-splitting grating: 400x400x80 at 25 nm; slab minus a
     40x40 lattice of elliptical holes, (x, y, r) per hole (4800 params)."""
