@@ -102,8 +102,13 @@ enum { SG_SIGMA_SIGMOID = 0, SG_SIGMA_ERF = 1, SG_SIGMA_SIN = 2, SG_SIGMA_LINEAR
 /* k modes: LOCAL k = k / (sample width along the argument's axis); FIXED k as given (1/um). */
 enum { SG_K_LOCAL = 0, SG_K_FIXED = 1 };
 /* op-tree nodes: union min{1, sum} (eq:union), intersection max{N-1, sum} - (N-1)
- * (eq:intersection), difference max{0, a - b} (exactly two operands). */
-enum { SG_OP_UNION = 0, SG_OP_INTERSECTION = 1, SG_OP_DIFFERENCE = 2 };
+ * (eq:intersection), difference max{0, a - b} (exactly two operands), and the
+ * non-binary union of Alg. cap (Sec. "Non-binary material systems"), root
+ * only: children are K >= 2 material sets (each a union / intersection node or
+ * one primitive) with levels eps^1 <= ... <= eps^K relative to the background
+ * (consts[aux .. aux + K), the top one equal to eps_fg - eps_bg);
+ * s = v_1, s = min{1, (eps^{k-1} / eps^k) s + v_k} for k = 2..K, eps = eps_bg + eps^K s. */
+enum { SG_OP_UNION = 0, SG_OP_INTERSECTION = 1, SG_OP_DIFFERENCE = 2, SG_OP_LEVELS = 3 };
 /* finite-difference schemes for eps_grad_fd */
 enum { SG_FD_CENTRAL = 0, SG_FD_FORWARD = 1 };
 
@@ -126,7 +131,7 @@ typedef struct sg_node_desc {
     int32_t op;
     int32_t nchild;
     int32_t child_off;    /* into sg_scene_desc.children */
-    int32_t pad;
+    int32_t aux;          /* SG_OP_LEVELS: first of its nchild level values in consts */
 } sg_node_desc;
 
 typedef struct sg_scene_desc {
@@ -175,7 +180,8 @@ sg_status eps_build(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_devi
 
 /* Step 5, fused (eq:1, eq:AD): e_fwd and e_adj are arrays of C device pointers
  * to complex64 planes.  grad_k = sum_c sum_j 2*omega*Im(E_cj Eadj_cj) d eps_cj/d p_k
- * (no conjugation). */
+ * (no conjugation).  The mu / H term of eq:1 has the same form: call this with
+ * a scene describing mu and the H, H_adj planes, and add the two gradients. */
 sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
                        const void* const* e_fwd, const void* const* e_adj, double omega,
                        double* grad, int grad_on_device, void* stream);

@@ -40,8 +40,18 @@ def check_scene(desc):
             seen.append(int(node))
             return
         op = node["op"]
-        if op not in ("union", "intersection", "difference"):
+        if op not in ("union", "intersection", "difference", "levels"):
             raise ValueError(f"unknown op {op!r}")
+        if op == "levels":
+            if node is not desc["tree"]:
+                raise ValueError("a levels node must be the root")
+            lv = [float(x) for x in node["levels"]]
+            if len(lv) != len(node["children"]) or len(lv) < 2:
+                raise ValueError("levels: one level per child, at least two")
+            if any(not (b >= a > 0.0) for a, b in zip(lv, lv[1:])) or lv[0] <= 0.0:
+                raise ValueError("levels must be positive and ascending")
+            if abs(lv[-1] - (desc["eps_fg"] - desc["eps_bg"])) > 1e-12 * max(1.0, abs(lv[-1])):
+                raise ValueError("the top level must equal eps_fg - eps_bg")
         if op == "difference" and len(node["children"]) != 2:
             raise ValueError("difference takes exactly two operands")
         if len(node["children"]) == 0:
@@ -118,6 +128,26 @@ def _compose(node, svals, shape):
         vals.append(np.broadcast_to(v, shape))
         lists.append(l)
     op = node["op"]
+    if op == "levels":
+        # Alg. cap (non-binary union): s = v_1; s = min{1, (eps^{k-1} / eps^k) s
+        # + v_k} for k = 2..K; the node value is s (eps = eps_bg + eps^K s)
+        lv = [float(x) for x in node["levels"]]
+        s = vals[0]
+        passes, qs = [None], [None]
+        for k in range(1, len(vals)):
+            q = lv[k - 1] / lv[k]
+            x = q * s + vals[k]
+            passes.append((x < 1.0).astype(np.float64))
+            qs.append(q)
+            s = np.minimum(1.0, x)
+        # d s / d v_k = pass_k prod_{j > k} pass_j q_j (k >= 2), prod_{j >= 2} pass_j q_j (k = 1)
+        coef = [None] * len(vals)
+        acc = np.ones(shape)
+        for k in range(len(vals) - 1, 0, -1):
+            coef[k] = acc * passes[k]
+            acc = acc * passes[k] * qs[k]
+        coef[0] = acc
+        return s, [(i, c * coef[k]) for k, l in enumerate(lists) for (i, c) in l]
     if op == "union":
         S = np.sum(vals, axis=0)
         out = np.minimum(1.0, S)

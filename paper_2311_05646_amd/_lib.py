@@ -17,7 +17,7 @@ STATUS = {0: "SG_OK", 1: "SG_EAGAIN", -1: "SG_E_INVALID", -2: "SG_E_NOMEM", -3: 
 PRIM = {"box": 0, "ellipse": 1, "poly": 2, "gcart": 3, "polar": 4, "series": 5}
 SIGMA = {"sigmoid": 0, "erf": 1, "sin": 2, "linear": 3, "quadratic": 4}
 KMODE = {"local": 0, "fixed": 1}
-OP = {"union": 0, "intersection": 1, "difference": 2}
+OP = {"union": 0, "intersection": 1, "difference": 2, "levels": 3}
 AXIS = {"x": 0, "y": 1, "z": 2}
 FD_SCHEME = {"central": 0, "forward": 1}
 MODE = {"eps": 0, "vjp": 1, "geps": 2, "fd": 3, "sparse": 4, "fd_sparse": 5}
@@ -38,7 +38,7 @@ class sg_prim_desc(C.Structure):
 
 
 class sg_node_desc(C.Structure):
-    _fields_ = [("op", C.c_int32), ("nchild", C.c_int32), ("child_off", C.c_int32), ("pad", C.c_int32)]
+    _fields_ = [("op", C.c_int32), ("nchild", C.c_int32), ("child_off", C.c_int32), ("aux", C.c_int32)]
 
 
 class sg_scene_desc(C.Structure):
@@ -153,7 +153,6 @@ def marshal_scene(desc):
     fa = (sg_field * max(1, len(fields)))()
     for i, (a, b, idx) in enumerate(fields):
         fa[i].a, fa[i].b, fa[i].idx = float(a), float(b), int(idx)
-    ca = (C.c_double * max(1, len(consts)))(*[float(c) for c in consts])
     # op tree -> postfix node list
     nodes, children = [], []
 
@@ -161,15 +160,21 @@ def marshal_scene(desc):
         if isinstance(node, (int, np.integer)):
             return int(node)
         ch = [walk(c) for c in node["children"]]
-        nodes.append((OP[node["op"]], ch))
+        aux = 0
+        if node["op"] == "levels":      # level values go after the primitives' constants
+            aux = len(consts)
+            consts.extend(float(x) for x in node["levels"])
+        nodes.append((OP[node["op"]], ch, aux))
         return -len(nodes)          # node k is referenced as -(k + 1)
 
     walk(desc["tree"])
+    ca = (C.c_double * max(1, len(consts)))(*[float(c) for c in consts])
     na = (sg_node_desc * len(nodes))()
-    for k, (op, ch) in enumerate(nodes):
+    for k, (op, ch, aux) in enumerate(nodes):
         na[k].op = op
         na[k].nchild = len(ch)
         na[k].child_off = len(children)
+        na[k].aux = aux
         children += ch
     cha = (C.c_int32 * len(children))(*children)
     s = sg_scene_desc()

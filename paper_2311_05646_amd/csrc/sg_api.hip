@@ -217,7 +217,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     auto child = [&](const sg_node_desc& nd, int c) -> int { return d->children[nd.child_off + c]; };
     for (int k = 0; k < d->nnode; ++k) {
         const sg_node_desc& nd = d->nodes_op[k];
-        if (nd.op < SG_OP_UNION || nd.op > SG_OP_DIFFERENCE) return fail(SG_E_INVALID, "node %d: op", k);
+        if (nd.op < SG_OP_UNION || nd.op > SG_OP_LEVELS) return fail(SG_E_INVALID, "node %d: op", k);
+        if (nd.op == SG_OP_LEVELS && k != d->nnode - 1) return fail(SG_E_INVALID, "node %d: levels must be the root", k);
         if (nd.nchild < 1 || nd.child_off < 0 || nd.child_off + nd.nchild > d->nchild)
             return fail(SG_E_INVALID, "node %d: children", k);
         if (nd.op == SG_OP_DIFFERENCE && nd.nchild != 2) return fail(SG_E_INVALID, "node %d: difference takes 2", k);
@@ -232,6 +233,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         const sg_node_desc& nd = d->nodes_op[nodeidx];
         if (nd.op == SG_OP_DIFFERENCE)
             return fail(SG_E_UNSUPPORTED, "a difference below the root is not supported by the GPU path");
+        if (nd.op == SG_OP_LEVELS) return fail(SG_E_INVALID, "levels must be the root");
         g.op = nd.op;
         g.nmember = nd.nchild;
         for (int c = 0; c < nd.nchild; ++c) {
@@ -242,7 +244,36 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         return SG_OK;
     };
     int root_op;
-    if (root.op == SG_OP_DIFFERENCE) {
+    double group_q[kMaxGroups] = {1.0, 1.0, 1.0, 1.0};    // levels root: eps^{g-1} / eps^g
+    if (root.op == SG_OP_LEVELS) {
+        // one group per material set, in level order
+        root_op = SG_OP_LEVELS;
+        const int K = root.nchild;
+        if (K < 2 || K > kMaxGroups) return fail(SG_E_UNSUPPORTED, "levels: 2 to %d material sets", kMaxGroups);
+        if (root.aux < 0 || root.aux + K > d->nconst) return fail(SG_E_INVALID, "levels: level values out of consts");
+        const double* lv = d->consts + root.aux;
+        for (int c = 0; c < K; ++c) {
+            if (!(lv[c] > 0.0) || !std::isfinite(lv[c]) || (c > 0 && lv[c] < lv[c - 1]))
+                return fail(SG_E_INVALID, "levels: values must be positive and ascending");
+            group_q[c] = c == 0 ? 1.0 : lv[c - 1] / lv[c];
+        }
+        const double top = d->eps_fg - d->eps_bg;
+        if (std::fabs(lv[K - 1] - top) > 1e-12 * std::max(1.0, std::fabs(top)))
+            return fail(SG_E_INVALID, "levels: the top level must equal eps_fg - eps_bg");
+        for (int c = 0; c < K; ++c) {
+            Group g;
+            const int ch = child(root, c);
+            if (ch >= 0) {
+                g.op = SG_OP_UNION;
+                g.nmember = 1;
+                g.prims.push_back(ch);
+            } else {
+                sg_status st = leaf_group(-(ch + 1), g);
+                if (st != SG_OK) return st;
+            }
+            groups.push_back(g);
+        }
+    } else if (root.op == SG_OP_DIFFERENCE) {
         root_op = SG_OP_DIFFERENCE;
         for (int c = 0; c < 2; ++c) {
             Group g;
@@ -408,6 +439,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     for (int g = 0; g < kMaxGroups; ++g) {
         s->group_op[g] = g < s->ngroup ? groups[g].op : SG_OP_UNION;
         s->group_nm1[g] = g < s->ngroup ? (double)(groups[g].nmember - 1) : 0.0;
+        s->group_q[g] = group_q[g];
     }
     s->root_nm1 = (double)(s->ngroup - 1);
 
@@ -739,6 +771,7 @@ KParams sg::column_params(sg_scene* s) {
     for (int g = 0; g < kMaxGroups; ++g) {
         kp.group_op[g] = s->group_op[g];
         kp.group_nm1[g] = s->group_nm1[g];
+        kp.group_q[g] = s->group_q[g];
     }
     kp.root_nm1 = s->root_nm1;
     kp.eps_bg = s->eps_bg;

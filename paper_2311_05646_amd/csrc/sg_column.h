@@ -346,6 +346,32 @@ __device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree
             o.s = v0;
             o.r0 = m0;
             o.r1 = o.r2 = o.r3 = 0.0;
+        } else if (P.root_op == SG_OP_LEVELS) {
+            // Alg. cap: s = v_0, s = min{1, q_g s + v_g}; d s / d v_g = pass_g prod_{j > g} pass_j q_j
+            const double v[4] = {v0, v1, v2, v3}, mk[4] = {m0, m1, m2, m3};
+            double s = v0, pass[4] = {1.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int g = 1; g < 4; ++g) {
+                if (g < P.ngroup) {
+                    const double x = P.group_q[g] * s + v[g];
+                    pass[g] = x < 1.0 ? 1.0 : 0.0;
+                    s = fmin(1.0, x);
+                }
+            }
+            double r[4] = {0.0, 0.0, 0.0, 0.0}, acc = 1.0;
+#pragma unroll
+            for (int g = 3; g >= 1; --g) {
+                if (g < P.ngroup) {
+                    r[g] = acc * pass[g];
+                    acc *= pass[g] * P.group_q[g];
+                }
+            }
+            r[0] = acc;
+            o.s = s;
+            o.r0 = r[0] * mk[0];
+            o.r1 = r[1] * mk[1];
+            o.r2 = r[2] * mk[2];
+            o.r3 = r[3] * mk[3];
         } else if (P.root_op == SG_OP_DIFFERENCE) {
             const double d = v0 - v1;
             o.s = fmax(0.0, d);

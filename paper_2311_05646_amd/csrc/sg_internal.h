@@ -137,6 +137,7 @@ struct KParams {
     int32_t ngroup, root_op;
     int32_t group_op[kMaxGroups];
     double group_nm1[kMaxGroups];
+    double group_q[kMaxGroups];  // SG_OP_LEVELS root: eps^{g-1} / eps^g (g >= 1)
     double root_nm1;
     double eps_bg, deps;
     const double* uc[kMaxComp];

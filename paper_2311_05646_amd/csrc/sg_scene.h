@@ -37,6 +37,7 @@ struct sg_scene {
     int64_t sv = 0, sw = 0, plane = 0;
     int nprim = 0, nclass = 0, ncls_pad = 1;
     int variant = sg::VAR_ALL;
+    double group_q[sg::kMaxGroups] = {1.0, 1.0, 1.0, 1.0};   // levels root: eps^{g-1} / eps^g
     int tree = sg::TR_GEN8;
     int ngroup = 0, root_op = sg::ROOT_NONE;
     int group_op[sg::kMaxGroups] = {0, 0, 0, 0};

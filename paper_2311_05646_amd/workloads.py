@@ -577,6 +577,41 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     return out
 
 
+def make_levels(seed=BASE_SEED + 22, dim=2, levels=(0.1, 0.34, 0.62, 1.0)):
+    """Four material sets under the non-binary union (Alg. cap): a circle from
+    each quadrant, brought towards the center so that all four overlap there
+    (the paper's Fig. nonbinary_union), the second set with an extra box and
+    the third a union of two circles.  Levels relative to eps_bg = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    X = uniform_nodes(40, 0.025)
+    Y = uniform_nodes(36, 0.025)
+    Z = uniform_nodes(8, 0.03) if dim == 3 else np.array([0.0, 1.0])
+    z = (P(0), K(float(Z[6]))) if dim == 3 else None
+    p = [float(Z[2]) + 0.004] if dim == 3 else []
+
+    def par(v):
+        p.append(v)
+        return P(len(p) - 1)
+
+    u = lambda a, b: float(rng.uniform(a, b))
+    sig = ("sigmoid", "fixed", 45.0)
+    cx, cy = 0.5, 0.45
+    prims = []
+    for qx, qy in ((-1, -1), (1, -1), (-1, 1), (1, 1)):
+        prims.append(ellipse(par(cx + qx * 0.12 + u(-.01, .01)), par(cy + qy * 0.11 + u(-.01, .01)),
+                             par(0.19 + u(-.01, .01)), z=z, sig=sig))
+    prims.append(box(x=(par(0.0537), par(0.2561)), y=(K(0.7013), K(0.8488)), z=z,
+                     sig=(LIN, ("quadratic", "local", 1.0), LIN)))
+    prims.append(ellipse(par(0.8537), par(0.7461), par(0.0813), z=z, sig=("erf", "fixed", 30.0)))
+    tree = {"op": "levels", "levels": list(levels),
+            "children": [0, {"op": "union", "children": [1, 4]}, {"op": "union", "children": [2, 5]}, 3]}
+    scene = {"name": f"levels{dim}d", "dim": dim, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": 1.0, "eps_fg": 1.0 + levels[-1], "n_params": len(p), "prims": prims, "tree": tree}
+    out = {"scene": scene, "p": np.array(p), "omega": 2 * math.pi / 1.4, "h": 1e-7}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
 def make_crowd(seed=BASE_SEED + 21, n_ell=50, n_box=30):
     """A slab minus a crowd of small sigmoid ellipses and linear boxes packed
     into a 0.34 um square, so that one in-plane tile holds far more candidate
@@ -646,6 +681,7 @@ CONFIGS = {
     "crowd3": make_crowd, "many2": make_many,
     "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
     "taper3_sine": make_taper_sine, "taper3_sine_small": make_taper_sine_small,
+    "levels2": lambda: make_levels(dim=2), "levels3": lambda: make_levels(dim=3),
 }
 
 

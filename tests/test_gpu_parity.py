@@ -16,10 +16,10 @@ pytestmark = pytest.mark.gpu
 # primitives than one candidate scan pass; psgc3_small(_local): Fourier-radius
 # scatterers with global (shared) or per-scatterer shape coefficients;
 # taper3_sine_small: the taper's sine-series boundary (every parameter reaches
-# every column of it)
+# every column of it); levels2/3: the non-binary union over four material sets
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
          "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
-         "psgc3_small", "psgc3_small_local", "taper3_sine_small"]
+         "psgc3_small", "psgc3_small_local", "taper3_sine_small", "levels2", "levels3"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 

@@ -61,3 +61,63 @@ def test_clamp_derivative_rules():
     s = {0: np.array([0.7, 0.4]), 1: np.array([0.2, 0.4])}
     _, coefs = _compose(node, s, (2,))
     assert [list(c) for _, c in coefs] == [[1.0, 0.0], [-1.0, -0.0]]
+
+
+# ---- non-binary union (Alg. cap, Sec. "Non-binary material systems")
+def _levels(levels, *vals):
+    vals = [np.asarray(v, dtype=np.float64) for v in vals]
+    shape = np.broadcast(*vals).shape
+    node = {"op": "levels", "levels": list(levels), "children": list(range(len(vals)))}
+    return _compose(node, {i: np.broadcast_to(v, shape) for i, v in enumerate(vals)}, shape)
+
+
+def test_levels_single_set_gives_its_own_level():
+    # where only set k is present (fill v), eps - eps_bg = eps^k v
+    lv = (0.1, 0.34, 0.62, 1.0)
+    v = np.linspace(0.0, 1.0, 11)
+    z = np.zeros_like(v)
+    for k in range(4):
+        vals = [z] * 4
+        vals[k] = v
+        s, _ = _levels(lv, *vals)
+        assert np.max(np.abs(lv[-1] * s - lv[k] * v)) < 1e-15
+
+
+def test_levels_priority_to_the_largest_level():
+    # where sets overlap fully, the largest present level wins
+    lv = (0.1, 0.34, 0.62, 1.0)
+    for present in np.ndindex(2, 2, 2, 2):
+        if sum(present) == 0:
+            continue
+        s, _ = _levels(lv, *[np.array(float(b)) for b in present])
+        top = max(lv[k] for k in range(4) if present[k])
+        assert abs(lv[-1] * float(s) - top) < 1e-15, present
+
+
+def test_levels_with_equal_levels_is_the_union():
+    rng = np.random.default_rng(3)
+    vals = [rng.uniform(0, 1, 200) * rng.integers(0, 2, 200) for _ in range(3)]
+    s, _ = _levels((1.0, 1.0, 1.0), *vals)
+    assert np.max(np.abs(s - _op("union", *vals))) < 1e-15
+
+
+def test_levels_chain_rule_matches_differences():
+    rng = np.random.default_rng(4)
+    lv = (0.2, 0.5, 1.3)
+    vals = [rng.uniform(0, 0.6, 500) for _ in range(3)]
+    _, parts = _levels(lv, *vals)
+    h = 1e-7
+    for i, d in parts:
+        vp = [v.copy() for v in vals]
+        vm = [v.copy() for v in vals]
+        vp[i] += h
+        vm[i] -= h
+        fd = (_levels(lv, *vp)[0] - _levels(lv, *vm)[0]) / (2 * h)
+        # away from the clamp kinks the chain rule is the derivative
+        x_far = np.ones(500, dtype=bool)
+        s = vals[0]
+        for k in (1, 2):
+            x = lv[k - 1] / lv[k] * s + vals[k]
+            x_far &= np.abs(x - 1.0) > 1e-5
+            s = np.minimum(1.0, x)
+        assert np.max(np.abs(fd - d)[x_far]) < 1e-6, i

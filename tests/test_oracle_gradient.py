@@ -42,6 +42,17 @@ def test_zoo_fd_matches_analytic(dim, root):
     assert np.count_nonzero(ga) >= 8
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_levels_fd_matches_analytic(dim):
+    # the non-binary union (Alg. cap) through the whole scene
+    cfg = W.make_levels(dim=dim)
+    g = S.sensitivity(cfg["E"], cfg["A"], cfg["omega"])
+    ga = S.grad_analytic(cfg["scene"], cfg["p"], g)
+    gf = S.grad_fd(cfg["scene"], cfg["p"], g, 1e-6)
+    assert _rel(gf, ga) < 1e-6
+    assert np.count_nonzero(ga) >= 12
+
+
 def test_forward_fd_matches_analytic_c1():
     cfg = W.make_c1()
     g = S.sensitivity(cfg["E"], cfg["A"], cfg["omega"])
