@@ -572,10 +572,10 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
                 if (p.type == SG_PRIM_GCART || p.type == SG_PRIM_SERIES) smask |= sigma_bit(p.sigma[1].kind);
             }
         }
-        const int vt[4] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL, T_BOX | T_POLAR};
-        const int vs[4] = {S_LIN, S_LIN, S_LIN | S_SIGMOID, S_LIN | S_SIGMOID};
+        const int vt[5] = {T_BOX, T_BOX | T_GCART, T_BOX | T_ELL, T_BOX | T_POLAR, T_BOX | T_SERIES};
+        const int vs[5] = {S_LIN, S_LIN, S_LIN | S_SIGMOID, S_LIN | S_SIGMOID, S_LIN};
         s->variant = VAR_ALL;
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 5; ++v)
             if ((tmask & ~vt[v]) == 0 && (smask & ~vs[v]) == 0) { s->variant = v; break; }
         // op-tree layout
         auto plain_union = [&](int g) { return groups[g].op == SG_OP_UNION || groups[g].nmember == 1; };

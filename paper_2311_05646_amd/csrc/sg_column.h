@@ -1467,6 +1467,7 @@ hipError_t launch_mode(int tree, int variant, const KParams& kp, hipStream_t st)
         case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(tree, kp, st);
         case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, kp, st);
         case VAR_POLAR_SIGMOID: return launch_variant<MODE, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, kp, st);
+        case VAR_SERIES_LIN: return launch_variant<MODE, T_BOX | T_SERIES, S_LIN>(tree, kp, st);
         default: return launch_variant<MODE, T_ALL, S_ALL>(tree, kp, st);
     }
 }

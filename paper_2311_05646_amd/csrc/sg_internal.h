@@ -34,7 +34,8 @@ constexpr uint32_t kCodeGeneral = 1u << 16;
 constexpr int kGroup = 4;    // the stage kernel and the stream kernel's group paths assume 4
 enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
 // kernel feature variants (primitive types x in-plane sigma kinds), smallest first
-enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_POLAR_SIGMOID = 3, VAR_ALL = 4 };
+enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_POLAR_SIGMOID = 3, VAR_SERIES_LIN = 4,
+               VAR_ALL = 5 };
 // op-tree layouts compiled into the column kernel: one union over 1 or 2
 // extrusion classes; the difference of two unions over (1, 1) or (1, 2)
 // classes; anything else through the generic composition (4 or 8 classes).

@@ -14,6 +14,8 @@ hipError_t launch_column_batch(int tree, int variant, const KParams* plist, cons
         case VAR_ELL_SIGMOID:
             return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, plist, first, nreq, blocks,
                                                                                           st);
+        case VAR_SERIES_LIN:
+            return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_SERIES, S_LIN>(tree, plist, first, nreq, blocks, st);
         case VAR_POLAR_SIGMOID:
             return launch_batch_variant<MODE_VJP_FIELDS, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, plist, first, nreq,
                                                                                             blocks, st);

@@ -200,3 +200,18 @@ def test_invalid_inputs_raise():
     d["tree"] = {"op": "union", "children": [{"op": "union", "children": [{"op": "union", "children": [0]}]}, 1]}
     with pytest.raises(SGError):
         api().Scene(d)
+    # the non-binary union: levels ascending, the top one = eps_fg - eps_bg, at the root only
+    lv = W.make_levels(dim=2)["scene"]
+    for tree in ({"op": "levels", "levels": [0.34, 0.1, 0.62, 1.0], "children": lv["tree"]["children"]},
+                 {"op": "levels", "levels": [0.1, 0.34, 0.62, 0.9], "children": lv["tree"]["children"]},
+                 {"op": "union", "children": [{"op": "levels", "levels": [0.5, 1.0], "children": [0, 1]}, 2]}):
+        with pytest.raises(SGError):
+            api().Scene(dict(lv, tree=tree))
+    # Fourier order above 29; a sine series with L <= 0
+    pol = W.polar(W.K(0.5), W.K(0.5), W.K(0.2), [W.K(0.0)] * 30, [W.K(0.0)] * 30, sig=("sigmoid", "fixed", 40.0))
+    ser = W.series(W.K(0.1), W.K(0.9), [W.K(0.0)] * 3, x0=0.1, L=1.0, w_in=0.1, w_out=0.2, yc=0.5)
+    ser["consts"][1] = 0.0
+    for pr in (pol, ser):
+        bad = dict(lv, prims=[pr], n_params=0, tree={"op": "union", "children": [0]})
+        with pytest.raises(SGError):
+            api().Scene(bad)
