@@ -75,6 +75,7 @@ SIGNATURES = {
     "sg_scene_destroy": (None, [_P]),
     "sg_scene_info": (_S, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "sg_scene_set_launch": (_S, [_P, C.c_int32, C.c_int32]),
+    "sg_scene_set_deterministic": (_S, [_P, _I]),
     "eps_build": (_S, [_P, _P, _P, _I, _P, _P]),
     "eps_grad_vjp": (_S, [_P, _P, _P, _I, _P, _P, _D, _P, _I, _P]),
     "eps_grad_vjp_geps": (_S, [_P, _P, _P, _I, _P, _P, _I, _P]),

@@ -57,6 +57,10 @@ class Scene:
     def set_launch(self, block_x=0, col_segments=0):
         check(lib().sg_scene_set_launch(self.handle, int(block_x), int(col_segments)))
 
+    def set_deterministic(self, enable=True):
+        """Two-pass (atomic-free) gradient reduction: bitwise-repeatable."""
+        check(lib().sg_scene_set_deterministic(self.handle, int(bool(enable))))
+
     def set_timing(self, enable=True, every=1):
         """Trace the column kernel of later calls (HIP events on the call's
         stream): every `every`-th launch of each kind; enabling clears

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -85,6 +86,7 @@ static void free_scene(sg_scene* s) {
     }
     hipFree(s->d_grad);
     hipFree(s->d_nread);
+    hipFree(s->d_det);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
     if (s->h_p) hipHostFree(s->h_p);
@@ -649,6 +651,10 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         free_scene(s);
         return fail(e == hipErrorOutOfMemory ? SG_E_NOMEM : SG_E_DEVICE, "sg_scene_create: %s", hipGetErrorString(e));
     }
+    {
+        const char* det = std::getenv("SG_DETERMINISTIC");
+        s->deterministic = det != nullptr && std::atoi(det) != 0;
+    }
     *out = s;
     return SG_OK;
 }
@@ -938,6 +944,24 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_nread), 0.0, kReadSlots, st));
         kp.nread = s->d_nread;
     }
+    int64_t det_rows = 0;
+    if (s->deterministic && s->n_params > 0) {
+        det_rows = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg * (kBlock / 64);
+        const int64_t need = det_rows * s->n_params;
+        if (need > (int64_t(1) << 29)) return fail(SG_E_TOO_LARGE, "deterministic mode: %lld partial sums exceed 4 GiB",
+                                                   (long long)need);
+        if (need > s->det_cap) {
+            HIP_OK(hipStreamSynchronize(st));
+            hipFree(s->d_det);
+            s->d_det = nullptr;
+            s->det_cap = 0;
+            HIP_OK(hipMalloc((void**)&s->d_det, need * sizeof(double)));
+            s->det_cap = need;
+        }
+        HIP_OK(launch_fill(s->d_det, 0.0, need, st));
+        kp.det = s->d_det;
+        kp.det_n = s->n_params;
+    }
     if (fields) {
         for (int c = 0; c < kMaxComp; ++c) {
             const int cc = std::min(c, s->ncomp - 1);
@@ -949,7 +973,15 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         kp.geps = geps;
     }
     if ((rc = run_column(s, mode, kp, st)) != SG_OK) return rc;
+    if (det_rows > 0) HIP_OK(launch_det_reduce(s->d_det, det_rows, s->n_params, g, st));
     return finish_grad(s, grad, grad_on_device, st);
+}
+
+extern "C" sg_status sg_scene_set_deterministic(sg_scene* s, int enable) {
+    if (!s) return fail(SG_E_INVALID, "NULL scene");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->deterministic = enable != 0;
+    return SG_OK;
 }
 
 extern "C" sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, const void* const* e_fwd,

@@ -41,22 +41,36 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The calling wavefront's row of the deterministic partials (P.det != nullptr).
+__device__ __forceinline__ double* det_row(const KParams& P) {
+    return P.det + ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * P.det_n;
+}
+
+// Adds v to grad[idx]: an FP64 atomic, or in deterministic mode a plain
+// read-modify-write of the wavefront's own row (one thread at a time).
+__device__ __forceinline__ void grad_add(const KParams& P, int idx, double v) {
+    if (P.det) det_row(P)[idx] += v;
+    else atomicAdd(P.grad + idx, v);
+}
+
 // Adds the wavefront sum of v (one value per lane) times the field's scale b
 // to grad[idx] (idx < 0: a constant field).  Called with wave-uniform control flow.
 __device__ __forceinline__ void emit_ref(const KParams& P, int idx, double b, float v) {
     if (idx < 0) return;
     if (__ballot(v != 0.0f) == 0) return;
     const float s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) atomicAdd(P.grad + idx, b * (double)s);
+    if ((threadIdx.x & 63) == 0) grad_add(P, idx, b * (double)s);
 }
 __device__ __forceinline__ void emit(const KParams& P, int field, float v) {
     const sg_field r = P.fref[field];
     emit_ref(P, r.idx, r.b, v);
 }
 
+// One thread's v for a field (deterministic mode: one thread of the wavefront
+// at a time, see gcart_partials).
 __device__ __forceinline__ void add_field(const KParams& P, int field, float v) {
     const sg_field r = P.fref[field];
-    if (r.idx >= 0 && v != 0.0f) atomicAdd(P.grad + r.idx, r.b * (double)v);
+    if (r.idx >= 0 && v != 0.0f) grad_add(P, (int)r.idx, r.b * (double)v);
 }
 
 // Appends (in primitive order) every primitive in [start, start + kScan)
@@ -538,9 +552,23 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
     if (bucket) {
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
-        for (int i = lane; i < 2 * nvx; i += 64) {
-            const float v = sg[i];
-            if (v != 0.0f) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
+        if (P.det) {
+            // lanes in turn: two vertex fields may share a parameter
+            for (int base = 0; base < 2 * nvx; base += 64) {
+                const int i = base + lane;
+                const float v = i < 2 * nvx ? sg[i] : 0.0f;
+                uint64_t pend = __ballot(v != 0.0f);
+                while (pend) {
+                    const int src = __ffsll((unsigned long long)pend) - 1;
+                    if (lane == src) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
+                    pend &= pend - 1;
+                }
+            }
+        } else {
+            for (int i = lane; i < 2 * nvx; i += 64) {
+                const float v = sg[i];
+                if (v != 0.0f) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
+            }
         }
     }
 }
@@ -564,6 +592,10 @@ __device__ __forceinline__ void polar_emit(const KParams& P, int field, int slot
     const float sum = wave_sum(v);
     if ((threadIdx.x & 63) == 0) {
         const int idx = (int)r.idx;
+        if (P.det) {      // deterministic mode: the wavefront's own row, no LDS sharing
+            grad_add(P, idx, r.b * (double)sum);
+            return;
+        }
         int k = s_pkey[slot];
         if (k == -2) {
             const int old = atomicCAS(&s_pkey[slot], -2, idx);

@@ -324,6 +324,22 @@ hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hip
     }
 }
 
+// Sums the rows of the deterministic partials in row order: grad[k] = sum_r det[r * n + k].
+__global__ __launch_bounds__(256) void k_det_reduce(const double* __restrict__ det, int64_t rows, int64_t n,
+                                                    double* __restrict__ grad) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s = 0.0;
+    for (int64_t r = 0; r < rows; ++r) s += det[r * n + k];
+    grad[k] = s;
+}
+
+hipError_t launch_det_reduce(const double* det, int64_t rows, int64_t n, double* grad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, det, rows, n, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int ncomp, int64_t plane,
                          float two_omega, float* g, hipStream_t st) {
     const float2* e[3] = {ef[0], ncomp > 1 ? ef[1] : ef[0], ncomp > 2 ? ef[2] : ef[0]};

@@ -76,3 +76,4 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.sg_scene_create(None, None, None) == -1
     assert b"NULL" in L.sg_last_error()
     assert L.eps_build(None, None, None, 0, None, None) == -1
+    assert L.sg_scene_set_deterministic(None, 1) == -1
