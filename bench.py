@@ -162,6 +162,30 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
                        "rel_l2_vs_dense": sparse_rel}}
 
 
+def time_deterministic(api, scene, p_dev, E, A, omega, reps):
+    """Whole-call time of eps_grad_vjp with atomic and with deterministic
+    (per-wavefront rows + ordered second pass) reduction, and the two
+    gradients' distance."""
+    import torch
+    res, grads = {}, {}
+    for name, det in (("atomic", False), ("deterministic", True)):
+        scene.set_deterministic(det)
+        g = torch.empty(scene.n_params, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
+        torch.cuda.synchronize()
+        res[name + "_call_us"] = 1e6 * (time.perf_counter() - t) / reps
+        grads[name] = g
+    scene.set_deterministic(False)
+    res["rel_l2"] = float(torch.linalg.norm(grads["deterministic"] - grads["atomic"]) /
+                          torch.linalg.norm(grads["atomic"]))
+    return res
+
+
 def kernels_3d(api, W, gen, reps):
     """Column-kernel bandwidth of eps_build and eps_grad_vjp on the 3D taper
     (600x240x100), the 3D polarization-splitting grating with elliptical holes
@@ -387,6 +411,7 @@ def main():
     fds_s = (time.perf_counter() - t) / reps
     vjp_only = time_kernels(api, scene, p_dev, E0, A0, cfg["omega"], 50)
     out["sparse_vjp"] = vjp_only["sparse"]
+    out["deterministic_vjp"] = time_deterministic(api, scene, p_dev, E0, A0, cfg["omega"], 50)
     out["fd"] = {"evals_per_s": 1.0 / fd_s, "seconds_per_eval": fd_s, "scheme": "central", "h_um": cfg["h"],
                  "rel_l2_vs_vjp": rel,
                  "vjp_kernel_speedup": fd_s / (vjp_only["vjp_us"] * 1e-6),

@@ -169,14 +169,17 @@ sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* desc, sg_scene** out
 void sg_scene_destroy(sg_scene* scene);
 sg_status sg_scene_info(const sg_scene* scene, int64_t* n_params, int32_t* ncomp, int64_t dims[3]);
 /* Deterministic reduction for eps_grad_vjp, eps_grad_vjp_sparse and
- * eps_grad_vjp_geps (default: off, or on when the environment variable
- * SG_DETERMINISTIC is a nonzero integer at scene creation).  Each wavefront
- * then adds its parameter sums into its own row of a scene-owned FP64 buffer
- * (rows = blocks x 4, n columns; at most 2^29 doubles, else SG_E_TOO_LARGE),
- * and a second kernel sums the rows in a fixed order, so repeated calls with
- * the same inputs and launch shape give bitwise-equal gradients.  The
- * atomic mode agrees with it to the order of FP64 additions.  The serving loop
- * always uses atomics. */
+ * eps_grad_vjp_geps: the sum over samples of eq. (1) (default: off, or on
+ * when the environment variable SG_DETERMINISTIC is a nonzero integer at
+ * scene creation).  Each wavefront's FP64 contribution is rounded down to a
+ * multiple of 2^-64 and added exactly, as 32-bit limbs in 64-bit integer
+ * accumulators (3 n + 1 words the scene owns), which a last kernel turns back
+ * into FP64; integer sums do not depend on the order of the additions, so
+ * repeated calls with the same inputs and launch shape give bitwise-equal
+ * gradients.  It agrees with the atomic mode to about 2^-64 per contribution
+ * plus the FP64 rounding of the atomic sums.  A contribution of magnitude
+ * >= 2^31 (or NaN) makes every entry of the gradient NaN.  The FD entry
+ * points and the serving loop always use atomics. */
 sg_status sg_scene_set_deterministic(sg_scene* scene, int enable);
 
 /* Launch shape override: block width in x (16, 32, 64, 128 or 256 samples; the

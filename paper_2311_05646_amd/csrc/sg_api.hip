@@ -86,7 +86,7 @@ static void free_scene(sg_scene* s) {
     }
     hipFree(s->d_grad);
     hipFree(s->d_nread);
-    hipFree(s->d_det);
+    hipFree(s->d_fx);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
     if (s->h_p) hipHostFree(s->h_p);
@@ -944,23 +944,13 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_nread), 0.0, kReadSlots, st));
         kp.nread = s->d_nread;
     }
-    int64_t det_rows = 0;
-    if (s->deterministic && s->n_params > 0) {
-        det_rows = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg * (kBlock / 64);
-        const int64_t need = det_rows * s->n_params;
-        if (need > (int64_t(1) << 29)) return fail(SG_E_TOO_LARGE, "deterministic mode: %lld partial sums exceed 4 GiB",
-                                                   (long long)need);
-        if (need > s->det_cap) {
-            HIP_OK(hipStreamSynchronize(st));
-            hipFree(s->d_det);
-            s->d_det = nullptr;
-            s->det_cap = 0;
-            HIP_OK(hipMalloc((void**)&s->d_det, need * sizeof(double)));
-            s->det_cap = need;
-        }
-        HIP_OK(launch_fill(s->d_det, 0.0, need, st));
-        kp.det = s->d_det;
-        kp.det_n = s->n_params;
+    const bool det = s->deterministic && s->n_params > 0;
+    if (det) {
+        const int64_t words = 3 * s->n_params + 1;
+        if (!s->d_fx) HIP_OK(hipMalloc((void**)&s->d_fx, words * sizeof(unsigned long long)));
+        HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_fx), 0.0, words, st));   // all-zero bits
+        kp.fx = s->d_fx;
+        kp.fx_n = s->n_params;
     }
     if (fields) {
         for (int c = 0; c < kMaxComp; ++c) {
@@ -973,7 +963,7 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         kp.geps = geps;
     }
     if ((rc = run_column(s, mode, kp, st)) != SG_OK) return rc;
-    if (det_rows > 0) HIP_OK(launch_det_reduce(s->d_det, det_rows, s->n_params, g, st));
+    if (det) HIP_OK(launch_fx_finish(s->d_fx, s->n_params, g, st));
     return finish_grad(s, grad, grad_on_device, st);
 }
 

@@ -41,15 +41,29 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// The calling wavefront's row of the deterministic partials (P.det != nullptr).
-__device__ __forceinline__ double* det_row(const KParams& P) {
-    return P.det + ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * P.det_n;
+// Adds v to the fixed-point accumulators acc[0 .. 2] of one parameter.  v is
+// rounded down to a multiple of 2^-64 and split into its integer part
+// (|.| <= 2^31) and the two 32-bit halves of its 64 fraction bits; each piece
+// goes into its own 64-bit integer accumulator, which fewer than 2^31 such
+// additions cannot overflow.  Integer addition is associative, so the three
+// sums, and the value k_fx_finish rebuilds from them, do not depend on the
+// order in which the additions arrive.  |v| >= 2^31 or NaN sets *flag.
+__device__ __forceinline__ void fx_add(unsigned long long* acc, unsigned long long* flag, double v) {
+    if (!(fabs(v) < 0x1p31)) {
+        *flag = 1ull;
+        return;
+    }
+    const double fl = floor(v);
+    const unsigned long long f = (unsigned long long)((v - fl) * 0x1p64);   // v - fl is exact, in [0, 1)
+    atomicAdd(acc, f & 0xffffffffull);
+    atomicAdd(acc + 1, f >> 32);
+    atomicAdd(acc + 2, (unsigned long long)(long long)fl);                  // two's complement
 }
 
-// Adds v to grad[idx]: an FP64 atomic, or in deterministic mode a plain
-// read-modify-write of the wavefront's own row (one thread at a time).
+// Adds v to grad[idx]: an FP64 atomic, or in deterministic mode the
+// order-independent fixed-point sum.
 __device__ __forceinline__ void grad_add(const KParams& P, int idx, double v) {
-    if (P.det) det_row(P)[idx] += v;
+    if (P.fx) fx_add(P.fx + 3 * (int64_t)idx, P.fx + 3 * P.fx_n, v);
     else atomicAdd(P.grad + idx, v);
 }
 
@@ -482,7 +496,8 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
     const GSeg* gs = P.gseg + pr.gs0 + (int64_t)comp * P.nu;
     const int jlo = gs[u0].j, jhi = gs[min(u0 + TU, P.nu) - 1].j;   // segments of the tile's first / last sample
     const int nvx = jhi - jlo + 2;               // vertices jlo .. jhi + 1
-    const bool bucket = nvx <= kSegBucket;
+    // (the LDS buckets add lanes' FP32 values in hardware order: not in deterministic mode)
+    const bool bucket = nvx <= kSegBucket && !P.fx;
     if (bucket) {
         for (int i = lane; i < 2 * nvx; i += 64) sg[i] = 0.0f;
         __builtin_amdgcn_s_waitcnt(0xc07f);      // lgkmcnt(0): the zeros are in LDS
@@ -552,23 +567,9 @@ __device__ __forceinline__ void gcart_partials(const KParams& P, const DevPrim& 
     if (bucket) {
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
-        if (P.det) {
-            // lanes in turn: two vertex fields may share a parameter
-            for (int base = 0; base < 2 * nvx; base += 64) {
-                const int i = base + lane;
-                const float v = i < 2 * nvx ? sg[i] : 0.0f;
-                uint64_t pend = __ballot(v != 0.0f);
-                while (pend) {
-                    const int src = __ffsll((unsigned long long)pend) - 1;
-                    if (lane == src) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
-                    pend &= pend - 1;
-                }
-            }
-        } else {
-            for (int i = lane; i < 2 * nvx; i += 64) {
-                const float v = sg[i];
-                if (v != 0.0f) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
-            }
+        for (int i = lane; i < 2 * nvx; i += 64) {
+            const float v = sg[i];
+            if (v != 0.0f) add_field(P, i < nvx ? pr.f0 + 2 + jlo + i : pr.f0 + 2 + M + jlo + (i - nvx), v);
         }
     }
 }
@@ -592,7 +593,7 @@ __device__ __forceinline__ void polar_emit(const KParams& P, int field, int slot
     const float sum = wave_sum(v);
     if ((threadIdx.x & 63) == 0) {
         const int idx = (int)r.idx;
-        if (P.det) {      // deterministic mode: the wavefront's own row, no LDS sharing
+        if (P.fx) {       // deterministic mode: no LDS combining (FP64 LDS atomics add in any order)
             grad_add(P, idx, r.b * (double)sum);
             return;
         }

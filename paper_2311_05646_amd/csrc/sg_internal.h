@@ -177,11 +177,11 @@ struct KParams {
     const int32_t* kprim_off;
     const int32_t* kprim;
     double fd_scale;
-    // deterministic reduction: each wavefront adds its parameter sums into its
-    // own row det[(block * 4 + wavefront) * det_n + k] (no atomics); a second
-    // kernel sums the rows in order.  nullptr: atomics into grad.
-    double* det;
-    int64_t det_n;
+    // deterministic reduction: each parameter sum goes into fx[3k .. 3k + 2]
+    // as an exact fixed-point number (see fx_add); fx[3 n] flags a value out
+    // of its range.  nullptr: FP64 atomics into grad.
+    unsigned long long* fx;
+    int64_t fx_n;
 };
 
 // kernel launchers (sg_kernels.hip)
@@ -198,6 +198,6 @@ hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int n
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t st);
-hipError_t launch_det_reduce(const double* det, int64_t rows, int64_t n, double* grad, hipStream_t st);
+hipError_t launch_fx_finish(const unsigned long long* fx, int64_t n, double* grad, hipStream_t st);
 
 }  // namespace sg

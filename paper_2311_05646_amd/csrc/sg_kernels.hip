@@ -324,19 +324,28 @@ hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hip
     }
 }
 
-// Sums the rows of the deterministic partials in row order: grad[k] = sum_r det[r * n + k].
-__global__ __launch_bounds__(256) void k_det_reduce(const double* __restrict__ det, int64_t rows, int64_t n,
-                                                    double* __restrict__ grad) {
+// grad[k] from the fixed-point accumulators fx[3k .. 3k + 2] (fraction bits
+// 0..31, fraction bits 32..63, integer part): the value is
+// (a2 2^64 + a1 2^32 + a0) 2^-64, carried into a signed 64-bit integer part
+// and a 64-bit fraction before the one conversion to FP64.  A range flag set
+// by any addition makes every entry NaN.
+__global__ __launch_bounds__(256) void k_fx_finish(const unsigned long long* __restrict__ fx, int64_t n,
+                                                   double* __restrict__ grad) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    double s = 0.0;
-    for (int64_t r = 0; r < rows; ++r) s += det[r * n + k];
-    grad[k] = s;
+    if (fx[3 * n] != 0ull) {
+        grad[k] = __builtin_nan("");
+        return;
+    }
+    const unsigned long long a0 = fx[3 * k], a1 = fx[3 * k + 1], a2 = fx[3 * k + 2];
+    const unsigned long long lo = a0 + (a1 << 32);
+    const long long hi = (long long)(a2 + (a1 >> 32) + (lo < a0 ? 1ull : 0ull));
+    grad[k] = (double)hi + (double)lo * 0x1p-64;
 }
 
-hipError_t launch_det_reduce(const double* det, int64_t rows, int64_t n, double* grad, hipStream_t st) {
+hipError_t launch_fx_finish(const unsigned long long* fx, int64_t n, double* grad, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, det, rows, n, grad);
+    hipLaunchKernelGGL(k_fx_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fx, n, grad);
     return hipGetLastError();
 }
 

@@ -68,9 +68,8 @@ struct sg_scene {
     bool static_w = false;
     float* d_work[2] = {nullptr, nullptr};
     unsigned long long* d_nread = nullptr;   // sparse VJP: (sample, step) pairs read
-    bool deterministic = false;              // two-pass reduction of the VJP (no atomics)
-    double* d_det = nullptr;                 // its per-wavefront partial rows
-    int64_t det_cap = 0;                     // doubles allocated there
+    bool deterministic = false;              // fixed-point (order-independent) VJP sums
+    unsigned long long* d_fx = nullptr;      // their accumulators: 3 n + 1 words
     // sparse FD: the primitives (device order) whose fields reference each
     // parameter, CSR; and the parameters an extrusion bound references
     std::vector<int32_t> kprim_off, kprim;

@@ -1,8 +1,10 @@
-"""Deterministic reduction mode: every wavefront writes its parameter sums
-into a row of its own and a second kernel adds the rows in a fixed order, so
-the gradient of eq. (1)'s sum is bitwise repeatable.  It holds the oracle
-within the gradient tolerance, and the atomic mode to the order of FP64
-additions (both add the same FP32 wavefront sums)."""
+"""Deterministic reduction mode: the wavefront sums of eq. (1) are added as
+exact fixed-point numbers (integer limbs), so the gradient does not depend on
+the order in which the additions land and is bitwise repeatable.  It holds
+the oracle within the gradient tolerance, and the atomic mode within the
+bound a change of tiling is held to: the gcart vertex sums go through
+wavefront reductions instead of the LDS buckets (whose FP32 additions land in
+hardware order), which groups their FP32 sums differently."""
 import numpy as np
 import pytest
 
@@ -17,7 +19,7 @@ pytestmark = pytest.mark.gpu
 CASES = ["c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo2_difference", "crowd3",
          "psgc3_small", "psgc3_small_local", "taper3_sine_small", "levels3"]
 GRAD_TOL = 1e-4
-ORDER_TOL = 1e-10
+ORDER_TOL = 1e-6
 
 
 def _scene(cfg, det):
@@ -64,8 +66,8 @@ def test_sparse_and_geps_deterministic(name):
 
 
 def test_deterministic_toggle_and_growth():
-    """Switching the mode on a live scene, and a launch with more blocks
-    after one with fewer (the partials buffer grows), keep the results."""
+    """Switching the mode on a live scene, and between tilings, keeps the
+    results."""
     cfg = config("c4_small")
     print("[det-toggle] c4_small", flush=True)
     E, A = fields_c64(cfg)
@@ -82,5 +84,23 @@ def test_deterministic_toggle_and_growth():
     a2 = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
     assert np.array_equal(d2, d3)
     assert rel(d1, atom) <= 1e-6             # another tiling regroups the FP32 sums
+    assert rel(d1, d2) <= 1e-6
     assert rel(d2, atom) <= ORDER_TOL
-    assert rel(a2, atom) <= ORDER_TOL
+    assert np.array_equal(a2, atom) or rel(a2, atom) <= 1e-12   # atomics: FP64 order only
+
+
+def test_out_of_range_contribution_gives_nan():
+    """A wavefront contribution beyond the fixed-point range (|.| >= 2^31)
+    turns the whole gradient into NaN instead of wrapping silently; the atomic
+    mode adds it as FP64."""
+    cfg = config("c2_small")
+    print("[det-range] c2_small", flush=True)
+    ge = to_dev(W.make_geps(cfg["scene"], 5) * 1e15)
+    det = _scene(cfg, True)
+    g = api().eps_grad_vjp_geps(det, cfg["p"], ge)
+    atom = api().eps_grad_vjp_geps(_scene(cfg, False), cfg["p"], ge)
+    assert np.all(np.isnan(g))
+    assert np.all(np.isfinite(atom)) and np.max(np.abs(atom)) >= 2.0 ** 31
+    det.set_deterministic(True)
+    ok = api().eps_grad_vjp_geps(det, cfg["p"], to_dev(W.make_geps(cfg["scene"], 5)))
+    assert np.all(np.isfinite(ok))            # the range flag is cleared per call
