@@ -178,8 +178,9 @@ sg_status sg_scene_info(const sg_scene* scene, int64_t* n_params, int32_t* ncomp
  * repeated calls with the same inputs and launch shape give bitwise-equal
  * gradients.  It agrees with the atomic mode to about 2^-64 per contribution
  * plus the FP64 rounding of the atomic sums.  A contribution of magnitude
- * >= 2^31 (or NaN) makes every entry of the gradient NaN.  The FD entry
- * points and the serving loop always use atomics. */
+ * >= 2^31 (or NaN) makes every entry of the gradient NaN.  A serving session
+ * takes the scene's setting when it opens (serve_open_session); the FD entry
+ * points always use atomics. */
 sg_status sg_scene_set_deterministic(sg_scene* scene, int enable);
 
 /* Launch shape override: block width in x (16, 32, 64, 128 or 256 samples; the
@@ -289,7 +290,9 @@ typedef struct sg_req_stats {
 sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* opts, sg_server** out);
 /* Cancels queued requests, waits for launched ones, frees everything. */
 sg_status sg_server_destroy(sg_server* server);
-/* A session runs its requests on `scene` (which must outlive the server). */
+/* A session runs its requests on `scene` (which must outlive the server),
+ * with the scene's deterministic setting at this call: its gradients are then
+ * bitwise the same whether a request runs alone or batched with others. */
 sg_status serve_open_session(sg_server* server, sg_scene* scene, uint32_t* session);
 /* Fake-executor sessions (scheduling tests): n_params and bytes per request given directly. */
 sg_status serve_open_fake_session(sg_server* server, int64_t n_params, int64_t request_bytes, uint32_t* session);

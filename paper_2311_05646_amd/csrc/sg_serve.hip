@@ -51,6 +51,7 @@ struct Buf {                 // device buffers of one admitted request
     uint32_t* code = nullptr;
     uint32_t* gcode = nullptr;
     double* grad = nullptr;
+    unsigned long long* fx = nullptr;   // deterministic sessions: fixed-point accumulators
     double* h_p = nullptr;   // pinned
     double* h_grad = nullptr;
 };
@@ -60,6 +61,7 @@ struct Session {
     sg_scene* scene = nullptr;      // null for fake sessions
     int64_t n_params = 0;
     int64_t req_bytes = 0;
+    bool det = false;               // the scene's deterministic setting when the session opened
     std::vector<Buf*> free_bufs;
     std::vector<Buf*> all_bufs;
 };
@@ -125,12 +127,13 @@ void free_buf(Buf* b) {
     hipFree(b->code);
     hipFree(b->gcode);
     hipFree(b->grad);
+    hipFree(b->fx);
     if (b->h_p) hipHostFree(b->h_p);
     if (b->h_grad) hipHostFree(b->h_grad);
     delete b;
 }
 
-bool alloc_buf(sg_scene* sc, Buf* b) {
+bool alloc_buf(sg_scene* sc, bool det, Buf* b) {
     const int64_t nfield = std::max<int64_t>(1, sc->nfield), n = std::max<int64_t>(1, sc->n_params);
     const int64_t cm = (int64_t)sc->ncomp * sc->plane;
     hipError_t e = hipMalloc((void**)&b->e, cm * sizeof(float2));
@@ -144,6 +147,7 @@ bool alloc_buf(sg_scene* sc, Buf* b) {
     if (e == hipSuccess)
         e = hipMalloc((void**)&b->gcode, (size_t)sc->ncomp * ((sc->nw + kGroup - 1) / kGroup) * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&b->grad, n * sizeof(double));
+    if (e == hipSuccess && det) e = hipMalloc((void**)&b->fx, (3 * n + 1) * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_p, n * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_grad, n * sizeof(double));
     return e == hipSuccess;
@@ -173,7 +177,7 @@ void admit(sg_server* v) {
         if (!v->opts.fake_executor) {
             if (r->s->free_bufs.empty()) {
                 Buf* b = new Buf;
-                if (!alloc_buf(r->s->scene, b)) {
+                if (!alloc_buf(r->s->scene, r->s->det, b)) {
                     free_buf(b);
                     return;        // device memory short: try again when something completes
                 }
@@ -261,6 +265,9 @@ bool launch_batch(sg_server* v, Lane& L) {
         sp.zero_ptr = b->grad;
         sp.zero_n = sc->n_params;
         if (launch_stage(sp, 1, st) != hipSuccess) return false;
+        if (r->s->det && sc->n_params > 0 &&
+            launch_fill(reinterpret_cast<double*>(b->fx), 0.0, 3 * sc->n_params + 1, st) != hipSuccess)
+            return false;
     }
     // one batched launch per kernel specialization; a group of g requests uses
     // h_plist[g0, g0 + g) and the prefix h_first[g0, g0 + g] (terminated by its total)
@@ -286,6 +293,10 @@ bool launch_batch(sg_server* v, Lane& L) {
                 kp.gcode = b->gcode;
             }
             kp.grad = b->grad;
+            if (L.batch[j]->s->det && sc->n_params > 0) {
+                kp.fx = b->fx;
+                kp.fx_n = sc->n_params;
+            }
             for (int c = 0; c < kMaxComp; ++c) {
                 const int cc = std::min(c, sc->ncomp - 1);
                 kp.ef[c] = b->e + (int64_t)cc * sc->plane;
@@ -305,6 +316,9 @@ bool launch_batch(sg_server* v, Lane& L) {
         slot = g0 + ng + 1;
     }
     for (Req* r : L.batch) {
+        if (r->s->det && r->s->n_params > 0 &&
+            launch_fx_finish(r->buf->fx, r->s->n_params, r->buf->grad, st) != hipSuccess)
+            return false;
         if (r->s->n_params &&
             hipMemcpyAsync(r->buf->h_grad, r->buf->grad, r->s->n_params * sizeof(double), hipMemcpyDeviceToHost, st))
             return false;
@@ -451,13 +465,14 @@ extern "C" sg_status sg_server_destroy(sg_server* v) {
     return SG_OK;
 }
 
-static sg_status open_session(sg_server* v, sg_scene* sc, int64_t n_params, int64_t bytes, uint32_t* id) {
+static sg_status open_session(sg_server* v, sg_scene* sc, int64_t n_params, int64_t bytes, bool det, uint32_t* id) {
     std::lock_guard<std::mutex> lk(v->mu);
     auto s = std::make_unique<Session>();
     s->id = (uint32_t)v->sessions.size();
     s->scene = sc;
     s->n_params = n_params;
     s->req_bytes = bytes;
+    s->det = det;
     *id = s->id;
     v->sessions.push_back(std::move(s));
     return SG_OK;
@@ -467,15 +482,21 @@ extern "C" sg_status serve_open_session(sg_server* v, sg_scene* sc, uint32_t* id
     if (!v || !sc || !id) return fail(SG_E_INVALID, "serve_open_session: NULL argument");
     if (v->opts.fake_executor) return fail(SG_E_INVALID, "fake-executor servers take fake sessions");
     if (sc->ctx->device != v->ctx->device) return fail(SG_E_INVALID, "scene on another device");
-    const int64_t bytes = 16 * (int64_t)sc->ncomp * sc->plane + staging_bytes(sc);
-    return open_session(v, sc, sc->n_params, bytes, id);
+    bool det;
+    {
+        std::lock_guard<std::mutex> lk(sc->mu);
+        det = sc->deterministic;
+    }
+    const int64_t bytes = 16 * (int64_t)sc->ncomp * sc->plane + staging_bytes(sc) +
+                          (det ? 8 * (3 * std::max<int64_t>(1, sc->n_params) + 1) : 0);
+    return open_session(v, sc, sc->n_params, bytes, det, id);
 }
 
 extern "C" sg_status serve_open_fake_session(sg_server* v, int64_t n_params, int64_t bytes, uint32_t* id) {
     if (!v || !id) return fail(SG_E_INVALID, "serve_open_fake_session: NULL argument");
     if (!v->opts.fake_executor) return fail(SG_E_INVALID, "only fake-executor servers take fake sessions");
     if (n_params < 0 || bytes < 0) return fail(SG_E_INVALID, "bad sizes");
-    return open_session(v, nullptr, n_params, bytes, id);
+    return open_session(v, nullptr, n_params, bytes, false, id);
 }
 
 extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, uint64_t seed, double omega,

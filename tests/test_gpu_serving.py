@@ -1,7 +1,7 @@
 """Serving loop on the GPU: every request's gradient is the same served in a
 mixed, continuously batched stream as computed alone (within the reordering
-of FP64 atomic additions), and matches the oracle on fields drawn by the
-oracle's own Philox generator."""
+of FP64 atomic additions; bitwise for sessions in deterministic mode), and
+matches the oracle on fields drawn by the oracle's own Philox generator."""
 import numpy as np
 import pytest
 import torch
@@ -33,10 +33,13 @@ def _requests(rng, cfgs, per=5):
     return [reqs[i] for i in order]
 
 
-def test_alone_equals_mix():
+@pytest.mark.parametrize("det", [False, True], ids=["atomic", "deterministic"])
+def test_alone_equals_mix(det):
     rng = np.random.default_rng(11)
     cfgs = {n: config(n) for n in NAMES}
     scenes = {n: api().Scene(c["scene"]) for n, c in cfgs.items()}
+    for sc in scenes.values():
+        sc.set_deterministic(det)
     srv = api().Server(hbm_budget_bytes=1 << 30, max_slots=16, max_batch=8, n_streams=2)
     sids = {n: srv.open_session(sc) for n, sc in scenes.items()}
     reqs = _requests(rng, cfgs)
@@ -57,7 +60,10 @@ def test_alone_equals_mix():
         # alone through the single-request entry point, same fields
         E, A = api().fieldgen(scenes[n], seed)
         g2 = api().eps_grad_vjp(scenes[n], p, E, A, om)
-        assert rel(g, g1) <= 1e-10 and rel(g, g2) <= 1e-10, n
+        if det:
+            assert np.array_equal(g, g1) and np.array_equal(g, g2), n
+        else:
+            assert rel(g, g1) <= 1e-10 and rel(g, g2) <= 1e-10, n
     srv.close()
 
 
