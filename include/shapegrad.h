@@ -272,7 +272,9 @@ sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* 
  * ------------------------------------------------------------------------- */
 typedef struct sg_server sg_server;
 typedef struct sg_server_opts {
-    int64_t hbm_budget_bytes;   /* device bytes admitted requests may hold at once (> 0) */
+    int64_t hbm_budget_bytes;   /* device bytes admitted requests may hold at once (> 0); 0: the
+                                   environment variable SG_HBM_BUDGET (bytes, optional K / M / G
+                                   suffix for 2^10 / 2^20 / 2^30), else 8 GiB */
     int32_t max_slots;          /* requests admitted at once (>= 1) */
     int32_t max_batch;          /* requests per batch (>= 1) */
     int32_t n_streams;          /* batches in flight at once, one per stream (1..8) */

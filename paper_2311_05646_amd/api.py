@@ -214,7 +214,7 @@ class Server:
     library).  submit() queues a request and returns a ticket; poll() waits for
     its gradient."""
 
-    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_batch=16, n_streams=2, device=0,
+    def __init__(self, hbm_budget_bytes=0, max_slots=64, max_batch=16, n_streams=2, device=0,
                  fake_executor=False, fake_us=0):
         o = _lib.sg_server_opts(int(hbm_budget_bytes), int(max_slots), int(max_batch), int(n_streams),
                                 int(bool(fake_executor)), int(fake_us))

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -396,12 +397,28 @@ extern "C" sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* o, sg_s
     if (!o || !out) return fail(SG_E_INVALID, "sg_server_create: NULL argument");
     *out = nullptr;
     if (!o->fake_executor && !ctx) return fail(SG_E_INVALID, "sg_server_create: NULL ctx");
-    if (o->hbm_budget_bytes <= 0 || o->max_slots < 1 || o->max_batch < 1 || o->n_streams < 1 || o->n_streams > 8 ||
+    int64_t budget = o->hbm_budget_bytes;
+    if (budget == 0) {       // SG_HBM_BUDGET: bytes, optionally K / M / G (powers of 2^10)
+        budget = int64_t(8) << 30;
+        if (const char* b = std::getenv("SG_HBM_BUDGET")) {
+            char* end = nullptr;
+            const long long v = std::strtoll(b, &end, 10);
+            int shift = 0;
+            if (end && (*end == 'K' || *end == 'k')) shift = 10, ++end;
+            else if (end && (*end == 'M' || *end == 'm')) shift = 20, ++end;
+            else if (end && (*end == 'G' || *end == 'g')) shift = 30, ++end;
+            if (end == b || !end || *end != '\0' || v <= 0 || v > (std::numeric_limits<int64_t>::max() >> shift))
+                return fail(SG_E_INVALID, "sg_server_create: SG_HBM_BUDGET=\"%s\" is not a positive size", b);
+            budget = (int64_t)v << shift;
+        }
+    }
+    if (budget <= 0 || o->max_slots < 1 || o->max_batch < 1 || o->n_streams < 1 || o->n_streams > 8 ||
         o->fake_us < 0)
         return fail(SG_E_INVALID, "sg_server_create: bad options");
     auto* v = new sg_server;
     v->ctx = ctx;
     v->opts = *o;
+    v->opts.hbm_budget_bytes = budget;
     if (const char* fi = std::getenv("SG_FAULT_INJECT")) {
         if (std::strncmp(fi, "launch:", 7) == 0) v->fault_launch = std::atoll(fi + 7);
     }

@@ -3,7 +3,8 @@ with its fake executor (no device work; a request's result is
 grad_k = 2 p_k + (seed mod 1000) after a fixed delay).  Covers routing of
 results to tickets, HBM-budget admission in arrival order, slot limits,
 batching of requests that arrive while others run, cancellation, polling
-time-outs, invalid requests and an injected launch failure."""
+time-outs, invalid requests, an injected launch failure and the budget taken
+from SG_HBM_BUDGET."""
 import os
 import subprocess
 import sys
@@ -157,3 +158,32 @@ srv.close()
     r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == "['ok', -4, 'ok', 'ok']"
+
+
+@pytest.mark.parametrize("value,expect", [("4K", "-3"), ("8k", "ok"), ("1G", "ok"), ("abc", "create -1"),
+                                          ("0", "create -1"), ("12X", "create -1")])
+def test_budget_from_environment(value, expect):
+    """hbm_budget_bytes = 0 takes SG_HBM_BUDGET (bytes with an optional binary
+    K / M / G suffix); a malformed value fails server creation."""
+    code = r'''
+import sys
+sys.path.insert(0, sys.argv[1])
+from paper_2311_05646_amd.api import Server
+from paper_2311_05646_amd._lib import SGError
+try:
+    srv = Server(hbm_budget_bytes=0, max_slots=2, max_batch=2, n_streams=1, fake_executor=True, fake_us=0)
+except SGError as e:
+    print("create", e.code)
+    sys.exit(0)
+sid = srv.open_fake_session(1, 5000)
+try:
+    print(srv.poll(srv.submit(sid, [1.0], 3, 1.0), 1)[0])
+except SGError as e:
+    print(e.code)
+srv.close()
+'''
+    _server(hbm_budget_bytes=1 << 20).close()          # builds the library if needed
+    env = dict(os.environ, SG_HBM_BUDGET=value)
+    r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == expect
