@@ -9,7 +9,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libshapegrad.so")
+# SG_LIB_PATH selects another build of the same library (the host-only
+# sanitizer builds of build.build_host_sanitized)
+LIB_PATH = os.environ.get("SG_LIB_PATH") or os.path.join(HERE, "libshapegrad.so")
 
 SG_OK, SG_EAGAIN = 0, 1
 STATUS = {0: "SG_OK", 1: "SG_EAGAIN", -1: "SG_E_INVALID", -2: "SG_E_NOMEM", -3: "SG_E_TOO_LARGE",
