@@ -104,3 +104,18 @@ def test_out_of_range_contribution_gives_nan():
     det.set_deterministic(True)
     ok = api().eps_grad_vjp_geps(det, cfg["p"], to_dev(W.make_geps(cfg["scene"], 5)))
     assert np.all(np.isfinite(ok))            # the range flag is cleared per call
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c4_small", "zoo3_union", "psgc3_small"])
+def test_atomic_run_to_run_spread(name):
+    """Atomic mode: repeated calls differ only by the order of the FP64
+    atomic additions (spread far below 1e-6 relative)."""
+    cfg = config(name)
+    print(f"[atomic-spread] {name}", flush=True)
+    E, A = fields_c64(cfg)
+    Ed, Ad = to_dev(E), to_dev(A)
+    sc = _scene(cfg, False)
+    runs = [api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"]) for _ in range(5)]
+    spread = max(rel(r, runs[0]) for r in runs[1:])
+    print(f"[atomic-spread] {name}: {spread:.2e}", flush=True)
+    assert spread <= 1e-12
