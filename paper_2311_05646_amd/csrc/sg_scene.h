@@ -95,7 +95,8 @@ struct sg_scene {
 namespace sg {
 // launch parameters of a scene's kernels, pointing at its own staging buffers
 StageParams stage_params(sg_scene* s, const double* dp);
-KParams column_params(sg_scene* s);
+// target_blocks: the block count the automatic column split aims for
+KParams column_params(sg_scene* s, int64_t target_blocks = 768);
 // bytes of device staging one gradient evaluation of the scene needs
 int64_t staging_bytes(const sg_scene* s);
 }  // namespace sg
