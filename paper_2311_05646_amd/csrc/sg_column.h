@@ -50,7 +50,7 @@ __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_read
 // order in which the additions arrive.  |v| >= 2^31 or NaN sets *flag.
 __device__ __forceinline__ void fx_add(unsigned long long* acc, unsigned long long* flag, double v) {
     if (!(fabs(v) < 0x1p31)) {
-        *flag = 1ull;
+        atomicOr(flag, 1ull);
         return;
     }
     const double fl = floor(v);
