@@ -433,6 +433,53 @@ def make_prop2_plane(kind, k_r, seed=BASE_SEED + 7, nside=3, pitch=0.6, dx=0.03,
     return out
 
 
+# shapes of the one-shot sampling study (Sec. "Experimental choice of
+# nonlinear function for Prop. 1", Fig. quadrature_oneshot): centered in a 3.2 um square plane,
+# edges off the grid lines
+MSE_SHAPES = {
+    "rect": {"x": (0.517, 2.613), "y": (0.763, 2.349)},
+    "square45": {"c": (1.613, 1.587), "h": 1.05},
+    "circle": {"c": (1.613, 1.587), "r": 1.03},
+    "polar": {"c": (1.613, 1.587), "R0": 0.95, "cs": (0.12, 0.06, 0.03), "ss": (0.05, -0.08, 0.02)},
+}
+
+
+def square45_vertices(c, h):
+    """The square rotated by 45 degrees about c with half-diagonal h (CCW)."""
+    return [(c[0] + h, c[1]), (c[0], c[1] + h), (c[0] - h, c[1]), (c[0], c[1] - h)]
+
+
+def make_mse_shape(shape, kind, k_r, dx=0.08, n=40):
+    """One shape of the one-shot sampling study on an n x n uniform plane
+    (Ez samples), sigma kind `kind` with k = k_r / dx: LOCAL (per-axis sample
+    width) for the rectangle's axis-aligned arguments, FIXED for the others.
+    The shape's geometry is the parameter vector; background SiO2, shape Si."""
+    g = MSE_SHAPES[shape]
+    X = uniform_nodes(n, dx)
+    Y = uniform_nodes(n, dx)
+    fixed = (kind, "fixed", k_r / dx)
+    if shape == "rect":
+        p = [g["x"][0], g["x"][1], g["y"][0], g["y"][1]]
+        loc = (kind, "local", k_r)
+        prim = box(x=(P(0), P(1)), y=(P(2), P(3)), sig=(loc, loc, LIN))
+    elif shape == "square45":
+        v = square45_vertices(g["c"], g["h"])
+        p = [x for x, _ in v] + [y for _, y in v]
+        prim = poly([P(i) for i in range(4)], [P(4 + i) for i in range(4)], sig=fixed)
+    elif shape == "circle":
+        p = [g["c"][0], g["c"][1], g["r"]]
+        prim = ellipse(P(0), P(1), P(2), sig=fixed)
+    else:
+        N = len(g["cs"])
+        p = [g["R0"]] + list(g["cs"]) + list(g["ss"])
+        prim = polar(K(g["c"][0]), K(g["c"][1]), P(0), [P(1 + i) for i in range(N)],
+                     [P(1 + N + i) for i in range(N)], sig=fixed)
+    scene = {"name": f"mse_{shape}", "dim": 2, "nodes": [X, Y, np.array([0.0, 1.0])], "components": ("z",),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": [prim],
+             "tree": {"op": "union", "children": [0]}}
+    return {"scene": scene, "p": np.array(p, dtype=np.float64), "dx": dx, "shape": shape}
+
+
 def make_c4(seed=BASE_SEED + 3, with_fields=True, **kw):
     """3D polarization-splitting grating: 400x400x80 at 25 nm; slab minus a
     40x40 lattice of elliptical holes, (x, y, r) per hole (4800 params)."""
