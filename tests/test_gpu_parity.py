@@ -186,6 +186,35 @@ def test_autograd_epsbuild(name):
     assert rel(p.grad.cpu().numpy()[ks], fd[ks]) <= GRAD_TOL
 
 
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+def test_autograd_against_fd_of_the_gpu_op(name):
+    """gradcheck-style: the autograd gradient of sum(w eps) against central
+    differences of the GPU op itself (FP32 eps, FP64 sums).  The edges sit
+    0.2-0.3 of a cell from the linear sigma's kinks and h is 0.05 of the
+    smallest cell, so eps is linear in each parameter over [p - h, p + h] and
+    the differences are exact up to the FP32 rounding of the samples that
+    change (the others repeat bitwise)."""
+    cfg = config(name)
+    print(f"[autograd-fd] {name}", flush=True)
+    sc = scene_for(name, cfg)
+    p = torch.tensor(cfg["p"], dtype=torch.float64, device="cuda", requires_grad=True)
+    wgt = to_dev(W.make_geps(cfg["scene"], 13)).double()
+    (api().EpsBuild.apply(p, sc).double() * wgt).sum().backward()
+    X = cfg["scene"]["nodes"][0]
+    h = 0.05 * float(np.min(np.diff(X)))
+    n = cfg["scene"]["n_params"]
+    ks = list(range(0, n, max(1, n // 8)))
+    fd = np.zeros(len(ks))
+    for i, k in enumerate(ks):
+        pp, pm = cfg["p"].copy(), cfg["p"].copy()
+        pp[k] += h
+        pm[k] -= h
+        lp = float((api().eps_build(sc, pp).double() * wgt).sum())
+        lm = float((api().eps_build(sc, pm).double() * wgt).sum())
+        fd[i] = (lp - lm) / (2 * h)
+    assert rel(p.grad.cpu().numpy()[ks], fd) <= 1e-3
+
+
 def test_invalid_inputs_raise():
     from paper_2311_05646_amd._lib import SGError
     cfg = config("c1")
