@@ -7,7 +7,7 @@ the curved shapes as 1000-vertex polygons, as the paper's ground truth), and
 against midpoint quadrature with S x S sub-samples of a hard step.  Checked:
 the linear sigma at k = 1 / dx reproduces the rectangle exactly; the quadratic
 sigma beats the linear one on the 45-degree square (zero error along its
-edges, error only at the corners); the best of the piecewise kinds (sin,
+edges, error only at the corners, as Fig. boundary_error shows); the best of the piecewise kinds (sin,
 linear, quadratic) beats sigmoid and erf on every shape; and each shape's best one-shot map is at
 least as good as quadrature with 9 sub-samples per cell (the paper: as good as
 9-16)."""
@@ -88,5 +88,16 @@ def test_one_shot_mse(shape):
     assert overall <= quad[3]
     if shape == "square45":
         assert best["quadratic"][0] < 0.1 * best["linear"][0]
+        # Fig. boundary_error: with the quadratic sigma at k = 1 / dx the
+        # error sits only where two edges share a sample box (the corners)
+        err = np.abs(_fill_gpu(W.make_mse_shape(shape, "quadratic", 1.0)) - exact)
+        g = W.MSE_SHAPES[shape]
+        X, Y = np.meshgrid(xc, yc)
+        near = np.zeros_like(err, dtype=bool)
+        for vx, vy in W.square45_vertices(g["c"], g["h"]):
+            near |= (np.abs(X - vx) < 1.5 * base["dx"]) & (np.abs(Y - vy) < 1.5 * base["dx"])
+        print(f"[mse] square45 quadratic: max error {err.max():.1e} at the corners, {err[~near].max():.1e} elsewhere",
+              flush=True)
+        assert err[~near].max() < 1e-6 and err[near].max() > 1e-3
     piecewise = min(best[k][0] for k in ("sin", "linear", "quadratic"))
     assert piecewise < min(best["sigmoid"][0], best["erf"][0])
