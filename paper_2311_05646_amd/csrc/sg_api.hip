@@ -87,6 +87,7 @@ static void free_scene(sg_scene* s) {
     hipFree(s->d_grad);
     hipFree(s->d_nread);
     hipFree(s->d_fx);
+    hipFree(s->d_gspread);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
     if (s->h_p) hipHostFree(s->h_p);
@@ -635,6 +636,13 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         e = hipMemcpy(s->d_consts, d->consts, d->nconst * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess && !gseg.empty())
         e = hipMemcpy(s->d_gseg, gseg.data(), gseg.size() * sizeof(GSeg), hipMemcpyHostToDevice);
+    // shared parameters: one referenced by at least 8 primitives, or a term
+    // of a sine-series boundary (which every block on the boundary reaches)
+    for (int64_t k = 0; k < d->n_params && !s->spread; ++k)
+        if (s->kprim_off[k + 1] - s->kprim_off[k] >= 8) s->spread = true;
+    for (int i = 0; i < d->nprim && !s->spread; ++i)
+        if (d->prims[i].type == SG_PRIM_SERIES) s->spread = true;
+    if (s->spread) alloc((void**)&s->d_gspread, (size_t)kGradSpread * std::max<int64_t>(1, d->n_params) * sizeof(double));
     // static extrusion tables: one stage launch with no primitive, on the null
     // stream, finished before the scene is returned
     s->static_w = true;
@@ -948,6 +956,12 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         kp.nread = s->d_nread;
     }
     const bool det = s->deterministic && s->n_params > 0;
+    const bool spread = !det && s->spread && s->n_params > 0;
+    if (spread) {
+        HIP_OK(launch_fill(s->d_gspread, 0.0, (int64_t)kGradSpread * s->n_params, st));
+        kp.grad = s->d_gspread;
+        kp.gstride = s->n_params;
+    }
     if (det) {
         const int64_t words = 3 * s->n_params + 1;
         if (!s->d_fx) HIP_OK(hipMalloc((void**)&s->d_fx, words * sizeof(unsigned long long)));
@@ -967,6 +981,7 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     }
     if ((rc = run_column(s, mode, kp, st)) != SG_OK) return rc;
     if (det) HIP_OK(launch_fx_finish(s->d_fx, s->n_params, g, st));
+    if (spread) HIP_OK(launch_spread_finish(s->d_gspread, s->n_params, g, st));
     return finish_grad(s, grad, grad_on_device, st);
 }
 

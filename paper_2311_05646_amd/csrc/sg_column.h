@@ -60,11 +60,16 @@ __device__ __forceinline__ void fx_add(unsigned long long* acc, unsigned long lo
     atomicAdd(acc + 2, (unsigned long long)(long long)fl);                  // two's complement
 }
 
-// Adds v to grad[idx]: an FP64 atomic, or in deterministic mode the
-// order-independent fixed-point sum.
+// The block's copy of the gradient (one of kGradSpread when P.gstride != 0).
+__device__ __forceinline__ double* grad_copy(const KParams& P) {
+    return P.grad + (int64_t)(blockIdx.x & (kGradSpread - 1)) * P.gstride;
+}
+
+// Adds v to grad[idx]: an FP64 atomic into the block's copy, or in
+// deterministic mode the order-independent fixed-point sum.
 __device__ __forceinline__ void grad_add(const KParams& P, int idx, double v) {
     if (P.fx) fx_add(P.fx + 3 * (int64_t)idx, P.fx + 3 * P.fx_n, v);
-    else atomicAdd(P.grad + idx, v);
+    else atomicAdd(grad_copy(P) + idx, v);
 }
 
 // Adds the wavefront sum of v (one value per lane) times the field's scale b
@@ -78,6 +83,40 @@ __device__ __forceinline__ void emit_ref(const KParams& P, int idx, double b, fl
 __device__ __forceinline__ void emit(const KParams& P, int field, float v) {
     const sg_field r = P.fref[field];
     emit_ref(P, r.idx, r.b, v);
+}
+
+// Field references [base, base + 64) of a primitive (those below `end`), one
+// per lane, loaded together: a run of emits then waits for one memory round
+// trip instead of one per emit (each emit branches on its field's index).
+struct FieldWin {
+    int base, idx;
+    double b;
+};
+__device__ __forceinline__ void load_win(const KParams& P, FieldWin& w, int base, int end) {
+    const int l = threadIdx.x & 63;
+    w.base = base;
+    w.idx = -1;
+    w.b = 0.0;
+    if (base + l < end) {
+        const sg_field r = P.fref[base + l];
+        w.idx = (int)r.idx;
+        w.b = r.b;
+    }
+}
+// The index and scale of field `field` (wave-uniform, base <= field < base + 64).
+__device__ __forceinline__ void win_ref(const FieldWin& w, int field, int& idx, double& b) {
+    const int l = uniform_int(field - w.base);
+    idx = __builtin_amdgcn_readlane(w.idx, l);
+    const long long bits = __double_as_longlong(w.b);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits & 0xffffffffll), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)bits >> 32), l);
+    b = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ void emit_win(const KParams& P, const FieldWin& w, int field, float v) {
+    int idx;
+    double b;
+    win_ref(w, field, idx, b);
+    emit_ref(P, idx, b, v);
 }
 
 // One thread's v for a field (deterministic mode: one thread of the wavefront
@@ -440,7 +479,8 @@ struct SampleLat {
 // Partials of a convex polygon at one sample, times a; one reduction per
 // vertex field and edge.
 template <int SIGS>
-__device__ __forceinline__ void poly_partials(const KParams& P, const DevPrim& pr, double ad, double uc, double vc) {
+__device__ __forceinline__ void poly_partials(const KParams& P, const DevPrim& pr, const FieldWin& fwx,
+                                              const FieldWin& fwy, double ad, double uc, double vc) {
     const double* fv = P.fval;
     const int N = pr.nvert;
     const double* xs = fv + pr.f0;
@@ -468,10 +508,10 @@ __device__ __forceinline__ void poly_partials(const KParams& P, const DevPrim& p
         else other = 0.0;
         const double g = ad * pr.k0 * ds * other;   // a * dF / d d_i
         const double iL = 1.0 / L, dL2 = d * iL * iL;
-        emit(P, pr.f0 + i, (float)(g * ((ey - wy) * iL + dL2 * ex)));
-        emit(P, pr.f0 + N + i, (float)(g * ((wx - ex) * iL + dL2 * ey)));
-        emit(P, pr.f0 + j, (float)(g * (wy * iL - dL2 * ex)));
-        emit(P, pr.f0 + N + j, (float)(g * (-wx * iL - dL2 * ey)));
+        emit_win(P, fwx, pr.f0 + i, (float)(g * ((ey - wy) * iL + dL2 * ex)));
+        emit_win(P, fwy, pr.f0 + N + i, (float)(g * ((wx - ex) * iL + dL2 * ey)));
+        emit_win(P, fwx, pr.f0 + j, (float)(g * (wy * iL - dL2 * ex)));
+        emit_win(P, fwy, pr.f0 + N + j, (float)(g * (-wx * iL - dL2 * ey)));
     }
 }
 
@@ -585,16 +625,17 @@ constexpr int kPolarSlots = 64;     // >= 2 x the largest Fourier order
 // Adds the wavefront sum of v for coefficient field `field` (slot = its
 // position among the coefficients): into the block's LDS slot when the slot
 // holds, or can be claimed for, the field's parameter; else to grad directly.
-__device__ __forceinline__ void polar_emit(const KParams& P, int field, int slot, float v, double* s_pacc,
-                                           int* s_pkey) {
-    const sg_field r = P.fref[field];
-    if (r.idx < 0) return;
+__device__ __forceinline__ void polar_emit(const KParams& P, const FieldWin& w, int field, int slot, float v,
+                                           double* s_pacc, int* s_pkey) {
+    int idx;
+    double b;
+    win_ref(w, field, idx, b);
+    if (idx < 0) return;
     if (__ballot(v != 0.0f) == 0) return;
     const float sum = wave_sum(v);
     if ((threadIdx.x & 63) == 0) {
-        const int idx = (int)r.idx;
         if (P.fx) {       // deterministic mode: no LDS combining (FP64 LDS atomics add in any order)
-            grad_add(P, idx, r.b * (double)sum);
+            grad_add(P, idx, b * (double)sum);
             return;
         }
         int k = s_pkey[slot];
@@ -602,8 +643,8 @@ __device__ __forceinline__ void polar_emit(const KParams& P, int field, int slot
             const int old = atomicCAS(&s_pkey[slot], -2, idx);
             k = (old == -2) ? idx : old;
         }
-        if (k == idx) atomicAdd(&s_pacc[slot], r.b * (double)sum);
-        else atomicAdd(P.grad + idx, r.b * (double)sum);
+        if (k == idx) atomicAdd(&s_pacc[slot], b * (double)sum);
+        else atomicAdd(grad_copy(P) + idx, b * (double)sum);
     }
 }
 
@@ -612,36 +653,74 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
                                                const SampleLat& L, double* s_pacc, int* s_pkey) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
-    const int N = pr.nvert;
+    const int N = uniform_int(pr.nvert);
+    FieldWin w;           // x0, y0, R0, c_1..c_N, s_1..s_N: 2 N + 3 <= 61 fields
+    load_win(P, w, pr.f0, pr.f0 + 3 + 2 * N);
+    const double* f = P.fval + pr.f0;
+    const float k0 = (float)pr.k0;
+    // the 2 N coefficients, one per lane (c_1..c_N, then s_1..s_N), read by
+    // lane moves in the per-sample recurrence instead of a load per term
+    const float coef = lane < 2 * N ? (float)f[3 + lane] : 0.0f;
+    const float R0 = (float)f[2];
     float g[Q], c1[Q], s1[Q];
     float sx = 0.0f, sy = 0.0f, sR = 0.0f;
+    // derivatives only: FP32 after the FP64 differences (as for the ellipse;
+    // k (R - r) keeps ~1e-6 absolute).  The Fourier recurrence runs over the
+    // terms outside and the wavefront's Q samples inside, so each coefficient
+    // is read once per candidate.
+    float av[Q], rv[Q], iv[Q], R[Q], dR[Q], cn[Q], sn[Q];
+    bool rowlive[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int t = q * 64 + lane;
-        const float a = sAc[t];
-        g[q] = 0.0f;
+        av[q] = sAc[t];
+        rowlive[q] = __ballot(av[q] != 0.0f) != 0;
         c1[q] = 1.0f;
         s1[q] = 0.0f;
-        if (a != 0.0f) {
-            double r, c, s, dR;
-            const double arg = polar_arg(pr, P.fval, L.uc(t), L.vc(t), &r, &c, &s, &dR);
-            double sv, ds;
-            sig_vd<SIGS>(pr.sk0, arg, sv, ds);
-            const double gg = (double)a * pr.k0 * ds;     // a * d F / d (R - r)
-            if (r > 0.0) {
-                sx += (float)(gg * (dR * s / r + c));
-                sy += (float)(gg * (-dR * c / r + s));
+        rv[q] = 0.0f;
+        iv[q] = 0.0f;
+        if (rowlive[q]) {
+            const float dx = (float)(L.uc(t) - f[0]), dy = (float)(L.vc(t) - f[1]);
+            rv[q] = sqrtf(dx * dx + dy * dy);
+            iv[q] = rv[q] > 0.0f ? 1.0f / rv[q] : 0.0f;
+            if (rv[q] > 0.0f) {
+                c1[q] = dx * iv[q];
+                s1[q] = dy * iv[q];
             }
-            sR += (float)gg;
-            g[q] = (float)gg;
-            c1[q] = (float)c;
-            s1[q] = (float)s;
+        }
+        R[q] = R0;
+        dR[q] = 0.0f;
+        cn[q] = 1.0f;
+        sn[q] = 0.0f;
+    }
+    for (int n = 1; n <= N; ++n) {
+        const float an = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, coef), n - 1));
+        const float bn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, coef), N + n - 1));
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float cr = cn[q] * c1[q] - sn[q] * s1[q];
+            sn[q] = sn[q] * c1[q] + cn[q] * s1[q];
+            cn[q] = cr;
+            R[q] -= an * cn[q] + bn * sn[q];
+            dR[q] += (float)n * (an * sn[q] - bn * cn[q]);
         }
     }
-    emit(P, pr.f0, sx);
-    emit(P, pr.f0 + 1, sy);
-    emit(P, pr.f0 + 2, sR);
-    float cn[Q], sn[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        g[q] = 0.0f;
+        if (av[q] != 0.0f) {
+            const float gg = av[q] * k0 * sig_d32(pr.sk0, k0 * (R[q] - rv[q]));     // a * d F / d (R - r)
+            if (rv[q] > 0.0f) {
+                sx += gg * (dR[q] * s1[q] * iv[q] + c1[q]);
+                sy += gg * (-dR[q] * c1[q] * iv[q] + s1[q]);
+            }
+            sR += gg;
+            g[q] = gg;
+        }
+    }
+    emit_win(P, w, pr.f0, sx);
+    emit_win(P, w, pr.f0 + 1, sy);
+    emit_win(P, w, pr.f0 + 2, sR);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         cn[q] = 1.0f;
@@ -657,8 +736,8 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
             pc -= g[q] * cn[q];
             ps -= g[q] * sn[q];
         }
-        polar_emit(P, pr.f0 + 2 + n, n - 1, pc, s_pacc, s_pkey);
-        polar_emit(P, pr.f0 + 2 + N + n, N + n - 1, ps, s_pacc, s_pkey);
+        polar_emit(P, w, pr.f0 + 2 + n, n - 1, pc, s_pacc, s_pkey);
+        polar_emit(P, w, pr.f0 + 2 + N + n, N + n - 1, ps, s_pacc, s_pkey);
     }
 }
 
@@ -674,6 +753,9 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
     const int lane = threadIdx.x & 63;
     const double* fv = P.fval;
     const double* c = P.consts + pr.c0;
+    const int fend = pr.f0 + 2 + pr.nvert;
+    FieldWin fw;          // xs, xe and the first 62 terms; later terms 64 at a time
+    load_win(P, fw, pr.f0, fend);
     float w[Q], s1[Q], c1[Q];
     float sxs = 0.0f, sxe = 0.0f;
     bool any = false;
@@ -704,8 +786,8 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
             any = any || (w[q] != 0.0f);
         }
     }
-    emit(P, pr.f0, sxs);
-    emit(P, pr.f0 + 1, sxe);
+    emit_win(P, fw, pr.f0, sxs);
+    emit_win(P, fw, pr.f0 + 1, sxe);
     if (__ballot(any) == 0) return;
     float si[Q], ci[Q];
 #pragma unroll
@@ -722,7 +804,9 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
             ci[q] = ci[q] * c1[q] - si[q] * s1[q];
             si[q] = sn;
         }
-        emit(P, pr.f0 + 2 + i, acc);
+        const int f = pr.f0 + 2 + i;
+        if (f >= fw.base + 64) load_win(P, fw, f, fend);
+        emit_win(P, fw, f, acc);
     }
 }
 
@@ -800,12 +884,15 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
     }
     if constexpr ((TYPES & T_POLY) != 0) {
         if (type == SG_PRIM_POLY) {
+            FieldWin fwx, fwy;    // the x and y vertex fields (nvert <= 64)
+            load_win(P, fwx, pr.f0, pr.f0 + pr.nvert);
+            load_win(P, fwy, pr.f0 + pr.nvert, pr.f0 + 2 * pr.nvert);
 #pragma unroll 1
             for (int q = 0; q < Q; ++q) {
                 const int t = q * 64 + lane;
                 const float a = sAc[t];
                 if (__ballot(a != 0.0f) == 0) continue;
-                poly_partials<SIGS>(P, pr, (double)a, L.uc(t), L.vc(t));
+                poly_partials<SIGS>(P, pr, fwx, fwy, (double)a, L.uc(t), L.vc(t));
             }
             return;
         }
@@ -886,15 +973,9 @@ __device__ __forceinline__ TileGeom tile_geom(const KParams& P, int b) {
 
 // ------------------------------------------------------------------ column kernel
 // Tables every wavefront reads at the same address (step and group codes,
-// extrusion tables) are read through the constant address space, which lets
-// the compiler use scalar loads: they neither occupy vector registers nor wait
+// extrusion tables) are read through the constant address space (ConstU32,
+// ConstF64): scalar loads, which neither occupy vector registers nor wait
 // behind the field loads.
-typedef __attribute__((address_space(4))) const uint32_t* ConstU32;
-typedef __attribute__((address_space(4))) const double* ConstF64;
-template <class T>
-__device__ __forceinline__ T const_space(const void* p) {
-    return (T)(uintptr_t)p;
-}
 
 // Raw buffer resource over [base, base + bytes) (bytes clamped to 32 bits;
 // reads past the end return 0).
@@ -1423,7 +1504,8 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         if constexpr ((TYPES & T_POLAR) != 0) {
             // one atomic per combined coefficient parameter
             __syncthreads();
-            if (tid < kPolarSlots && s_pkey[tid] >= 0 && s_pacc[tid] != 0.0) atomicAdd(P.grad + s_pkey[tid], s_pacc[tid]);
+            if (tid < kPolarSlots && s_pkey[tid] >= 0 && s_pacc[tid] != 0.0)
+                atomicAdd(grad_copy(P) + s_pkey[tid], s_pacc[tid]);
         }
     }
 }

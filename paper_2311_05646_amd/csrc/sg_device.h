@@ -256,6 +256,23 @@ __device__ __forceinline__ void gcart_segment(const double* __restrict__ xv, int
     t = fmin(1.0, fmax(0.0, tt));
 }
 
+// Reads through the constant address space: for tables that are constant
+// during a kernel and read at a wave-uniform address, the compiler then uses
+// scalar loads (through the scalar cache, merged when consecutive).
+typedef __attribute__((address_space(4))) const uint32_t* ConstU32;
+typedef __attribute__((address_space(4))) const double* ConstF64;
+template <class T>
+__device__ __forceinline__ T const_space(const void* p) {
+    return (T)(uintptr_t)p;
+}
+// A pointer that is the same in every active lane, moved to scalar registers.
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    return (const void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Fourier radius of eq:PSGCboundary at the sample's polar angle about the
 // center, R(theta) = R0 - sum_n (c_n cos n theta + s_n sin n theta) (the pi
 // shift flips both signs), with cos n theta, sin n theta by repeated rotation
@@ -264,8 +281,10 @@ __device__ __forceinline__ void gcart_segment(const double* __restrict__ xv, int
 __device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __restrict__ fv, double uc, double vc,
                                             double* r_out = nullptr, double* c1_out = nullptr,
                                             double* s1_out = nullptr, double* dR = nullptr) {
-    const int N = pr.nvert;
-    const double* f = fv + pr.f0;
+    // called for one primitive at a time by the whole wavefront: its fields
+    // sit at a uniform address
+    const int N = __builtin_amdgcn_readfirstlane(pr.nvert);
+    const ConstF64 f = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0));
     const double dx = uc - f[0], dy = vc - f[1];
     const double r = sqrt(dx * dx + dy * dy);
     const double c1 = r > 0.0 ? dx / r : 1.0, s1 = r > 0.0 ? dy / r : 0.0;
@@ -291,14 +310,19 @@ __device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __r
 __device__ __forceinline__ double series_f(const DevPrim& pr, const double* __restrict__ fv,
                                            const double* __restrict__ cst, double uc, double* env_out = nullptr,
                                            double* s1_out = nullptr, double* c1_out = nullptr) {
-    const double x0 = cst[0], L = cst[1], w_in = cst[2], w_out = cst[3];
+    // called for one primitive at a time by the whole wavefront: its fields
+    // and constants sit at uniform addresses
+    const ConstF64 cc = const_space<ConstF64>(uniform_ptr(cst));
+    const double x0 = cc[0], L = cc[1], w_in = cc[2], w_out = cc[3];
     const double u = (uc - x0) / L;
     double s1, c1;
     sincospi(u, &s1, &c1);
     const double env = 0.1 + 0.9 * s1 * s1;
-    const double* v = fv + pr.f0 + 2;
+    const ConstF64 v = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0) + 2);
+    const int K = __builtin_amdgcn_readfirstlane(pr.nvert);
     double sum = 0.0, si = s1, ci = c1;
-    for (int i = 0; i < pr.nvert; ++i) {
+#pragma unroll 8
+    for (int i = 0; i < K; ++i) {
         sum += v[i] * si;
         const double sn = si * c1 + ci * s1;
         ci = ci * c1 - si * s1;
@@ -390,10 +414,13 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
 // nonzero.
 constexpr double kSupportSlack = 1e-9;
 template <int SIGS>
-__device__ __forceinline__ bool sig_live(int kind, double t) {
-    if constexpr (SIGS == S_LIN) return fabs(t) < 0.5 + kSupportSlack;
-    else return fabs(t) < sigma_cut(kind) + kSupportSlack;
+__device__ __forceinline__ bool sig_live(int kind, double t, double slack = kSupportSlack) {
+    if constexpr (SIGS == S_LIN) return fabs(t) < 0.5 + slack;
+    else return fabs(t) < sigma_cut(kind) + slack;
 }
+// The Fourier-radius partials evaluate their argument in FP32 (error up to
+// ~1e-5 in t for order-6 radii): their probe takes a wider slack.
+constexpr double kSupportSlack32 = 1e-3;
 
 // prim_value of a polygon or a piecewise-linear boundary, and in *live
 // whether some in-plane partial of the primitive can be nonzero at the sample:
@@ -457,7 +484,7 @@ __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const doubl
     if constexpr ((TYPES & T_POLAR) != 0) {
         if (pr.type == SG_PRIM_POLAR) {
             const double t = polar_arg(pr, fv, uc, vc);
-            live = sig_live<SIGS>(pr.sk0, t);
+            live = sig_live<SIGS>(pr.sk0, t, kSupportSlack32);
             return sig_v<SIGS>(pr.sk0, t);
         }
     }

@@ -12,6 +12,10 @@ constexpr int kMaxComp = 3;
 constexpr int kMaxGroups = 4;
 constexpr int kMaxClasses = 8;
 constexpr int kBlock = 256;        // threads (= in-plane samples) per block
+// copies of the gradient that blocks spread their FP64 atomics over when a
+// parameter is shared by many blocks (one address taking an atomic from every
+// block serializes them)
+constexpr int kGradSpread = 32;
 constexpr int kCandCap = 2048;     // candidate primitives listed in LDS per pass
 constexpr int kZStage = 512;       // extrusion-table entries staged in LDS per chunk
 constexpr int kReadSlots = 256;    // partial counters of the sparse VJP's read statistic
@@ -182,6 +186,9 @@ struct KParams {
     // of its range.  nullptr: FP64 atomics into grad.
     unsigned long long* fx;
     int64_t fx_n;
+    // spread accumulation: block b adds into grad + (b mod kGradSpread) * gstride
+    // (gstride = n: kGradSpread copies, summed by k_spread_finish; 0: one copy)
+    int64_t gstride;
 };
 
 // kernel launchers (sg_kernels.hip)
@@ -199,5 +206,6 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, d
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t st);
 hipError_t launch_fx_finish(const unsigned long long* fx, int64_t n, double* grad, hipStream_t st);
+hipError_t launch_spread_finish(const double* spread, int64_t n, double* grad, hipStream_t st);
 
 }  // namespace sg

@@ -343,6 +343,23 @@ __global__ __launch_bounds__(256) void k_fx_finish(const unsigned long long* __r
     grad[k] = (double)hi + (double)lo * 0x1p-64;
 }
 
+// grad[k] = sum of the kGradSpread copies, in copy order.
+__global__ __launch_bounds__(256) void k_spread_finish(const double* __restrict__ sp, int64_t n,
+                                                       double* __restrict__ grad) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < kGradSpread; ++c) s += sp[c * n + k];
+    grad[k] = s;
+}
+
+hipError_t launch_spread_finish(const double* spread, int64_t n, double* grad, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spread_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, spread, n, grad);
+    return hipGetLastError();
+}
+
 hipError_t launch_fx_finish(const unsigned long long* fx, int64_t n, double* grad, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fx_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fx, n, grad);

@@ -70,6 +70,10 @@ struct sg_scene {
     unsigned long long* d_nread = nullptr;   // sparse VJP: (sample, step) pairs read
     bool deterministic = false;              // fixed-point (order-independent) VJP sums
     unsigned long long* d_fx = nullptr;      // their accumulators: 3 n + 1 words
+    // parameters shared by many blocks (one referenced by many primitives, or
+    // a sine-series term): the VJP spreads its atomics over kGradSpread copies
+    bool spread = false;
+    double* d_gspread = nullptr;             // kGradSpread x n
     // sparse FD: the primitives (device order) whose fields reference each
     // parameter, CSR; and the parameters an extrusion bound references
     std::vector<int32_t> kprim_off, kprim;
