@@ -746,10 +746,9 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
 // like a Rect1D, and d F / d v_i = (d F / d f) envelope(x) sin(i phi), the
 // sines by repeated FP32 rotation (error linear in i), one reduction per term;
 // a wavefront whose samples all have d F / d f = 0 skips the terms.
-template <int SIGS>
+template <int SIGS, int Q>
 __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim& pr, const float* sAc,
-                                                const SampleLat& L) {
-    constexpr int Q = kBlock / 64;
+                                                const SampleLat& L, int qbase) {
     const int lane = threadIdx.x & 63;
     const double* fv = P.fval;
     const double* c = P.consts + pr.c0;
@@ -761,7 +760,7 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
     bool any = false;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int t = q * 64 + lane;
+        const int t = (qbase + q) * 64 + lane;
         const float a = sAc[t];
         w[q] = 0.0f;
         s1[q] = 0.0f;
@@ -909,11 +908,20 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
             return;
         }
     }
+    // sine-series boundaries: series_split, called by every wavefront
+}
+
+// The sine-series candidates of a staged set: every wavefront takes its own
+// 64 samples of each (one candidate's K term reductions would otherwise run on
+// one wavefront while the other three wait at the block's end).
+template <int TYPES, int SIGS>
+__device__ __forceinline__ void series_split(const KParams& P, const PrimRec* s_rec, int n, const float* sA,
+                                             const SampleLat& L) {
     if constexpr ((TYPES & T_SERIES) != 0) {
-        if (type == SG_PRIM_SERIES) {
-            series_partials<SIGS>(P, pr, sAc, L);
-            return;
-        }
+        const int wave = threadIdx.x >> 6;
+        for (int j = 0; j < n; ++j)
+            if (s_rec[j].pr.type == SG_PRIM_SERIES)
+                series_partials<SIGS, 1>(P, s_rec[j].pr, sA + s_rec[j].pr.cls * kBlock, L, wave);
     }
 }
 
@@ -1488,6 +1496,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
             for (int j = wave; j < ncand; j += kBlock / 64)
                 block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0, sgw,
                                             s_pacc, s_pkey);
+            series_split<TYPES, SIGS>(P, s_rec, ncand, sA, L);
         } else {
             for (int next = 0; next < P.nprim;) {
                 const int n = scan_candidates(P.bbox, P.nprim, next, G.T.ulo, G.T.uhi, G.T.vlo, G.T.vhi, s_cand,
@@ -1498,6 +1507,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                     for (int j = wave; j < nj; j += kBlock / 64)
                         block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0,
                                                     sgw, s_pacc, s_pkey);
+                    series_split<TYPES, SIGS>(P, s_rec, nj, sA, L);
                 }
             }
         }
