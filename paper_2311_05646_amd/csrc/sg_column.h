@@ -481,10 +481,9 @@ struct SampleLat {
 template <int SIGS>
 __device__ __forceinline__ void poly_partials(const KParams& P, const DevPrim& pr, const FieldWin& fwx,
                                               const FieldWin& fwy, double ad, double uc, double vc) {
-    const double* fv = P.fval;
-    const int N = pr.nvert;
-    const double* xs = fv + pr.f0;
-    const double* ys = xs + N;
+    const int N = uniform_int(pr.nvert);
+    const ConstF64 xs = const_space<ConstF64>(P.fval + uniform_int(pr.f0));
+    const ConstF64 ys = xs + N;
     double pnz = 1.0;
     int nzero = 0, zidx = -1;
     for (int i = 0; i < N; ++i) {

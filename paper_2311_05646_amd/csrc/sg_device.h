@@ -361,9 +361,10 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
     }
     if constexpr ((TYPES & T_POLY) != 0) {
         if (pr.type == SG_PRIM_POLY) {
-            const int N = pr.nvert;
-            const double* xs = fv + pr.f0;
-            const double* ys = xs + N;
+            // one primitive at a time for the whole wavefront: scalar loads
+            const int N = __builtin_amdgcn_readfirstlane(pr.nvert);
+            const ConstF64 xs = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0));
+            const ConstF64 ys = xs + N;
             double f = 1.0;
             for (int i = 0; i < N && f > 0.0; ++i) {
                 const int j = (i + 1 == N) ? 0 : i + 1;
@@ -435,9 +436,10 @@ __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const doubl
                                                   bool& live) {
     if constexpr ((TYPES & T_POLY) != 0) {
         if (pr.type == SG_PRIM_POLY) {
-            const int N = pr.nvert;
-            const double* xs = fv + pr.f0;
-            const double* ys = xs + N;
+            // one primitive at a time for the whole wavefront: scalar loads
+            const int N = __builtin_amdgcn_readfirstlane(pr.nvert);
+            const ConstF64 xs = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0));
+            const ConstF64 ys = xs + N;
             double f = 1.0;
             int nzero = 0;
             bool any = false, zlive = false;
