@@ -1519,8 +1519,16 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     }
 }
 
+// minimum wavefronts per SIMD the register allocation must leave room for:
+// the box + sine-series variant sits 2 VGPRs over the 3-wave budget otherwise
+template <int MODE, int TYPES>
+constexpr int column_min_waves() {
+    return (MODE == MODE_VJP_FIELDS && TYPES == (T_BOX | T_SERIES)) ? 3 : 1;
+}
+
 template <int MODE, int TREE, int TYPES, int SIGS>
-__global__ __launch_bounds__(256) void k_column(const KParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(column_min_waves<MODE, TYPES>())))
+void k_column(const KParams P) {
     column_body<MODE, TREE, TYPES, SIGS>(P, blockIdx.x);
 }
 
