@@ -94,7 +94,88 @@ def test_volume_average_derivatives():
             assert dsigma(kind, x / dx) / dx == pytest.approx(fd, rel=1e-6)
 
 
-def test_paper_printed_inverse_length_scale():
+def test_grating_coupler_workload_uses_the_printed_inverse_length_scale():
+    # the paper prints k = 4 sqrt(2) / dx = 188.6 / um at dx = 30 nm (Fig.
+    # psgc_full_jac_smh caption); the grating-coupler workloads keep k_r and
+    # scale it to their 25 nm spacing
+    from paper_2311_05646_amd import workloads as W
     g = _gold("paper_constants.txt")
-    assert g["psgc_k_r"] == pytest.approx(4 * np.sqrt(2), rel=1e-15)
     assert round(g["psgc_k_r"] / g["psgc_dx_um"], 1) == g["psgc_k_printed"]
+    for mk in (W.make_c4, W.make_psgc):
+        d = mk(with_fields=False, nside=2, nz=8)["scene"]
+        dx = float(d["nodes"][0][1] - d["nodes"][0][0])
+        for pr in d["prims"][1:]:
+            assert pr["sigma"][0][:2] == ("sigmoid", "fixed")
+            assert pr["sigma"][0][2] == pytest.approx(g["psgc_k_r"] / dx, rel=1e-15)
+
+
+# ---- values of each kind that its definition in Tab. nonlinearfunctions fixes,
+# chosen so that a wrong scale of the argument (e.g. sigmoid(2t), or the erf
+# kind read as the normal CDF (1 + erf(t / sqrt 2)) / 2) fails
+
+def test_sigmoid_closed_form_values():
+    # (1 + e^-t)^-1 at t = +-ln 3 is 3/4 and 1/4; at ln 9, 9/10
+    assert sigma("sigmoid", np.log(3.0)) == pytest.approx(0.75, abs=1e-15)
+    assert sigma("sigmoid", -np.log(3.0)) == pytest.approx(0.25, abs=1e-15)
+    assert sigma("sigmoid", np.log(9.0)) == pytest.approx(0.9, abs=1e-15)
+
+
+def _erf_maclaurin(t, terms=60):
+    # erf(t) = 2/sqrt(pi) sum_n (-1)^n t^(2n+1) / (n! (2n+1)), summed here
+    # independently of any library error function
+    s, term = 0.0, t
+    for n in range(terms):
+        s += term / (2 * n + 1)
+        term *= -t * t / (n + 1)
+    return 2.0 / np.sqrt(np.pi) * s
+
+
+def test_erf_kind_against_published_table_and_series():
+    g = _gold("erf_table.txt")
+    for t in (0.5, 1.0, 2.0):
+        ref = 0.5 * (1.0 + g[f"erf_{t}"])
+        assert sigma("erf", t) == pytest.approx(ref, abs=1e-10)
+        assert sigma("erf", t) == pytest.approx(0.5 * (1.0 + _erf_maclaurin(t)), abs=1e-14)
+        assert sigma("erf", -t) == pytest.approx(0.5 * (1.0 - g[f"erf_{t}"]), abs=1e-10)
+
+
+def test_piecewise_closed_form_values():
+    # sin: (1 + sin t) / 2 -> 3/4 at pi/6; linear: t + 1/2 -> 3/4 at 1/4;
+    # quadratic: (1/sqrt2 + t)^2 -> 1/8 at t = -1/(2 sqrt2), 7/8 at +1/(2 sqrt2)
+    assert sigma("sin", np.pi / 6) == pytest.approx(0.75, abs=1e-15)
+    assert sigma("sin", -np.pi / 6) == pytest.approx(0.25, abs=1e-15)
+    assert sigma("linear", 0.25) == pytest.approx(0.75, abs=1e-15)
+    assert sigma("linear", -0.4) == pytest.approx(0.1, abs=1e-15)
+    q = 1.0 / (2.0 * np.sqrt(2.0))
+    assert sigma("quadratic", -q) == pytest.approx(0.125, abs=1e-15)
+    assert sigma("quadratic", q) == pytest.approx(0.875, abs=1e-15)
+
+
+# the slope at the boundary, from difference quotients of sigma itself:
+# sigmoid 1/4, erf 1/sqrt(pi), sin 1/2, linear 1, quadratic sqrt 2
+SLOPE0 = {"sigmoid": 0.25, "erf": 1.0 / np.sqrt(np.pi), "sin": 0.5, "linear": 1.0, "quadratic": np.sqrt(2.0)}
+# sigma is a cumulative distribution whose density is sigma'; its variance
+# int t^2 sigma'(t) dt: logistic pi^2/3, normal with variance 1/2, the
+# half-cosine density pi^2/4 - 2, uniform on [-1/2, 1/2] 1/12, the triangle of
+# half-width 1/sqrt 2 1/12
+VARIANCE = {"sigmoid": np.pi ** 2 / 3.0, "erf": 0.5, "sin": np.pi ** 2 / 4.0 - 2.0, "linear": 1.0 / 12.0,
+            "quadratic": 1.0 / 12.0}
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_slope_at_the_boundary(kind):
+    h = 1e-6
+    # the piecewise kinds are kinked only away from 0 (quadratic: its two
+    # pieces meet at 0 with equal slope)
+    fd = (sigma(kind, h) - sigma(kind, -h)) / (2 * h)
+    assert fd == pytest.approx(SLOPE0[kind], rel=1e-5)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_second_moment_of_the_derivative(kind):
+    # int t^2 d sigma(t), by the midpoint rule over the increments of sigma
+    t = np.linspace(-60.0, 60.0, 1_200_001)
+    ds = np.diff(sigma(kind, t))
+    tm = 0.5 * (t[1:] + t[:-1])
+    assert float(np.sum(ds)) == pytest.approx(1.0, abs=1e-12)
+    assert float(np.sum(tm * tm * ds)) == pytest.approx(VARIANCE[kind], rel=1e-6)
