@@ -272,7 +272,8 @@ sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* 
  * ------------------------------------------------------------------------- */
 typedef struct sg_server sg_server;
 typedef struct sg_server_opts {
-    int64_t hbm_budget_bytes;   /* device bytes admitted requests may hold at once (> 0); 0: the
+    int64_t hbm_budget_bytes;   /* device bytes the server's request buffers may hold at once
+                                   (> 0), busy or kept idle for a session's next request; 0: the
                                    environment variable SG_HBM_BUDGET (bytes, optional K / M / G
                                    suffix for 2^10 / 2^20 / 2^30), else 8 GiB */
     int32_t max_slots;          /* requests admitted at once (>= 1) */
@@ -309,9 +310,12 @@ sg_status serve_submit(sg_server* server, uint32_t session, const double* p, uin
 sg_status serve_poll(sg_server* server, uint64_t ticket, double* grad_out, int64_t timeout_us, sg_req_stats* stats);
 /* Cancels a request: queued requests never run; launched ones finish but their result is dropped. */
 sg_status serve_cancel(sg_server* server, uint64_t ticket);
-/* Counters: requests completed, batches launched, largest batch, bytes admitted now. */
+/* Counters: requests completed, batches launched, largest batch, bytes of the
+ * requests admitted and not finished, and bytes of every request buffer the
+ * server holds (busy, or idle and kept for its session; at most the budget).
+ * Any pointer may be NULL. */
 sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches, int64_t* max_batch_seen,
-                         int64_t* bytes_in_use);
+                         int64_t* bytes_in_use, int64_t* bytes_held);
 
 /* Kernel tracing.  With timing enabled the scene records a pair of HIP events
  * on the call's stream around every launch of its column kernel (the kernel

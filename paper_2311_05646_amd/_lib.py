@@ -97,7 +97,7 @@ SIGNATURES = {
     "serve_poll": (_S, [_P, C.c_uint64, _P, C.c_int64, C.POINTER(sg_req_stats)]),
     "serve_cancel": (_S, [_P, C.c_uint64]),
     "serve_counters": (_S, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
-                            C.POINTER(C.c_int64)]),
+                            C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
 }
 
 _lib = None

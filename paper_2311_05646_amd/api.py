@@ -264,16 +264,9 @@ class Server:
         check(lib().serve_cancel(self.handle, int(ticket)))
 
     def counters(self):
-        v = [C.c_int64() for _ in range(4)]
+        v = [C.c_int64() for _ in range(5)]
         check(lib().serve_counters(self.handle, *[C.byref(x) for x in v]))
-        return dict(zip(("completed", "batches", "max_batch", "bytes_in_use"), [x.value for x in v]))
-
-    def sparse_reads(self):
-        """(sample, column step) pairs whose fields the last eps_grad_vjp_sparse
-        call read."""
-        n = C.c_int64()
-        check(lib().sg_scene_sparse_reads(self.handle, C.byref(n)))
-        return n.value
+        return dict(zip(("completed", "batches", "max_batch", "bytes_in_use", "bytes_held"), [x.value for x in v]))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <limits>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -55,6 +56,8 @@ struct Buf {                 // device buffers of one admitted request
     unsigned long long* fx = nullptr;   // deterministic sessions: fixed-point accumulators
     double* h_p = nullptr;   // pinned
     double* h_grad = nullptr;
+    int64_t bytes = 0;       // counted against the budget while the buffer exists
+    struct Session* owner = nullptr;
 };
 
 struct Session {
@@ -63,7 +66,7 @@ struct Session {
     int64_t n_params = 0;
     int64_t req_bytes = 0;
     bool det = false;               // the scene's deterministic setting when the session opened
-    std::vector<Buf*> free_bufs;
+    std::vector<Buf*> free_bufs;    // idle buffers kept for the session's next requests
     std::vector<Buf*> all_bufs;
 };
 
@@ -107,17 +110,25 @@ struct sg_server {
     std::deque<Req*> ready;
     std::unordered_map<uint64_t, Req*> reqs;
     uint64_t next_ticket = 1;
-    int64_t bytes_used = 0;
+    int64_t bytes_used = 0;         // bytes of the requests admitted and not yet finished
+    int64_t bytes_held = 0;         // bytes of every request buffer that exists (busy or idle)
+    std::list<Buf*> idle;           // idle buffers, least recently released first
     int slots_used = 0;
     std::vector<Lane> lanes;
     int next_lane = 0;
     int64_t launches = 0, completed = 0, max_batch_seen = 0;
     int64_t fault_launch = -1;      // SG_FAULT_INJECT=launch:N
+    int64_t fault_alloc = -1;       // SG_FAULT_INJECT=alloc:N: buffer allocations N, N+1, ... fail
+    int64_t allocs = 0;
 };
 
 namespace {
 
-void free_buf(Buf* b) {
+void free_buf(Buf* b, bool fake) {
+    if (fake) {
+        delete b;
+        return;
+    }
     hipFree(b->e);
     hipFree(b->a);
     hipFree(b->p);
@@ -163,31 +174,81 @@ void fake_result(Req* r) {
 void release(sg_server* v, Req* r) {
     if (r->buf) {
         r->s->free_bufs.push_back(r->buf);
+        v->idle.push_back(r->buf);
         r->buf = nullptr;
     }
     v->bytes_used -= r->s->req_bytes;
     v->slots_used -= 1;
 }
 
-// Admit queued requests in arrival order while slots and budget allow.
+// Frees an idle buffer (its session's next request allocates a new one).
+void drop_idle(sg_server* v, Buf* b) {
+    Session* s = b->owner;
+    s->free_bufs.erase(std::find(s->free_bufs.begin(), s->free_bufs.end(), b));
+    s->all_bufs.erase(std::find(s->all_bufs.begin(), s->all_bufs.end(), b));
+    v->idle.remove(b);
+    v->bytes_held -= b->bytes;
+    free_buf(b, v->opts.fake_executor != 0);
+}
+
+// A new request buffer for session s, or nullptr when the device is out of
+// memory (or an injected allocation failure).
+Buf* new_buf(sg_server* v, Session* s) {
+    const bool inject = v->fault_alloc >= 0 && v->allocs >= v->fault_alloc;
+    v->allocs++;
+    if (inject) return nullptr;
+    Buf* b = new Buf;
+    b->bytes = s->req_bytes;
+    b->owner = s;
+    if (!v->opts.fake_executor && !alloc_buf(s->scene, s->det, b)) {
+        free_buf(b, false);
+        return nullptr;
+    }
+    return b;
+}
+
+void retire(sg_server* v, Req* r, int state, sg_status status) {
+    r->state = state;
+    r->status = status;
+    r->st.done_ns = now_ns();
+    v->cv_done.notify_all();
+}
+
+// Admit queued requests in arrival order while slots and budget allow.  The
+// budget bounds every request buffer that exists: a session keeps its idle
+// buffers for its next requests, and the least recently released idle
+// buffers of any session are freed when a new buffer would not fit.
 void admit(sg_server* v) {
     while (!v->pending.empty()) {
         Req* r = v->pending.front();
+        Session* s = r->s;
         if (v->slots_used >= v->opts.max_slots) return;
-        if (v->bytes_used + r->s->req_bytes > v->opts.hbm_budget_bytes) return;
-        if (!v->opts.fake_executor) {
-            if (r->s->free_bufs.empty()) {
-                Buf* b = new Buf;
-                if (!alloc_buf(r->s->scene, r->s->det, b)) {
-                    free_buf(b);
-                    return;        // device memory short: try again when something completes
-                }
-                r->s->all_bufs.push_back(b);
-                r->s->free_bufs.push_back(b);
+        Buf* b = nullptr;
+        if (!s->free_bufs.empty()) {
+            b = s->free_bufs.back();
+            s->free_bufs.pop_back();
+            v->idle.remove(b);
+        } else {
+            while (v->bytes_held + s->req_bytes > v->opts.hbm_budget_bytes && !v->idle.empty())
+                drop_idle(v, v->idle.front());
+            if (v->bytes_held + s->req_bytes > v->opts.hbm_budget_bytes) return;   // busy buffers hold it
+            b = new_buf(v, s);
+            if (!b) {
+                // device memory short: free every idle buffer and try once more
+                while (!v->idle.empty()) drop_idle(v, v->idle.front());
+                b = new_buf(v, s);
             }
-            r->buf = r->s->free_bufs.back();
-            r->s->free_bufs.pop_back();
+            if (!b) {
+                if (v->slots_used > 0) return;     // in-flight requests will free memory
+                // nothing runs that could free memory: the request cannot be served now
+                v->pending.pop_front();
+                retire(v, r, FAILED, SG_E_NOMEM);
+                continue;
+            }
+            s->all_bufs.push_back(b);
+            v->bytes_held += b->bytes;
         }
+        r->buf = b;
         v->pending.pop_front();
         v->bytes_used += r->s->req_bytes;
         v->slots_used += 1;
@@ -421,6 +482,7 @@ extern "C" sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* o, sg_s
     v->opts.hbm_budget_bytes = budget;
     if (const char* fi = std::getenv("SG_FAULT_INJECT")) {
         if (std::strncmp(fi, "launch:", 7) == 0) v->fault_launch = std::atoll(fi + 7);
+        if (std::strncmp(fi, "alloc:", 6) == 0) v->fault_alloc = std::atoll(fi + 6);
     }
     v->lanes.resize(o->n_streams);
     if (!o->fake_executor) {
@@ -466,9 +528,9 @@ extern "C" sg_status sg_server_destroy(sg_server* v) {
     v->cv_done.notify_all();
     for (auto& kv : v->reqs) delete kv.second;
     v->reqs.clear();
+    for (auto& s : v->sessions)
+        for (Buf* b : s->all_bufs) free_buf(b, v->opts.fake_executor != 0);
     if (!v->opts.fake_executor) {
-        for (auto& s : v->sessions)
-            for (Buf* b : s->all_bufs) free_buf(b);
         for (Lane& L : v->lanes) {
             if (L.stream) hipStreamDestroy(L.stream);
             if (L.done) hipEventDestroy(L.done);
@@ -569,6 +631,9 @@ extern "C" sg_status serve_poll(sg_server* v, uint64_t ticket, double* grad_out,
     v->reqs.erase(it);
     delete r;
     if (st == SG_E_CANCELLED) return fail(SG_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+    if (st == SG_E_NOMEM)
+        return fail(st, "request %llu: no device memory for its buffers while nothing else ran",
+                    (unsigned long long)ticket);
     if (st != SG_OK) return fail(st, "request %llu failed on the device", (unsigned long long)ticket);
     return SG_OK;
 }
@@ -596,12 +661,13 @@ extern "C" sg_status serve_cancel(sg_server* v, uint64_t ticket) {
 }
 
 extern "C" sg_status serve_counters(sg_server* v, int64_t* completed, int64_t* batches, int64_t* max_batch_seen,
-                                    int64_t* bytes_in_use) {
+                                    int64_t* bytes_in_use, int64_t* bytes_held) {
     if (!v) return fail(SG_E_INVALID, "NULL server");
     std::lock_guard<std::mutex> lk(v->mu);
     if (completed) *completed = v->completed;
     if (batches) *batches = v->launches;
     if (max_batch_seen) *max_batch_seen = v->max_batch_seen;
     if (bytes_in_use) *bytes_in_use = v->bytes_used;
+    if (bytes_held) *bytes_held = v->bytes_held;
     return SG_OK;
 }

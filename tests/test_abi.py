@@ -77,3 +77,12 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"NULL" in L.sg_last_error()
     assert L.eps_build(None, None, None, 0, None, None) == -1
     assert L.sg_scene_set_deterministic(None, 1) == -1
+
+
+def test_server_binding_makes_no_scene_level_calls():
+    # a server handle is not a scene: the Server class must never pass its
+    # handle to a call that takes an sg_scene*
+    import inspect
+    from paper_2311_05646_amd import api
+    src = inspect.getsource(api.Server)
+    assert "sg_scene_" not in src and "eps_" not in src

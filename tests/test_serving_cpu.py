@@ -187,3 +187,55 @@ srv.close()
     r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == expect
+
+
+def test_idle_buffers_count_against_the_budget():
+    # a session keeps its buffers for its next requests, but the budget bounds
+    # every buffer that exists: another session's request frees the least
+    # recently released idle buffer instead of waiting for it forever
+    srv = _server(hbm_budget_bytes=1000, max_slots=8, max_batch=8, n_streams=1, fake_us=2000)
+    a = srv.open_fake_session(1, 400)
+    b = srv.open_fake_session(1, 400)
+    ta = [srv.submit(a, [float(i)], i, 1.0) for i in range(2)]
+    for t in ta:
+        assert srv.poll(t, 1)[0] == "ok"
+    c = srv.counters()
+    assert c["bytes_in_use"] == 0 and c["bytes_held"] == 800
+    st, g, _ = srv.poll(srv.submit(b, [5.0], 7, 1.0), 1, timeout_us=5_000_000)
+    assert st == "ok" and np.array_equal(g, _expect([5.0], 7))
+    c = srv.counters()
+    assert c["bytes_held"] == 800 and c["bytes_in_use"] == 0
+    # both sessions keep serving within the budget
+    ts = [srv.submit(s, [1.0], 3, 1.0) for s in (a, b, a, b)]
+    for t in ts:
+        assert srv.poll(t, 1, timeout_us=5_000_000)[0] == "ok"
+        assert srv.counters()["bytes_held"] <= 1000
+    srv.close()
+
+
+def test_allocation_failure_with_nothing_running_is_retired():
+    # every buffer allocation after the first fails: a request that needs a
+    # new buffer while nothing runs (so nothing can free memory) comes back
+    # SG_E_NOMEM instead of waiting forever
+    code = r'''
+import sys
+sys.path.insert(0, sys.argv[1])
+from paper_2311_05646_amd.api import Server
+from paper_2311_05646_amd._lib import SGError
+srv = Server(hbm_budget_bytes=1 << 20, max_slots=4, max_batch=4, n_streams=1, fake_executor=True, fake_us=1000)
+a = srv.open_fake_session(1, 100)
+b = srv.open_fake_session(1, 100)
+out = []
+for s in (a, b, a):
+    try:
+        out.append(srv.poll(srv.submit(s, [1.0], 1, 1.0), 1, timeout_us=10_000_000)[0])
+    except SGError as e:
+        out.append(e.code)
+print(out, srv.counters()["bytes_held"])
+srv.close()
+'''
+    _server(hbm_budget_bytes=1 << 20).close()
+    env = dict(os.environ, SG_FAULT_INJECT="alloc:1")
+    r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "['ok', -2, -2] 0"
