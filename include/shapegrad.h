@@ -201,6 +201,23 @@ sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_d
                        const void* const* e_fwd, const void* const* e_adj, double omega,
                        double* grad, int grad_on_device, void* stream);
 
+/* eps_grad_vjp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments and result (up to the order of the floating-point sums; bitwise
+ * the same in deterministic mode), but the call allocates nothing.  Its
+ * per-call staging (resolved fields, support boxes, primitive records, the
+ * extrusion tables when they depend on p, spread gradient copies or
+ * fixed-point accumulators) lives in a 4 MiB device array that the library
+ * holds on every device it runs on until the process ends, and that every
+ * such call on the device shares: calls that overlap on one device (on
+ * different streams or threads) race and give wrong results.  Scenes whose
+ * staging exceeds 4 MiB return SG_E_TOO_LARGE before any launch.  p and grad
+ * on the host use the scene's pinned staging (allocated by sg_scene_create).
+ * Not traced by sg_scene_set_timing. */
+sg_status eps_grad_vjp_noalloc(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
+                               const void* const* e_fwd, const void* const* e_adj, double omega,
+                               double* grad, int grad_on_device, void* stream);
+
 /* Step 5, sparse form (Sec. "Single-polarization blazed grating coupler in 2D",
  * item (iv): restrict the material Jacobian to where shapes are perturbed;
  * Sec. "Discussion and Conclusion": track its nonzero entries along shape

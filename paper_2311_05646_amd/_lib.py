@@ -80,6 +80,7 @@ SIGNATURES = {
     "sg_scene_set_deterministic": (_S, [_P, _I]),
     "eps_build": (_S, [_P, _P, _P, _I, _P, _P]),
     "eps_grad_vjp": (_S, [_P, _P, _P, _I, _P, _P, _D, _P, _I, _P]),
+    "eps_grad_vjp_noalloc": (_S, [_P, _P, _P, _I, _P, _P, _D, _P, _I, _P]),
     "eps_grad_vjp_geps": (_S, [_P, _P, _P, _I, _P, _P, _I, _P]),
     "eps_grad_vjp_sparse": (_S, [_P, _P, _P, _I, _P, _P, _D, _P, _I, _P]),
     "sg_scene_sparse_reads": (_S, [_P, C.POINTER(C.c_int64)]),

@@ -149,6 +149,18 @@ def eps_grad_vjp(scene, p, E, A, omega, grad=None, stream=None):
     return g
 
 
+def eps_grad_vjp_noalloc(scene, p, E, A, omega, grad=None, stream=None):
+    """eps_grad_vjp whose call allocates no device memory (its staging lives in
+    the library's per-device scratch array; overlapping calls on one device race)."""
+    dev = torch.device("cuda", scene.device)
+    pp, pdev, keep = _p_arg(scene, p)
+    fe, fa = _plane_ptrs(scene, E), _plane_ptrs(scene, A)
+    g, gp, gdev = _grad_out(scene, pdev, grad, dev)
+    check(lib().eps_grad_vjp_noalloc(scene.ctx, scene.handle, pp, pdev, fe, fa, float(omega), gp, gdev,
+                                     _stream(stream)))
+    return g
+
+
 def eps_grad_vjp_sparse(scene, p, E, A, omega, grad=None, stream=None):
     """eps_grad_vjp that reads the fields only where d eps / d p can be nonzero."""
     dev = torch.device("cuda", scene.device)

@@ -35,15 +35,36 @@ sg_status sg::fail(sg_status code, const char* fmt, ...) {
 
 extern "C" const char* sg_last_error(void) { return g_err.c_str(); }
 
+// ------------------------------------------------------------------ scratch
+// Per-call staging of eps_grad_vjp_noalloc (resolved fields, support boxes,
+// primitive records, extrusion tables and step codes when they depend on p,
+// spread gradient copies or fixed-point accumulators), for callers that
+// cannot allocate device memory.  Each device holds its own copy for the life
+// of the process; host code never uses this name as an address: sg_ctx_create
+// takes the device address with hipGetSymbolAddress (sg_ctx::scratch).
+constexpr int64_t kScratchBytes = int64_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 // ------------------------------------------------------------------ context
 extern "C" sg_status sg_ctx_create(int hip_device, sg_ctx** out) {
     if (!out) return fail(SG_E_INVALID, "sg_ctx_create: out is NULL");
     int n = 0;
     HIP_OK(hipGetDeviceCount(&n));
     if (hip_device < 0 || hip_device >= n) return fail(SG_E_INVALID, "sg_ctx_create: device %d of %d", hip_device, n);
+    // the device address of this device's scratch array, taken with the
+    // device current (every device holds its own copy)
+    int prev = 0;
+    HIP_OK(hipGetDevice(&prev));
+    HIP_OK(hipSetDevice(hip_device));
+    void* sp = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    HIP_OK(hipSetDevice(prev));
+    if (e != hipSuccess || !sp)
+        return fail(SG_E_DEVICE, "sg_ctx_create: scratch address on device %d: %s", hip_device, hipGetErrorString(e));
     auto* c = new (std::nothrow) sg_ctx;
     if (!c) return fail(SG_E_NOMEM, "sg_ctx_create: out of host memory");
     c->device = hip_device;
+    c->scratch = sp;
     *out = c;
     return SG_OK;
 }
@@ -916,9 +937,45 @@ extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_
     return run_column(s, MODE_EPS, kp, st);
 }
 
+// Device buffers of one call's staging (scene-owned, or carved from the
+// scratch array by eps_grad_vjp_noalloc).
+struct Staging {
+    double* fval = nullptr;
+    float4* bbox = nullptr;
+    PrimRec* prec = nullptr;
+    double* ztab = nullptr;              // only when the extrusion tables depend on p
+    uint32_t* code = nullptr;
+    uint32_t* gcode = nullptr;
+    double* gspread = nullptr;           // spread accumulation
+    unsigned long long* fx = nullptr;    // deterministic reduction
+};
+
+// Lays out one VJP call's staging at base; returns the bytes it needs (each
+// table aligned to 256 bytes).  base == nullptr only measures.
+static int64_t scratch_layout(const sg_scene* s, bool det, bool spread, char* base, Staging* st) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char* {
+        char* q = base ? base + off : nullptr;
+        off += (std::max<int64_t>(bytes, 1) + 255) / 256 * 256;
+        return q;
+    };
+    const int64_t n = std::max<int64_t>(1, s->n_params);
+    st->fval = (double*)take(8 * std::max<int64_t>(1, s->nfield));
+    st->bbox = (float4*)take((int64_t)sizeof(float4) * s->nprim);
+    st->prec = (PrimRec*)take((int64_t)sizeof(PrimRec) * s->nprim);
+    if (!s->static_w) {
+        st->ztab = (double*)take(24 * (int64_t)s->ncomp * s->nclass * s->nw);
+        st->code = (uint32_t*)take(4 * (int64_t)s->ncomp * s->nw);
+        st->gcode = (uint32_t*)take(4 * (int64_t)s->ncomp * ((s->nw + kGroup - 1) / kGroup));
+    }
+    if (spread) st->gspread = (double*)take(8 * (int64_t)kGradSpread * n);
+    if (det) st->fx = (unsigned long long*)take(8 * (3 * n + 1));
+    return off;
+}
+
 static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device, int mode,
                             const void* const* e_fwd, const void* const* e_adj, double omega, const float* geps,
-                            double* grad, int grad_on_device, void* stream) {
+                            double* grad, int grad_on_device, void* stream, bool noalloc = false) {
     sg_status rc = check_call(ctx, s);
     if (rc != SG_OK) return rc;
     if (!grad && s->n_params > 0) return fail(SG_E_INVALID, "grad is NULL");
@@ -933,14 +990,54 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     }
     std::lock_guard<std::mutex> lk(s->mu);
     hipStream_t st = (hipStream_t)stream;
+    const bool det = s->deterministic && s->n_params > 0;
+    const bool spread = !det && s->spread && s->n_params > 0;
+    Staging stg;
+    if (noalloc) {
+        // every per-call table in the scratch array: no allocation on any path
+        const int64_t need = scratch_layout(s, det, spread, (char*)ctx->scratch, &stg);
+        if (need > kScratchBytes)
+            return fail(SG_E_TOO_LARGE, "eps_grad_vjp_noalloc: the scene's staging needs %lld bytes, the scratch holds "
+                        "%lld", (long long)need, (long long)kScratchBytes);
+    } else {
+        stg.fval = s->d_fval[0];
+        stg.bbox = s->d_bbox[0];
+        stg.prec = s->d_prec[0];
+        if (!s->static_w) {
+            stg.ztab = s->d_ztab[0];
+            stg.code = s->d_code[0];
+            stg.gcode = s->d_gcode[0];
+        }
+        stg.gspread = s->d_gspread;
+        if (det) {
+            if (!s->d_fx) HIP_OK(hipMalloc((void**)&s->d_fx, (3 * s->n_params + 1) * sizeof(unsigned long long)));
+            stg.fx = s->d_fx;
+        }
+    }
     const double* dp;
     if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
     double* g = grad_on_device ? grad : s->d_grad;
     StageParams sp = stage_params(s, dp);
+    sp.fval[0] = stg.fval;
+    sp.bbox[0] = stg.bbox;
+    sp.prec[0] = stg.prec;
+    if (!s->static_w) {
+        sp.ztab[0] = stg.ztab;
+        sp.code[0] = stg.code;
+        sp.gcode[0] = stg.gcode;
+    }
     sp.zero_ptr = g;
     sp.zero_n = s->n_params;
     HIP_OK(launch_stage(sp, 1, st));
     KParams kp = column_params(s);
+    kp.fval = stg.fval;
+    kp.bbox = stg.bbox;
+    kp.prec = stg.prec;
+    if (!s->static_w) {
+        kp.ztab = stg.ztab;
+        kp.code = stg.code;
+        kp.gcode = stg.gcode;
+    }
     kp.grad = g;
     if (mode == MODE_VJP_SPARSE) {
         // its segments split only the steps where some class is nonzero, and
@@ -955,18 +1052,17 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
         HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_nread), 0.0, kReadSlots, st));
         kp.nread = s->d_nread;
     }
-    const bool det = s->deterministic && s->n_params > 0;
-    const bool spread = !det && s->spread && s->n_params > 0;
+    // the spread copies and the fixed-point accumulators start at zero (a
+    // fill kernel: they hold the previous call's sums)
     if (spread) {
-        HIP_OK(launch_fill(s->d_gspread, 0.0, (int64_t)kGradSpread * s->n_params, st));
-        kp.grad = s->d_gspread;
+        HIP_OK(launch_fill(stg.gspread, 0.0, (int64_t)kGradSpread * s->n_params, st));
+        kp.grad = stg.gspread;
         kp.gstride = s->n_params;
     }
     if (det) {
         const int64_t words = 3 * s->n_params + 1;
-        if (!s->d_fx) HIP_OK(hipMalloc((void**)&s->d_fx, words * sizeof(unsigned long long)));
-        HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_fx), 0.0, words, st));   // all-zero bits
-        kp.fx = s->d_fx;
+        HIP_OK(launch_fill(reinterpret_cast<double*>(stg.fx), 0.0, words, st));   // all-zero bits
+        kp.fx = stg.fx;
         kp.fx_n = s->n_params;
     }
     if (fields) {
@@ -979,9 +1075,13 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     } else {
         kp.geps = geps;
     }
-    if ((rc = run_column(s, mode, kp, st)) != SG_OK) return rc;
-    if (det) HIP_OK(launch_fx_finish(s->d_fx, s->n_params, g, st));
-    if (spread) HIP_OK(launch_spread_finish(s->d_gspread, s->n_params, g, st));
+    if (noalloc) {
+        HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));     // untraced: tracing creates events
+    } else if ((rc = run_column(s, mode, kp, st)) != SG_OK) {
+        return rc;
+    }
+    if (det) HIP_OK(launch_fx_finish(stg.fx, s->n_params, g, st));
+    if (spread) HIP_OK(launch_spread_finish(stg.gspread, s->n_params, g, st));
     return finish_grad(s, grad, grad_on_device, st);
 }
 
@@ -997,6 +1097,13 @@ extern "C" sg_status eps_grad_vjp(sg_ctx* ctx, sg_scene* s, const double* p, int
                                   void* stream) {
     return vjp_common(ctx, s, p, p_on_device, MODE_VJP_FIELDS, e_fwd, e_adj, omega, nullptr, grad, grad_on_device,
                       stream);
+}
+
+extern "C" sg_status eps_grad_vjp_noalloc(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,
+                                          const void* const* e_fwd, const void* const* e_adj, double omega,
+                                          double* grad, int grad_on_device, void* stream) {
+    return vjp_common(ctx, s, p, p_on_device, MODE_VJP_FIELDS, e_fwd, e_adj, omega, nullptr, grad, grad_on_device,
+                      stream, true);
 }
 
 extern "C" sg_status eps_grad_vjp_sparse(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_device,

@@ -22,6 +22,7 @@ sg_status fail(sg_status code, const char* fmt, ...);
 
 struct sg_ctx {
     int device;
+    void* scratch = nullptr;    // device address of this device's copy of the allocation-free scratch array
 };
 
 struct sg_scene {
