@@ -161,10 +161,14 @@ void sg_ctx_destroy(sg_ctx* ctx);
 const char* sg_last_error(void);
 
 /* Compile a scene description (copied; the caller's arrays may be freed after
- * the call) into device tables.  Trees may nest one level below the root:
- * root = op(children), each child a primitive or a node whose children are all
- * primitives; at most 4 such groups and 8 distinct extrusion classes.
- * Deeper trees return SG_E_UNSUPPORTED. */
+ * the call) into device tables.  Op trees of any shape and depth (eq:eps:
+ * nested unions, intersections and differences, a levels node as the root)
+ * with at most 6 op nodes (a levels root turns each primitive among its
+ * material sets into a node of its own) and at most 8 extrusion classes (the
+ * primitives that are children of one node with the same sign there and the
+ * same factor along the column axis form one class); larger trees return
+ * SG_E_UNSUPPORTED.  Every node must lie below the root and every primitive
+ * may appear once. */
 sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* desc, sg_scene** out);
 void sg_scene_destroy(sg_scene* scene);
 sg_status sg_scene_info(const sg_scene* scene, int64_t* n_params, int32_t* ncomp, int64_t dims[3]);
@@ -297,8 +301,15 @@ typedef struct sg_server_opts {
     int32_t max_batch;          /* requests per batch (>= 1) */
     int32_t n_streams;          /* batches in flight at once, one per stream (1..8) */
     int32_t fake_executor;      /* 1: no device work (scheduling tests); the result of a
-                                   request is grad_k = 2 p_k + (seed mod 1000) after fake_us */
+                                   request is grad_k = 2 p_k + (seed mod 1000); a batch takes
+                                   fake_us plus its estimated time (request_bytes at 4.5 TB/s) */
     int64_t fake_us;
+    int64_t max_launch_us;      /* > 0: a batch takes work only up to this many estimated
+                                   microseconds (HBM bytes at 4.5 TB/s: 16 per field sample
+                                   generated and 16 per sample of the column stream); larger
+                                   requests are sliced over several batches of one stream, so
+                                   requests that arrive meanwhile do not wait for all of them.
+                                   0: every batch takes its requests whole */
 } sg_server_opts;
 typedef struct sg_req_stats {
     int64_t submit_ns, admit_ns, launch_ns, done_ns;   /* steady-clock times */
@@ -320,6 +331,15 @@ sg_status serve_open_fake_session(sg_server* server, int64_t n_params, int64_t r
  * SG_E_TOO_LARGE if the request can never fit the budget. */
 sg_status serve_submit(sg_server* server, uint32_t session, const double* p, uint64_t field_seed, double omega,
                        uint64_t* ticket);
+/* Queues a request on the caller's field planes (Sec. "Background": E and
+ * E_adj are the solver's outputs, given to step 5): e_fwd, e_adj are arrays
+ * of C device pointers to complex64 planes as for eps_grad_vjp.  The pointer
+ * arrays are copied; the planes are read by the device work of the request,
+ * so they must stay allocated and unchanged until serve_poll has returned
+ * the ticket's outcome (or the server is destroyed).  The request holds only
+ * staging memory from the budget. */
+sg_status serve_submit_fields(sg_server* server, uint32_t session, const double* p, const void* const* e_fwd,
+                              const void* const* e_adj, double omega, uint64_t* ticket);
 /* Waits up to timeout_us (0: no wait, < 0: forever) for a request.  SG_OK: done,
  * the gradient (n_params FP64) is copied to grad_out (host) and the ticket is
  * retired; SG_EAGAIN: not done yet; SG_E_CANCELLED / SG_E_DEVICE: retired with

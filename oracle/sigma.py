@@ -12,7 +12,7 @@ import numpy as np
 from scipy.special import erf as _erf, expit as _expit
 
 KINDS = ("sigmoid", "erf", "sin", "linear", "quadratic")
-_R2 = 1.0 / np.sqrt(2.0)
+_R2 = np.sqrt(0.5)     # 1/sqrt(2), correctly rounded
 
 
 def sigma(kind, t):

@@ -55,7 +55,8 @@ class sg_scene_desc(C.Structure):
 
 class sg_server_opts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("max_batch", C.c_int32),
-                ("n_streams", C.c_int32), ("fake_executor", C.c_int32), ("fake_us", C.c_int64)]
+                ("n_streams", C.c_int32), ("fake_executor", C.c_int32), ("fake_us", C.c_int64),
+                ("max_launch_us", C.c_int64)]
 
 
 class sg_req_stats(C.Structure):
@@ -95,6 +96,7 @@ SIGNATURES = {
     "serve_open_session": (_S, [_P, _P, C.POINTER(C.c_uint32)]),
     "serve_open_fake_session": (_S, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_uint32)]),
     "serve_submit": (_S, [_P, C.c_uint32, _P, C.c_uint64, _D, C.POINTER(C.c_uint64)]),
+    "serve_submit_fields": (_S, [_P, C.c_uint32, _P, _P, _P, _D, C.POINTER(C.c_uint64)]),
     "serve_poll": (_S, [_P, C.c_uint64, _P, C.c_int64, C.POINTER(sg_req_stats)]),
     "serve_cancel": (_S, [_P, C.c_uint64]),
     "serve_counters": (_S, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),

@@ -227,21 +227,24 @@ class Server:
     its gradient."""
 
     def __init__(self, hbm_budget_bytes=0, max_slots=64, max_batch=16, n_streams=2, device=0,
-                 fake_executor=False, fake_us=0):
+                 fake_executor=False, fake_us=0, max_launch_us=0):
         o = _lib.sg_server_opts(int(hbm_budget_bytes), int(max_slots), int(max_batch), int(n_streams),
-                                int(bool(fake_executor)), int(fake_us))
+                                int(bool(fake_executor)), int(fake_us), int(max_launch_us))
         h = C.c_void_p()
         ctx = None if fake_executor else context(device)
         check(lib().sg_server_create(ctx, C.byref(o), C.byref(h)))
         self.handle = h
         self.n_params = {}
         self._scenes = []
+        self._scene_of = {}
+        self._keep = {}          # caller planes of requests not yet polled
 
     def open_session(self, scene):
         sid = C.c_uint32()
         check(lib().serve_open_session(self.handle, scene.handle, C.byref(sid)))
         self.n_params[sid.value] = scene.n_params
         self._scenes.append(scene)
+        self._scene_of[sid.value] = scene
         return sid.value
 
     def open_fake_session(self, n_params, request_bytes):
@@ -260,6 +263,22 @@ class Server:
                                  C.byref(t)))
         return t.value
 
+    def submit_fields(self, session, p, E, A, omega):
+        """A request on the caller's complex64 planes E, A (C, Nz, Ny, Nx CUDA
+        tensors); they must stay alive and unchanged until the ticket is
+        polled."""
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        n = self.n_params.get(session)
+        if n is not None and a.size != n:
+            raise ValueError("p has the wrong size for this session")
+        sc = self._scene_of[session]
+        fe, fa = _plane_ptrs(sc, E), _plane_ptrs(sc, A)
+        t = C.c_uint64()
+        check(lib().serve_submit_fields(self.handle, int(session), C.c_void_p(a.ctypes.data), fe, fa, float(omega),
+                                        C.byref(t)))
+        self._keep[t.value] = (E, A)
+        return t.value
+
     def poll(self, ticket, n_params, timeout_us=-1):
         """(status, grad or None, stats dict).  status 'ok' | 'pending' (raises
         on cancelled / failed)."""
@@ -268,6 +287,7 @@ class Server:
         r = lib().serve_poll(self.handle, int(ticket), C.c_void_p(g.ctypes.data), int(timeout_us), C.byref(st))
         if r == _lib.SG_EAGAIN:
             return "pending", None, None
+        self._keep.pop(int(ticket), None)        # the ticket is retired: its planes are free
         check(r)
         stats = {k: getattr(st, k) for k in ("submit_ns", "admit_ns", "launch_ns", "done_ns", "batch_size")}
         return "ok", g[:n_params], stats

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -234,10 +235,16 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
                 if (!(d->consts[p.const_off + j + 1] > d->consts[p.const_off + j]))
                     return fail(SG_E_INVALID, "gcart %d: vertex x not increasing", i);
     }
-    // tree -> groups
-    struct Group { int op; std::vector<int> prims; int nmember; };
-    std::vector<Group> groups;
-    const sg_node_desc& root = d->nodes_op[d->nnode - 1];
+    // op tree -> nodes (postfix, root last), each with the primitives among
+    // its children (and the sign they enter its sum with) and its child nodes
+    struct HNode {
+        int op = SG_OP_UNION;
+        int parent = -1;
+        double sign = 1.0;
+        int nchild = 0;
+        std::vector<int> prims;
+        std::vector<double> psign;
+    };
     auto child = [&](const sg_node_desc& nd, int c) -> int { return d->children[nd.child_off + c]; };
     for (int k = 0; k < d->nnode; ++k) {
         const sg_node_desc& nd = d->nodes_op[k];
@@ -252,96 +259,118 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             if (ch < 0 && -(ch + 1) >= k) return fail(SG_E_INVALID, "node %d: child node must come earlier", k);
         }
     }
+    std::vector<HNode> hn;
+    std::vector<int> map(d->nnode, -1);       // description node -> hn index
     std::vector<int> used(d->nprim, 0);
-    auto leaf_group = [&](int nodeidx, Group& g) -> sg_status {
-        const sg_node_desc& nd = d->nodes_op[nodeidx];
-        if (nd.op == SG_OP_DIFFERENCE)
-            return fail(SG_E_UNSUPPORTED, "a difference below the root is not supported by the GPU path");
-        if (nd.op == SG_OP_LEVELS) return fail(SG_E_INVALID, "levels must be the root");
-        g.op = nd.op;
-        g.nmember = nd.nchild;
+    const sg_node_desc& root = d->nodes_op[d->nnode - 1];
+    const bool levels = root.op == SG_OP_LEVELS;
+    double lev_q[kMaxNodes] = {};
+    std::vector<int> lev_child;               // hn index of each level's node
+    for (int k = 0; k < d->nnode; ++k) {
+        const sg_node_desc& nd = d->nodes_op[k];
+        const bool is_root = k == d->nnode - 1;
+        if (is_root && levels) {
+            const int K = nd.nchild;
+            if (K < 2 || K > kMaxNodes - 1) return fail(SG_E_UNSUPPORTED, "levels: 2 to %d material sets", kMaxNodes - 1);
+            if (nd.aux < 0 || nd.aux + K > d->nconst) return fail(SG_E_INVALID, "levels: level values out of consts");
+            const double* lv = d->consts + nd.aux;
+            for (int c = 0; c < K; ++c) {
+                if (!(lv[c] > 0.0) || !std::isfinite(lv[c]) || (c > 0 && lv[c] < lv[c - 1]))
+                    return fail(SG_E_INVALID, "levels: values must be positive and ascending");
+                lev_q[c] = c == 0 ? 1.0 : lv[c - 1] / lv[c];
+            }
+            const double top = d->eps_fg - d->eps_bg;
+            if (std::fabs(lv[K - 1] - top) > 1e-12 * std::max(1.0, std::fabs(top)))
+                return fail(SG_E_INVALID, "levels: the top level must equal eps_fg - eps_bg");
+            // every material set becomes a node: a primitive child is a union of one
+            for (int c = 0; c < K; ++c) {
+                const int ch = child(nd, c);
+                if (ch >= 0) {
+                    HNode w;
+                    w.nchild = 1;
+                    w.prims.push_back(ch);
+                    w.psign.push_back(1.0);
+                    hn.push_back(w);
+                    lev_child.push_back((int)hn.size() - 1);
+                } else {
+                    const int j = map[-(ch + 1)];
+                    if (hn[j].parent >= 0) return fail(SG_E_INVALID, "node %d has two parents", -(ch + 1));
+                    if (hn[j].op == SG_OP_LEVELS) return fail(SG_E_INVALID, "levels must be the root");
+                    lev_child.push_back(j);
+                }
+            }
+            HNode r;
+            r.op = SG_OP_LEVELS;
+            r.nchild = K;
+            hn.push_back(r);
+            for (int j : lev_child) hn[j].parent = (int)hn.size() - 1;
+            map[k] = (int)hn.size() - 1;
+            continue;
+        }
+        HNode h;
+        h.op = nd.op;
+        h.nchild = nd.nchild;
+        const int me = (int)hn.size();
         for (int c = 0; c < nd.nchild; ++c) {
             const int ch = child(nd, c);
-            if (ch < 0) return fail(SG_E_UNSUPPORTED, "op trees deeper than root -> node -> primitive");
-            g.prims.push_back(ch);
-        }
-        return SG_OK;
-    };
-    int root_op;
-    double group_q[kMaxGroups] = {1.0, 1.0, 1.0, 1.0};    // levels root: eps^{g-1} / eps^g
-    if (root.op == SG_OP_LEVELS) {
-        // one group per material set, in level order
-        root_op = SG_OP_LEVELS;
-        const int K = root.nchild;
-        if (K < 2 || K > kMaxGroups) return fail(SG_E_UNSUPPORTED, "levels: 2 to %d material sets", kMaxGroups);
-        if (root.aux < 0 || root.aux + K > d->nconst) return fail(SG_E_INVALID, "levels: level values out of consts");
-        const double* lv = d->consts + root.aux;
-        for (int c = 0; c < K; ++c) {
-            if (!(lv[c] > 0.0) || !std::isfinite(lv[c]) || (c > 0 && lv[c] < lv[c - 1]))
-                return fail(SG_E_INVALID, "levels: values must be positive and ascending");
-            group_q[c] = c == 0 ? 1.0 : lv[c - 1] / lv[c];
-        }
-        const double top = d->eps_fg - d->eps_bg;
-        if (std::fabs(lv[K - 1] - top) > 1e-12 * std::max(1.0, std::fabs(top)))
-            return fail(SG_E_INVALID, "levels: the top level must equal eps_fg - eps_bg");
-        for (int c = 0; c < K; ++c) {
-            Group g;
-            const int ch = child(root, c);
+            const double sg = (nd.op == SG_OP_DIFFERENCE && c == 1) ? -1.0 : 1.0;
             if (ch >= 0) {
-                g.op = SG_OP_UNION;
-                g.nmember = 1;
-                g.prims.push_back(ch);
+                h.prims.push_back(ch);
+                h.psign.push_back(sg);
             } else {
-                sg_status st = leaf_group(-(ch + 1), g);
-                if (st != SG_OK) return st;
-            }
-            groups.push_back(g);
-        }
-    } else if (root.op == SG_OP_DIFFERENCE) {
-        root_op = SG_OP_DIFFERENCE;
-        for (int c = 0; c < 2; ++c) {
-            Group g;
-            const int ch = child(root, c);
-            if (ch >= 0) {
-                g.op = SG_OP_UNION;
-                g.nmember = 1;
-                g.prims.push_back(ch);
-            } else {
-                sg_status st = leaf_group(-(ch + 1), g);
-                if (st != SG_OK) return st;
-            }
-            groups.push_back(g);
-        }
-    } else {
-        Group direct;
-        direct.op = root.op;
-        direct.nmember = 0;
-        std::vector<Group> nodes;
-        for (int c = 0; c < root.nchild; ++c) {
-            const int ch = child(root, c);
-            if (ch >= 0) {
-                direct.prims.push_back(ch);
-                direct.nmember++;
-            } else {
-                Group g;
-                sg_status st = leaf_group(-(ch + 1), g);
-                if (st != SG_OK) return st;
-                nodes.push_back(g);
+                const int j = map[-(ch + 1)];
+                if (hn[j].parent >= 0) return fail(SG_E_INVALID, "node %d has two parents", -(ch + 1));
+                hn[j].parent = me;
+                hn[j].sign = sg;
             }
         }
-        // primitives directly under a union / intersection root form one group
-        // with the root's op: min{1, min{1, a} + X} = min{1, a + X} and the
-        // clamped-sum intersection nests the same way.
-        if (!direct.prims.empty()) groups.push_back(direct);
-        for (auto& g : nodes) groups.push_back(g);
-        root_op = groups.size() == 1 ? ROOT_NONE : root.op;
+        hn.push_back(h);
+        map[k] = me;
     }
-    if ((int)groups.size() > kMaxGroups) return fail(SG_E_UNSUPPORTED, "more than %d groups under the root", kMaxGroups);
-    for (auto& g : groups)
-        for (int pi : g.prims) {
+    // every node must hang below the root
+    for (int j = 0; j + 1 < (int)hn.size(); ++j)
+        if (hn[j].parent < 0) return fail(SG_E_INVALID, "op node %d is not below the root", j);
+    if ((int)hn.size() > kMaxNodes)
+        return fail(SG_E_UNSUPPORTED, "the op tree has %d nodes (the GPU composition takes at most %d)", (int)hn.size(),
+                    kMaxNodes);
+    for (auto& h : hn)
+        for (int pi : h.prims) {
             if (used[pi]) return fail(SG_E_INVALID, "primitive %d appears twice in the tree", pi);
             used[pi] = 1;
         }
+    // the order classes are numbered in: a depth-first walk from the root,
+    // children in order, so a difference's minuend side comes first
+    std::vector<std::pair<int, int>> class_order;     // (hn node, index into its prims)
+    {
+        std::vector<std::vector<int>> kids(hn.size());
+        for (int j = 0; j + 1 < (int)hn.size(); ++j) kids[hn[j].parent].push_back(j);
+        // children of a description node in their given order: primitives
+        // and child nodes interleave as listed
+        std::vector<std::vector<std::pair<int, int>>> items(hn.size());   // (0 prim idx | 1 node, value)
+        for (int k = 0; k < d->nnode; ++k) {
+            const int me = map[k];
+            const sg_node_desc& nd = d->nodes_op[k];
+            if (hn[me].op == SG_OP_LEVELS) {
+                for (int j : lev_child) items[me].push_back({1, j});
+                continue;
+            }
+            int pc = 0;
+            for (int c = 0; c < nd.nchild; ++c) {
+                const int ch = child(nd, c);
+                if (ch >= 0) items[me].push_back({0, pc++});
+                else items[me].push_back({1, map[-(ch + 1)]});
+            }
+        }
+        for (int j : lev_child)
+            if (items[j].empty() && hn[j].prims.size() == 1) items[j].push_back({0, 0});
+        std::function<void(int)> walk = [&](int k) {
+            for (auto& it : items[k]) {
+                if (it.first == 0) class_order.push_back({k, it.second});
+                else walk(it.second);
+            }
+        };
+        walk((int)hn.size() - 1);
+    }
 
     // column axis: y for 2D scenes made only of boxes whose y-extents form at
     // most kMaxClasses classes (the boxes' y factor then becomes the column
@@ -351,25 +380,25 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         if (used[i] && d->prims[i].type != SG_PRIM_BOX) all_box = false;
     bool y_classes_fit = true;
     if (d->dim == 2 && all_box) {
-        int total = 0;
-        for (auto& g : groups) {
-            std::vector<ColSpec> seen;
-            for (int pi : g.prims) {
-                const sg_prim_desc& p = d->prims[pi];
-                ColSpec cs{};
-                cs.bounded = p.bounded[1] != 0;
-                if (cs.bounded) {
-                    cs.lo = d->fields[p.field_off + 2];
-                    cs.hi = d->fields[p.field_off + 3];
-                    cs.kind = p.sigma[1].kind;
-                    cs.kmode = p.sigma[1].kmode;
-                    cs.k = p.sigma[1].k;
-                }
-                if (std::find(seen.begin(), seen.end(), cs) == seen.end()) seen.push_back(cs);
+        // classes are (node, sign, y factor) when y is the column axis
+        std::vector<std::tuple<int, double, ColSpec>> seen;
+        for (auto& [k, i] : class_order) {
+            const sg_prim_desc& p = d->prims[hn[k].prims[i]];
+            ColSpec cs{};
+            cs.bounded = p.bounded[1] != 0;
+            if (cs.bounded) {
+                cs.lo = d->fields[p.field_off + 2];
+                cs.hi = d->fields[p.field_off + 3];
+                cs.kind = p.sigma[1].kind;
+                cs.kmode = p.sigma[1].kmode;
+                cs.k = p.sigma[1].k;
             }
-            total += (int)seen.size();
+            bool found = false;
+            for (auto& t : seen)
+                if (std::get<0>(t) == k && std::get<1>(t) == hn[k].psign[i] && std::get<2>(t) == cs) found = true;
+            if (!found) seen.emplace_back(k, hn[k].psign[i], cs);
         }
-        y_classes_fit = total <= kMaxClasses;
+        y_classes_fit = (int)seen.size() <= kMaxClasses;
     }
     const int col = (d->dim == 2 && all_box && y_classes_fit) ? 1 : 2;
     const int axis_v = col == 2 ? 1 : 2;
@@ -428,44 +457,47 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     };
     std::vector<int> prim_cls(d->nprim, -1);
     std::vector<ColSpec> specs;
-    std::vector<int> spec_group;
-    for (int gi = 0; gi < (int)groups.size(); ++gi) {
-        for (int pi : groups[gi].prims) {
-            auto [cs, fz] = colspec(pi);
-            int found = -1;
-            for (int c = 0; c < (int)specs.size(); ++c)
-                if (spec_group[c] == gi && specs[c] == cs) found = c;
-            if (found < 0) {
-                if ((int)specs.size() == kMaxClasses) {
-                    free_scene(s);
-                    return fail(SG_E_UNSUPPORTED, "more than %d extrusion classes", kMaxClasses);
-                }
-                found = (int)specs.size();
-                specs.push_back(cs);
-                spec_group.push_back(gi);
-                DevClass dc{};
-                dc.group = gi;
-                dc.bounded = cs.bounded;
-                dc.flo = cs.bounded ? fz : -1;
-                dc.fhi = cs.bounded ? fz + 1 : -1;
-                dc.skind = cs.kind;
-                dc.smode = cs.kmode;
-                dc.k = cs.bounded ? cs.k : 1.0;
-                s->classes.push_back(dc);
+    for (auto& [k, i] : class_order) {
+        const int pi = hn[k].prims[i];
+        const double sg = hn[k].psign[i];
+        auto [cs, fz] = colspec(pi);
+        int found = -1;
+        for (int c = 0; c < (int)specs.size(); ++c)
+            if (s->classes[c].node == k && s->cls_sign[c] == sg && specs[c] == cs) found = c;
+        if (found < 0) {
+            if ((int)specs.size() == kMaxClasses) {
+                free_scene(s);
+                return fail(SG_E_UNSUPPORTED, "more than %d extrusion classes", kMaxClasses);
             }
-            prim_cls[pi] = found;
+            found = (int)specs.size();
+            specs.push_back(cs);
+            DevClass dc{};
+            dc.node = k;
+            dc.bounded = cs.bounded;
+            dc.flo = cs.bounded ? fz : -1;
+            dc.fhi = cs.bounded ? fz + 1 : -1;
+            dc.skind = cs.kind;
+            dc.smode = cs.kmode;
+            dc.k = cs.bounded ? cs.k : 1.0;
+            s->classes.push_back(dc);
+            s->cls_sign.push_back(sg);
         }
+        prim_cls[pi] = found;
     }
     s->nclass = (int)s->classes.size();
     s->ncls_pad = s->nclass <= 1 ? 1 : s->nclass <= 2 ? 2 : s->nclass <= 4 ? 4 : 8;
-    s->ngroup = (int)groups.size();
-    s->root_op = root_op;
-    for (int g = 0; g < kMaxGroups; ++g) {
-        s->group_op[g] = g < s->ngroup ? groups[g].op : SG_OP_UNION;
-        s->group_nm1[g] = g < s->ngroup ? (double)(groups[g].nmember - 1) : 0.0;
-        s->group_q[g] = group_q[g];
+    s->nnode = (int)hn.size();
+    for (int k = 0; k < s->nnode; ++k) {
+        s->node_op[k] = hn[k].op;
+        s->node_parent[k] = hn[k].parent;
+        s->node_sign[k] = hn[k].sign;
+        s->node_nm1[k] = (double)(hn[k].nchild - 1);
     }
-    s->root_nm1 = (double)(s->ngroup - 1);
+    s->nlev = (int)lev_child.size();
+    for (int g = 0; g < s->nlev; ++g) {
+        s->lev_node[g] = lev_child[g];
+        s->lev_q[g] = lev_q[g];
+    }
 
     // lattices and the largest sample width per in-plane axis
     std::vector<double> lat;
@@ -601,18 +633,37 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         s->variant = VAR_ALL;
         for (int v = 0; v < 5; ++v)
             if ((tmask & ~vt[v]) == 0 && (smask & ~vs[v]) == 0) { s->variant = v; break; }
-        // op-tree layout
-        auto plain_union = [&](int g) { return groups[g].op == SG_OP_UNION || groups[g].nmember == 1; };
-        int ncls_g[kMaxGroups] = {0, 0, 0, 0};
-        for (const DevClass& c : s->classes) ncls_g[c.group]++;
+        // op-tree layout: the fixed ones need every node to be a plain union
+        // (or a single-primitive node) over primitives only
+        auto plain = [&](int k) {
+            return (hn[k].op == SG_OP_UNION || hn[k].nchild == 1) && (int)hn[k].prims.size() == hn[k].nchild;
+        };
+        int ncls_node[kMaxNodes] = {};
+        bool neg_cls = false;
+        for (int c = 0; c < s->nclass; ++c) {
+            ncls_node[s->classes[c].node]++;
+            neg_cls = neg_cls || s->cls_sign[c] < 0.0;
+        }
+        const int rt = s->nnode - 1;
         s->tree = s->nclass <= 4 ? TR_GEN4 : TR_GEN8;
-        if (s->ngroup == 1 && plain_union(0)) {
+        if (s->nnode == 1 && plain(0) && !neg_cls) {
             if (s->nclass == 1) s->tree = TR_U1;
             else if (s->nclass == 2) s->tree = TR_U2;
-        } else if (s->ngroup == 2 && s->root_op == SG_OP_DIFFERENCE && plain_union(0) && plain_union(1) &&
-                   ncls_g[0] == 1) {
-            if (ncls_g[1] == 1) s->tree = TR_D11;
-            else if (ncls_g[1] == 2) s->tree = TR_D12;
+        } else if (hn[rt].op == SG_OP_DIFFERENCE && s->nnode <= 3) {
+            // difference of (a primitive or a plain union) and (a primitive or a
+            // plain union); class 0 is the minuend's, the rest the subtrahend's
+            bool ok = true;
+            int nsub = 0;
+            for (int k = 0; k < rt; ++k) ok = ok && plain(k) && hn[k].parent == rt;
+            for (int c = 0; c < s->nclass && ok; ++c) {
+                const int k = s->classes[c].node;
+                const bool minuend = (k == rt) ? s->cls_sign[c] > 0.0 : hn[k].sign > 0.0;
+                if (k != rt && s->cls_sign[c] < 0.0) ok = false;
+                if ((c == 0) != minuend) ok = false;
+                if (!minuend) ++nsub;
+            }
+            if (ok && nsub == 1) s->tree = TR_D11;
+            else if (ok && nsub == 2) s->tree = TR_D12;
         }
         if (s->tree == TR_GEN4 || s->tree == TR_GEN8) s->variant = VAR_ALL;
     }
@@ -794,21 +845,24 @@ KParams sg::column_params(sg_scene* s, int64_t target_blocks) {
     kp.nprim = s->nprim;
     kp.nclass = s->nclass;
     for (int c = 0; c < kMaxClasses; ++c) {
-        kp.cls_group[c] = c < s->nclass ? s->classes[c].group : 0;
+        kp.cls_node[c] = c < s->nclass ? s->classes[c].node : 0;
+        kp.cls_sign[c] = c < s->nclass ? s->cls_sign[c] : 0.0;
         int wp = 0;
         if (c < s->nclass && s->classes[c].bounded) {
             wp = s->fields[s->classes[c].flo].idx >= 0 || s->fields[s->classes[c].fhi].idx >= 0;
         }
         kp.cls_wparam[c] = wp;
     }
-    kp.ngroup = s->ngroup;
-    kp.root_op = s->root_op;
-    for (int g = 0; g < kMaxGroups; ++g) {
-        kp.group_op[g] = s->group_op[g];
-        kp.group_nm1[g] = s->group_nm1[g];
-        kp.group_q[g] = s->group_q[g];
+    kp.nnode = s->nnode;
+    kp.nlev = s->nlev;
+    for (int k = 0; k < kMaxNodes; ++k) {
+        kp.node_op[k] = s->node_op[k];
+        kp.node_parent[k] = s->node_parent[k];
+        kp.node_sign[k] = s->node_sign[k];
+        kp.node_nm1[k] = s->node_nm1[k];
+        kp.lev_node[k] = s->lev_node[k];
+        kp.lev_q[k] = s->lev_q[k];
     }
-    kp.root_nm1 = s->root_nm1;
     kp.eps_bg = s->eps_bg;
     kp.deps = s->eps_fg - s->eps_bg;
     for (int c = 0; c < kMaxComp; ++c) {

@@ -339,23 +339,14 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
     if (!hooked) after_stage();
 }
 
-// Composition at one column step: root value s and, per group g, the
-// derivative r_g = d s / d (group sum g) in {0, +1, -1}.
+// Composition at one column step: root value s and, per class c, the
+// derivative cf_c = d s / d (F_c Z_c) (0, +-1, or a product of the levels
+// root's ratios).
+template <int NC>
 struct Comp {
     double s;
-    double r0, r1, r2, r3;
+    double cf[NC];
 };
-
-__device__ __forceinline__ void group_op(const KParams& P, int g, double S, double& val, double& msk) {
-    if (P.group_op[g] == SG_OP_INTERSECTION) {
-        const double nm1 = P.group_nm1[g];
-        val = fmax(nm1, S) - nm1;
-        msk = (S > nm1) ? 1.0 : 0.0;
-    } else {
-        val = fmin(1.0, S);
-        msk = (S < 1.0) ? 1.0 : 0.0;
-    }
-}
 
 // Extrusion factors of a step on which every class factor is exactly 0 or 1:
 // bit c of mask set <=> Z_c = 1.
@@ -366,17 +357,18 @@ __device__ __forceinline__ void mask_z(uint32_t mask, double (&Z)[NC]) {
 }
 
 template <int TREE>
-__device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree_nc(TREE)],
-                                        const double (&Z)[tree_nc(TREE)]) {
+__device__ __forceinline__ Comp<tree_nc(TREE)> compose(const KParams& P, const double (&F)[tree_nc(TREE)],
+                                                       const double (&Z)[tree_nc(TREE)]) {
     constexpr int NC = tree_nc(TREE);
-    Comp o;
+    Comp<NC> o;
     if constexpr (TREE == TR_U1 || TREE == TR_U2) {
         double S = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) S += F[c] * Z[c];
         o.s = fmin(1.0, S);
-        o.r0 = S < 1.0 ? 1.0 : 0.0;
-        o.r1 = o.r2 = o.r3 = 0.0;
+        const double m = S < 1.0 ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) o.cf[c] = m;
         return o;
     } else if constexpr (TREE == TR_D11 || TREE == TR_D12) {
         const double S0 = F[0] * Z[0];
@@ -387,79 +379,122 @@ __device__ __forceinline__ Comp compose(const KParams& P, const double (&F)[tree
         const double d = v0 - v1;
         o.s = fmax(0.0, d);
         const bool pass = d > 0.0;
-        o.r0 = (pass && S0 < 1.0) ? 1.0 : 0.0;
-        o.r1 = (pass && S1 < 1.0) ? -1.0 : 0.0;
-        o.r2 = o.r3 = 0.0;
+        o.cf[0] = (pass && S0 < 1.0) ? 1.0 : 0.0;
+        const double r1 = (pass && S1 < 1.0) ? -1.0 : 0.0;
+#pragma unroll
+        for (int c = 1; c < NC; ++c) o.cf[c] = r1;
         return o;
     } else {
-        double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0;
+        // the general program: node sums in postfix order, then the chain
+        // rule back from the root (every node has one parent, after it).
+        // The clamp derivatives are bits of `passm`; a levels root keeps only
+        // its children's values.
+        constexpr int NN = kMaxNodes;
+        double acc[NN], lvv[NN], r[NN];
+#pragma unroll
+        for (int k = 0; k < NN; ++k) acc[k] = lvv[k] = r[k] = 0.0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             if (c < P.nclass) {
-                const double t = F[c] * Z[c];
-                const int g = P.cls_group[c];
-                if (g == 0) S0 += t;
-                else if (g == 1) S1 += t;
-                else if (g == 2) S2 += t;
-                else S3 += t;
+                const double t = P.cls_sign[c] * (F[c] * Z[c]);
+                const int kn = P.cls_node[c];
+#pragma unroll
+                for (int k = 0; k < NN; ++k)
+                    if (kn == k) acc[k] += t;
             }
         }
-        double v0, v1 = 0.0, v2 = 0.0, v3 = 0.0, m0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
-        group_op(P, 0, S0, v0, m0);
-        if (P.ngroup > 1) group_op(P, 1, S1, v1, m1);
-        if (P.ngroup > 2) group_op(P, 2, S2, v2, m2);
-        if (P.ngroup > 3) group_op(P, 3, S3, v3, m3);
-        if (P.root_op == ROOT_NONE) {
-            o.s = v0;
-            o.r0 = m0;
-            o.r1 = o.r2 = o.r3 = 0.0;
-        } else if (P.root_op == SG_OP_LEVELS) {
-            // Alg. cap: s = v_0, s = min{1, q_g s + v_g}; d s / d v_g = pass_g prod_{j > g} pass_j q_j
-            const double v[4] = {v0, v1, v2, v3}, mk[4] = {m0, m1, m2, m3};
-            double s = v0, pass[4] = {1.0, 0.0, 0.0, 0.0};
+        const int root = P.nnode - 1;
+        const bool lev_root = P.node_op[root] == SG_OP_LEVELS;
+        uint32_t passm = 0u;
+        double s = 0.0;
 #pragma unroll
-            for (int g = 1; g < 4; ++g) {
-                if (g < P.ngroup) {
-                    const double x = P.group_q[g] * s + v[g];
-                    pass[g] = x < 1.0 ? 1.0 : 0.0;
-                    s = fmin(1.0, x);
+        for (int k = 0; k < NN; ++k) {
+            if (k < P.nnode && !(lev_root && k == root)) {
+                const int op = P.node_op[k];
+                const double S = acc[k];
+                double v;
+                bool ps;
+                if (op == SG_OP_UNION) {
+                    v = fmin(1.0, S);
+                    ps = S < 1.0;
+                } else if (op == SG_OP_INTERSECTION) {
+                    const double nm1 = P.node_nm1[k];
+                    v = fmax(nm1, S) - nm1;
+                    ps = S > nm1;
+                } else {
+                    v = fmax(0.0, S);
+                    ps = S > 0.0;
+                }
+                if (ps) passm |= 1u << k;
+                if (k == root) s = v;
+                const int par = P.node_parent[k];
+#pragma unroll
+                for (int j = k + 1; j < NN; ++j)
+                    if (par == j) acc[j] += P.node_sign[k] * v;
+#pragma unroll
+                for (int g = 0; g < NN; ++g)
+                    if (g < P.nlev && P.lev_node[g] == k) lvv[g] = v;
+            }
+        }
+        if (lev_root) {
+            // Alg. cap: s = v_0, s = min{1, q_g s + v_g}; d s / d v_g =
+            // pass_g prod_{j > g} pass_j q_j (d s / d v_0 = prod_{j >= 1} pass_j q_j)
+            uint32_t lpass = 0u;
+            double t = lvv[0];
+#pragma unroll
+            for (int g = 1; g < NN; ++g) {
+                if (g < P.nlev) {
+                    const double x = P.lev_q[g] * t + lvv[g];
+                    if (x < 1.0) lpass |= 1u << g;
+                    t = fmin(1.0, x);
                 }
             }
-            double r[4] = {0.0, 0.0, 0.0, 0.0}, acc = 1.0;
+            s = t;
+            double a = 1.0;
 #pragma unroll
-            for (int g = 3; g >= 1; --g) {
-                if (g < P.ngroup) {
-                    r[g] = acc * pass[g];
-                    acc *= pass[g] * P.group_q[g];
+            for (int g = NN - 1; g >= 1; --g) {
+                if (g < P.nlev) {
+                    const double pg = ((lpass >> g) & 1u) ? 1.0 : 0.0;
+                    const double rg = a * pg;
+                    a *= pg * P.lev_q[g];
+#pragma unroll
+                    for (int j = 0; j < NN; ++j)
+                        if (P.lev_node[g] == j) r[j] = rg;
                 }
             }
-            r[0] = acc;
-            o.s = s;
-            o.r0 = r[0] * mk[0];
-            o.r1 = r[1] * mk[1];
-            o.r2 = r[2] * mk[2];
-            o.r3 = r[3] * mk[3];
-        } else if (P.root_op == SG_OP_DIFFERENCE) {
-            const double d = v0 - v1;
-            o.s = fmax(0.0, d);
-            const double m = d > 0.0 ? 1.0 : 0.0;
-            o.r0 = m * m0;
-            o.r1 = -m * m1;
-            o.r2 = o.r3 = 0.0;
+#pragma unroll
+            for (int j = 0; j < NN; ++j)
+                if (P.lev_node[0] == j) r[j] = a;
         } else {
-            const double tot = v0 + v1 + v2 + v3;
-            double m;
-            if (P.root_op == SG_OP_UNION) {
-                o.s = fmin(1.0, tot);
-                m = tot < 1.0 ? 1.0 : 0.0;
-            } else {
-                o.s = fmax(P.root_nm1, tot) - P.root_nm1;
-                m = tot > P.root_nm1 ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < NN; ++k)
+                if (k == root) r[k] = 1.0;
+        }
+        o.s = s;
+        // reverse: parents come after their children, so walking down from
+        // the root every r[parent] is final before it is used
+#pragma unroll
+        for (int k = NN - 2; k >= 0; --k) {
+            if (k < root) {
+                const int par = P.node_parent[k];
+                if (!(lev_root && par == root)) {
+                    double rp = 0.0;
+#pragma unroll
+                    for (int j = k + 1; j < NN; ++j)
+                        if (par == j) rp = ((passm >> j) & 1u) ? r[j] : 0.0;
+                    r[k] = rp * P.node_sign[k];
+                }
             }
-            o.r0 = m * m0;
-            o.r1 = m * m1;
-            o.r2 = m * m2;
-            o.r3 = m * m3;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            o.cf[c] = 0.0;
+            if (c < P.nclass) {
+                const int kn = P.cls_node[c];
+#pragma unroll
+                for (int k = 0; k < NN; ++k)
+                    if (kn == k) o.cf[c] = ((passm >> k) & 1u) ? r[k] * P.cls_sign[c] : 0.0;
+            }
         }
         return o;
     }
@@ -1347,16 +1382,12 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         for (int c = 0; c < NC; ++c) A[c] = Blo[c] = Bhi[c] = 0.0f;
         // g of one step times gscale is d F / d eps at that sample, times deps
         const float gscale = (FIELDS ? P.two_omega : 1.0f) * (float)P.deps;
-        // A_c += gd * r_(group of c) * Z_c (and the w-bound partials on general steps)
-        auto accumulate = [&](const Comp& o, const double (&Z)[NC], float gd, int w, bool general) {
-            const float cg0 = gd * (float)o.r0, cg1 = gd * (float)o.r1;
-            const float cg2 = gd * (float)o.r2, cg3 = gd * (float)o.r3;
+        // A_c += gd * cf_c * Z_c (and the w-bound partials on general steps)
+        auto accumulate = [&](const Comp<NC>& o, const double (&Z)[NC], float gd, int w, bool general) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 if (c < P.nclass) {
-                    constexpr int fixed = tree_group(TREE, 0) >= 0;
-                    const int g = fixed ? tree_group(TREE, c) : P.cls_group[c];
-                    const float cc = (g == 0) ? cg0 : (g == 1) ? cg1 : (g == 2) ? cg2 : cg3;
+                    const float cc = gd * (float)o.cf[c];
                     A[c] += cc * (float)Z[c];
                     if (general && P.cls_wparam[c]) {
                         const int64_t zi = 3 * ((int64_t)c * P.nw + w);
@@ -1533,7 +1564,8 @@ void k_column(const KParams P) {
 }
 
 // Several requests in one launch: request r owns blocks [first[r], first[r+1])
-// and its own parameter block plist[r] (same kernel specialization).
+// and its own parameter block plist[r] (same kernel specialization); they are
+// its blocks plist[r].block0 + [0, first[r+1] - first[r]).
 template <int MODE, int TREE, int TYPES, int SIGS>
 __global__ __launch_bounds__(256) void k_column_batch(const KParams* __restrict__ plist,
                                                       const int* __restrict__ first, int nreq) {
@@ -1543,7 +1575,7 @@ __global__ __launch_bounds__(256) void k_column_batch(const KParams* __restrict_
         const int mid = (lo + hi) >> 1;
         if (first[mid] <= b) lo = mid; else hi = mid;
     }
-    column_body<MODE, TREE, TYPES, SIGS>(plist[lo], b - first[lo]);
+    column_body<MODE, TREE, TYPES, SIGS>(plist[lo], b - first[lo] + plist[lo].block0);
 }
 
 // ------------------------------------------------------------------ launch templates

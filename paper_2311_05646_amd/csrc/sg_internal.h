@@ -9,8 +9,8 @@
 namespace sg {
 
 constexpr int kMaxComp = 3;
-constexpr int kMaxGroups = 4;
 constexpr int kMaxClasses = 8;
+constexpr int kMaxNodes = 6;       // op-tree nodes of the general composition program
 constexpr int kBlock = 256;        // threads (= in-plane samples) per block
 // copies of the gradient that blocks spread their FP64 atomics over when a
 // parameter is shared by many blocks (one address taking an atomic from every
@@ -36,22 +36,17 @@ enum Mode { MODE_EPS = 0, MODE_VJP_FIELDS = 1, MODE_VJP_GEPS = 2, MODE_FD = 3, M
 // common code, or kCodeGeneral when they differ.
 constexpr uint32_t kCodeGeneral = 1u << 16;
 constexpr int kGroup = 4;    // the stage kernel and the stream kernel's group paths assume 4
-enum RootOp { ROOT_NONE = -1 };    // else SG_OP_*
 // kernel feature variants (primitive types x in-plane sigma kinds), smallest first
 enum Variant { VAR_BOX_LIN = 0, VAR_GCART_LIN = 1, VAR_ELL_SIGMOID = 2, VAR_POLAR_SIGMOID = 3, VAR_SERIES_LIN = 4,
                VAR_ALL = 5 };
 // op-tree layouts compiled into the column kernel: one union over 1 or 2
 // extrusion classes; the difference of two unions over (1, 1) or (1, 2)
-// classes; anything else through the generic composition (4 or 8 classes).
+// classes; any other tree through the general composition program (4 or 8
+// classes, at most kMaxNodes nodes).
 enum Tree { TR_U1 = 0, TR_U2 = 1, TR_D11 = 2, TR_D12 = 3, TR_GEN4 = 4, TR_GEN8 = 5 };
 __host__ __device__ constexpr int tree_nc(int tr) {
     return tr == TR_U1 ? 1 : tr == TR_U2 ? 2 : tr == TR_D11 ? 2 : tr == TR_D12 ? 3 : tr == TR_GEN4 ? 4 : 8;
 }
-// group of class c in the fixed layouts (-1: decided at run time)
-__host__ __device__ constexpr int tree_group(int tr, int c) {
-    return (tr == TR_U1 || tr == TR_U2) ? 0 : (tr == TR_D11 || tr == TR_D12) ? (c == 0 ? 0 : 1) : -1;
-}
-
 // One primitive as the column kernel sees it.  The kernel works in (u, v, w)
 // sample coordinates: u = x (lanes, contiguous in memory), v = the other
 // in-plane axis and w = the column axis each thread walks.  Everything a
@@ -97,10 +92,11 @@ struct PrimRec {
     int32_t pad[2];
 };
 
-// An extrusion class: primitives of one group that share the same factor
-// along the column axis (a Rect1D in w, or 1).
+// An extrusion class: primitives that are children of one op-tree node, with
+// the same sign there (a difference's subtrahend enters its sum negated), and
+// share the same factor along the column axis (a Rect1D in w, or 1).
 struct DevClass {
-    int32_t group;
+    int32_t node;
     int32_t bounded;
     int32_t flo, fhi;      // fields of the w bounds
     int32_t skind, smode;
@@ -137,13 +133,21 @@ struct KParams {
     int32_t tu, tv, tiles_u, tiles_v;        // in-plane tiles of the column kernel's blocks
     int32_t nseg, seglen;                    // column segments (seglen a multiple of kGroup)
     int32_t nprim, nclass;
-    int32_t cls_group[kMaxClasses];
     int32_t cls_wparam[kMaxClasses];
-    int32_t ngroup, root_op;
-    int32_t group_op[kMaxGroups];
-    double group_nm1[kMaxGroups];
-    double group_q[kMaxGroups];  // SG_OP_LEVELS root: eps^{g-1} / eps^g (g >= 1)
-    double root_nm1;
+    // general composition program (TR_GEN*): nodes in postfix order, the root
+    // last.  Node k sums sign_c F_c Z_c over its classes and sign_j v_j over
+    // its child nodes, and applies its op: union min{1, S}, intersection
+    // max{N - 1, S} - (N - 1), difference max{0, S}; a levels root chains its
+    // child nodes in level order (Alg. cap).
+    int32_t nnode, nlev;
+    int32_t node_op[kMaxNodes];
+    int32_t node_parent[kMaxNodes];        // -1 for the root
+    int32_t cls_node[kMaxClasses];
+    int32_t lev_node[kMaxNodes];           // levels root: the child node of each level
+    double node_sign[kMaxNodes];           // +1, or -1 for a difference's subtrahend
+    double node_nm1[kMaxNodes];            // intersection: number of children - 1
+    double cls_sign[kMaxClasses];
+    double lev_q[kMaxNodes];               // levels root: eps^{g-1} / eps^g (g >= 1)
     double eps_bg, deps;
     const double* uc[kMaxComp];
     const double* uw[kMaxComp];
@@ -170,7 +174,7 @@ struct KParams {
     const float2* ef[kMaxComp];
     const float2* ea[kMaxComp];
     float two_omega;
-    int32_t pad;
+    int32_t block0;              // k_column_batch: the request's first block in this launch (a slice of its blocks)
     const float* geps;
     double* grad;
     unsigned long long* nread;   // MODE_VJP_SPARSE: (sample, step) pairs whose fields were read, kReadSlots partial counts
@@ -198,8 +202,8 @@ hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hip
 // plist / first in device memory, blocks = first[nreq]
 hipError_t launch_column_batch(int tree, int variant, const KParams* plist, const int* first, int nreq,
                                int64_t blocks, hipStream_t st);
-// Philox4x32-10 N(0,1) complex64 planes (see shapegrad.h: sg_fieldgen)
-hipError_t launch_fieldgen(float2* e, float2* a, int64_t n, uint64_t seed, hipStream_t st);
+// Philox4x32-10 N(0,1) complex64 planes (see shapegrad.h: sg_fieldgen), elements [i0, i1)
+hipError_t launch_fieldgen(float2* e, float2* a, int64_t i0, int64_t i1, uint64_t seed, hipStream_t st);
 hipError_t launch_gplane(const float2* const* ef, const float2* const* ea, int ncomp, int64_t plane,
                          float two_omega, float* g, hipStream_t st);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, double* out, hipStream_t st);

@@ -278,10 +278,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // Element i of E and Eadj: Philox of counter (i_lo, i_hi, 0, 0) under key
 // (seed_lo, seed_hi); u_k = (x_k + 1/2) 2^-32; two Box-Muller pairs give
 // (Re E, Im E) from (u0, u1) and (Re Eadj, Im Eadj) from (u2, u3).
-__global__ __launch_bounds__(256) void k_fieldgen(float2* __restrict__ e, float2* __restrict__ a, int64_t n,
-                                                  uint32_t k0, uint32_t k1) {
+// Elements [i0, i1) only (a served request draws its planes in slices).
+__global__ __launch_bounds__(256) void k_fieldgen(float2* __restrict__ e, float2* __restrict__ a, int64_t i0,
+                                                  int64_t i1, uint32_t k0, uint32_t k1) {
     const float scale = 2.3283064365386963e-10f;   // 2^-32
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < i1; i += (int64_t)gridDim.x * blockDim.x) {
         const uint4 x = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u), k0, k1);
         const float u0 = ((float)x.x + 0.5f) * scale, u1 = ((float)x.y + 0.5f) * scale;
         const float u2 = ((float)x.z + 0.5f) * scale, u3 = ((float)x.w + 0.5f) * scale;
@@ -380,9 +381,9 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double scale, d
     return hipGetLastError();
 }
 
-hipError_t launch_fieldgen(float2* e, float2* a, int64_t n, uint64_t seed, hipStream_t st) {
-    const int64_t blocks = std::min<int64_t>(8192, (n + 255) / 256);
-    hipLaunchKernelGGL(k_fieldgen, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, e, a, n,
+hipError_t launch_fieldgen(float2* e, float2* a, int64_t i0, int64_t i1, uint64_t seed, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>(8192, (i1 - i0 + 255) / 256);
+    hipLaunchKernelGGL(k_fieldgen, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, e, a, i0, i1,
                        (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();
 }

@@ -38,12 +38,16 @@ struct sg_scene {
     int64_t sv = 0, sw = 0, plane = 0;
     int nprim = 0, nclass = 0, ncls_pad = 1;
     int variant = sg::VAR_ALL;
-    double group_q[sg::kMaxGroups] = {1.0, 1.0, 1.0, 1.0};   // levels root: eps^{g-1} / eps^g
     int tree = sg::TR_GEN8;
-    int ngroup = 0, root_op = sg::ROOT_NONE;
-    int group_op[sg::kMaxGroups] = {0, 0, 0, 0};
-    double group_nm1[sg::kMaxGroups] = {0, 0, 0, 0};
-    double root_nm1 = 0;
+    // the general composition program (see KParams)
+    int nnode = 0, nlev = 0;
+    int node_op[sg::kMaxNodes] = {};
+    int node_parent[sg::kMaxNodes] = {};
+    int lev_node[sg::kMaxNodes] = {};
+    double node_sign[sg::kMaxNodes] = {};
+    double node_nm1[sg::kMaxNodes] = {};
+    double lev_q[sg::kMaxNodes] = {};
+    std::vector<double> cls_sign;
     std::vector<sg::DevClass> classes;
     std::vector<sg_field> fields;
     int block_x = 0, nseg = 0;        // 0: automatic

@@ -3,19 +3,26 @@
 //
 // One scheduler thread owns all device work.  Each turn it
 //   1. admits queued requests in arrival order while a request slot is free and
-//      the request's device bytes fit the remaining HBM budget (a request that
-//      does not fit waits at the head of the queue);
+//      the request's buffers fit the HBM budget (a request that does not fit
+//      waits at the head of the queue);
 //   2. polls the events of the batches in flight and completes their requests;
-//   3. when a stream is free, forms a batch of up to max_batch admitted
-//      requests and enqueues it on that stream: p upload, Philox fields, stage
-//      and one batched column-kernel launch per kernel specialization, then the
-//      gradient copies and an event.
+//   3. when a stream is free, forms a batch of admitted requests and enqueues
+//      it on that stream: per request its p upload and stage (first slice
+//      only), slices of its seeded field generation, one batched column-kernel
+//      launch per kernel specialization covering slices of the requests'
+//      blocks, and for requests whose last slice it holds the gradient copy;
+//      then an event.
+// With max_launch_us set, a batch takes work only up to that many estimated
+// microseconds: a large request is split into slices over several batches of
+// the same stream (so its stage, field generation and column blocks stay in
+// stream order), and requests that arrive meanwhile are batched beside its
+// later slices or run on the other streams instead of waiting for all of it.
 // Clients never touch the device: serve_submit queues, serve_poll waits on a
 // condition variable for the scheduler to publish the result.
 #include <algorithm>
 #include <atomic>
-#include <cmath>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -35,6 +42,11 @@ using namespace sg;
 
 namespace {
 
+// cost model of a batch's device work: HBM bytes moved at 4.5 TB/s
+constexpr double kBytesPerUs = 4.5e6;
+constexpr int64_t kGenSlice = 1 << 16;      // field generation is sliced in multiples of this many samples
+constexpr int64_t kFakeBlocks = 1000;       // fake-executor requests: work units of a request
+
 int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
@@ -42,8 +54,10 @@ int64_t now_ns() {
 
 enum ReqState { PENDING, ADMITTED, LAUNCHED, DONE, CANCELLED, FAILED };
 
+struct Session;
+
 struct Buf {                 // device buffers of one admitted request
-    float2* e = nullptr;
+    float2* e = nullptr;     // seeded field planes (allocated when a seeded request first needs them)
     float2* a = nullptr;
     double* p = nullptr;
     double* fval = nullptr;
@@ -56,15 +70,17 @@ struct Buf {                 // device buffers of one admitted request
     unsigned long long* fx = nullptr;   // deterministic sessions: fixed-point accumulators
     double* h_p = nullptr;   // pinned
     double* h_grad = nullptr;
+    bool fields = false;     // holds field planes (fake buffers: counted only)
     int64_t bytes = 0;       // counted against the budget while the buffer exists
-    struct Session* owner = nullptr;
+    Session* owner = nullptr;
 };
 
 struct Session {
     uint32_t id = 0;
     sg_scene* scene = nullptr;      // null for fake sessions
     int64_t n_params = 0;
-    int64_t req_bytes = 0;
+    int64_t stage_bytes = 0;        // staging, gradient and accumulators of one request
+    int64_t field_bytes = 0;        // the seeded field planes of one request
     bool det = false;               // the scene's deterministic setting when the session opened
     std::vector<Buf*> free_bufs;    // idle buffers kept for the session's next requests
     std::vector<Buf*> all_bufs;
@@ -75,18 +91,35 @@ struct Req {
     Session* s = nullptr;
     std::vector<double> p, grad;
     uint64_t seed = 0;
+    bool caller = false;            // fields from the caller's planes (ce, ca)
+    const float2* ce[kMaxComp] = {};
+    const float2* ca[kMaxComp] = {};
     double omega = 0;
     int state = PENDING;
     bool cancel = false;
     sg_status status = SG_OK;
     Buf* buf = nullptr;
+    int64_t need = 0;               // bytes of its buffer this request uses
     sg_req_stats st{};
+    // progress through sliced launches
+    int64_t gen_n = 0, gen_done = 0;        // seeded field samples
+    int64_t blocks = 0, blocks_done = 0;    // column-kernel blocks
+    double block_bytes = 0.0;               // estimated HBM bytes per block
+    bool staged = false;
+    int lane = -1;                  // the stream its slices run on once one has been launched
+};
+
+struct Slice {                     // one request's share of a batch
+    Req* r;
+    int64_t g0, g1;                 // field samples generated
+    int64_t b0, b1;                 // column blocks
+    bool first, last;
 };
 
 struct Lane {                      // one stream and the batch in flight on it
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    std::vector<Req*> batch;
+    std::vector<Slice> batch;
     bool busy = false;
     bool failed = false;
     int64_t fake_ready_ns = 0;
@@ -107,7 +140,7 @@ struct sg_server {
     bool stop = false;
     std::vector<std::unique_ptr<Session>> sessions;
     std::deque<Req*> pending;
-    std::deque<Req*> ready;
+    std::deque<Req*> ready;         // admitted, with slices left to launch
     std::unordered_map<uint64_t, Req*> reqs;
     uint64_t next_ticket = 1;
     int64_t bytes_used = 0;         // bytes of the requests admitted and not yet finished
@@ -145,12 +178,9 @@ void free_buf(Buf* b, bool fake) {
     delete b;
 }
 
-bool alloc_buf(sg_scene* sc, bool det, Buf* b) {
+bool alloc_staging(sg_scene* sc, bool det, Buf* b) {
     const int64_t nfield = std::max<int64_t>(1, sc->nfield), n = std::max<int64_t>(1, sc->n_params);
-    const int64_t cm = (int64_t)sc->ncomp * sc->plane;
-    hipError_t e = hipMalloc((void**)&b->e, cm * sizeof(float2));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->a, cm * sizeof(float2));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->p, n * sizeof(double));
+    hipError_t e = hipMalloc((void**)&b->p, n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b->fval, nfield * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&b->bbox, std::max(1, sc->nprim) * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc((void**)&b->prec, std::max(1, sc->nprim) * sizeof(PrimRec));
@@ -162,6 +192,18 @@ bool alloc_buf(sg_scene* sc, bool det, Buf* b) {
     if (e == hipSuccess && det) e = hipMalloc((void**)&b->fx, (3 * n + 1) * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_p, n * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_grad, n * sizeof(double));
+    return e == hipSuccess;
+}
+
+bool alloc_fields(sg_scene* sc, Buf* b) {
+    const int64_t cm = (int64_t)sc->ncomp * sc->plane;
+    hipError_t e = hipMalloc((void**)&b->e, cm * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->a, cm * sizeof(float2));
+    if (e != hipSuccess) {
+        hipFree(b->e);
+        hipFree(b->a);
+        b->e = b->a = nullptr;
+    }
     return e == hipSuccess;
 }
 
@@ -177,7 +219,7 @@ void release(sg_server* v, Req* r) {
         v->idle.push_back(r->buf);
         r->buf = nullptr;
     }
-    v->bytes_used -= r->s->req_bytes;
+    v->bytes_used -= r->need;
     v->slots_used -= 1;
 }
 
@@ -191,20 +233,52 @@ void drop_idle(sg_server* v, Buf* b) {
     free_buf(b, v->opts.fake_executor != 0);
 }
 
-// A new request buffer for session s, or nullptr when the device is out of
-// memory (or an injected allocation failure).
-Buf* new_buf(sg_server* v, Session* s) {
+// The least recently released idle buffer other than `keep`, or null.
+Buf* oldest_idle(sg_server* v, const Buf* keep) {
+    for (Buf* b : v->idle)
+        if (b != keep) return b;
+    return nullptr;
+}
+
+// Frees least recently released idle buffers (never `keep`) until `extra`
+// more bytes fit the budget; true if they fit.
+bool make_room(sg_server* v, int64_t extra, const Buf* keep) {
+    while (v->bytes_held + extra > v->opts.hbm_budget_bytes) {
+        Buf* b = oldest_idle(v, keep);
+        if (!b) return false;
+        drop_idle(v, b);
+    }
+    return true;
+}
+
+// Gives buffer b (a new one when null) what a request of session s needs:
+// staging, and the field planes for a seeded request.  False when the device
+// is out of memory (or an injected allocation failure); b keeps what it had.
+bool provide(sg_server* v, Session* s, Buf*& b, bool fields) {
     const bool inject = v->fault_alloc >= 0 && v->allocs >= v->fault_alloc;
     v->allocs++;
-    if (inject) return nullptr;
-    Buf* b = new Buf;
-    b->bytes = s->req_bytes;
-    b->owner = s;
-    if (!v->opts.fake_executor && !alloc_buf(s->scene, s->det, b)) {
-        free_buf(b, false);
-        return nullptr;
+    if (inject) return false;
+    const bool fake = v->opts.fake_executor != 0;
+    Buf* nb = b;
+    if (!nb) {
+        nb = new Buf;
+        nb->owner = s;
+        if (!fake && !alloc_staging(s->scene, s->det, nb)) {
+            free_buf(nb, false);
+            return false;
+        }
+        nb->bytes = s->stage_bytes;
     }
-    return b;
+    if (fields && !nb->fields) {
+        if (!fake && !alloc_fields(s->scene, nb)) {
+            if (!b) free_buf(nb, false);
+            return false;
+        }
+        nb->fields = true;
+        nb->bytes += s->field_bytes;
+    }
+    b = nb;
+    return true;
 }
 
 void retire(sg_server* v, Req* r, int state, sg_status status) {
@@ -219,63 +293,90 @@ void retire(sg_server* v, Req* r, int state, sg_status status) {
 // buffers for its next requests, and the least recently released idle
 // buffers of any session are freed when a new buffer would not fit.
 void admit(sg_server* v) {
+    const bool fake = v->opts.fake_executor != 0;
     while (!v->pending.empty()) {
         Req* r = v->pending.front();
         Session* s = r->s;
         if (v->slots_used >= v->opts.max_slots) return;
+        const bool fields = !r->caller;
+        // an idle buffer of the session, preferably one that already has what r needs
         Buf* b = nullptr;
-        if (!s->free_bufs.empty()) {
-            b = s->free_bufs.back();
-            s->free_bufs.pop_back();
+        for (Buf* c : s->free_bufs)
+            if (!b || (fields && c->fields && !b->fields)) b = c;
+        const int64_t extra = !b ? s->stage_bytes + (fields ? s->field_bytes : 0)
+                                 : ((fields && !b->fields) ? s->field_bytes : 0);
+        if (extra > 0) {
+            if (!make_room(v, extra, b)) return;       // busy buffers hold the budget
+            const bool had = b != nullptr;
+            const int64_t before = had ? b->bytes : 0;
+            if (!provide(v, s, b, fields)) {
+                // device memory short: free every other idle buffer and try once more
+                while (Buf* x = oldest_idle(v, b)) drop_idle(v, x);
+                if (!provide(v, s, b, fields)) {
+                    if (v->slots_used > 0) return;     // in-flight requests will free memory
+                    // nothing runs that could free memory: the request cannot be served now
+                    v->pending.pop_front();
+                    retire(v, r, FAILED, SG_E_NOMEM);
+                    continue;
+                }
+            }
+            if (!had) s->all_bufs.push_back(b);
+            v->bytes_held += b->bytes - before;
+        }
+        auto it = std::find(s->free_bufs.begin(), s->free_bufs.end(), b);
+        if (it != s->free_bufs.end()) {
+            s->free_bufs.erase(it);
             v->idle.remove(b);
-        } else {
-            while (v->bytes_held + s->req_bytes > v->opts.hbm_budget_bytes && !v->idle.empty())
-                drop_idle(v, v->idle.front());
-            if (v->bytes_held + s->req_bytes > v->opts.hbm_budget_bytes) return;   // busy buffers hold it
-            b = new_buf(v, s);
-            if (!b) {
-                // device memory short: free every idle buffer and try once more
-                while (!v->idle.empty()) drop_idle(v, v->idle.front());
-                b = new_buf(v, s);
-            }
-            if (!b) {
-                if (v->slots_used > 0) return;     // in-flight requests will free memory
-                // nothing runs that could free memory: the request cannot be served now
-                v->pending.pop_front();
-                retire(v, r, FAILED, SG_E_NOMEM);
-                continue;
-            }
-            s->all_bufs.push_back(b);
-            v->bytes_held += b->bytes;
         }
         r->buf = b;
+        r->need = s->stage_bytes + (fields ? s->field_bytes : 0);
         v->pending.pop_front();
-        v->bytes_used += r->s->req_bytes;
+        v->bytes_used += r->need;
         v->slots_used += 1;
         r->state = ADMITTED;
         r->st.admit_ns = now_ns();
+        // its work: field generation (seeded), then the column blocks
+        if (fake) {
+            r->blocks = kFakeBlocks;
+            r->block_bytes = (double)s->stage_bytes / kFakeBlocks;
+        } else {
+            sg_scene* sc = s->scene;
+            const KParams kp = column_params(sc);
+            r->gen_n = fields ? (int64_t)sc->ncomp * sc->plane : 0;
+            r->blocks = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
+            r->block_bytes = 16.0 * (double)sc->ncomp * (double)sc->plane / (double)std::max<int64_t>(1, r->blocks);
+        }
         v->ready.push_back(r);
     }
 }
 
+void drop_ready(sg_server* v, Req* r) {
+    auto it = std::find(v->ready.begin(), v->ready.end(), r);
+    if (it != v->ready.end()) v->ready.erase(it);
+}
+
 void finish_batch(sg_server* v, Lane& L, bool ok) {
     const int64_t t = now_ns();
-    for (Req* r : L.batch) {
-        if (r->cancel) {
-            r->state = CANCELLED;
-            r->status = SG_E_CANCELLED;
-        } else if (!ok) {
+    for (const Slice& c : L.batch) {
+        Req* r = c.r;
+        if (!ok) {
+            drop_ready(v, r);
             r->state = FAILED;
             r->status = SG_E_DEVICE;
-        } else {
-            if (v->opts.fake_executor) {
-                fake_result(r);
+        } else if (c.last || r->cancel) {
+            drop_ready(v, r);
+            if (r->cancel) {
+                r->state = CANCELLED;
+                r->status = SG_E_CANCELLED;
             } else {
-                r->grad.assign(r->buf->h_grad, r->buf->h_grad + r->s->n_params);
+                if (v->opts.fake_executor) fake_result(r);
+                else r->grad.assign(r->buf->h_grad, r->buf->h_grad + r->s->n_params);
+                r->state = DONE;
+                r->status = SG_OK;
+                v->completed++;
             }
-            r->state = DONE;
-            r->status = SG_OK;
-            v->completed++;
+        } else {
+            continue;       // more slices to come, on this lane
         }
         r->st.done_ns = t;
         release(v, r);
@@ -285,21 +386,91 @@ void finish_batch(sg_server* v, Lane& L, bool ok) {
     L.failed = false;
 }
 
-// Enqueue one batch on lane L (device work only; called with the lock held).
-bool launch_batch(sg_server* v, Lane& L) {
-    const int64_t t = now_ns();
-    const int nb = (int)L.batch.size();
-    for (Req* r : L.batch) {
-        r->state = LAUNCHED;
-        r->st.launch_ns = t;
-        r->st.batch_size = nb;
+// Takes work from the ready requests into lane li's batch, up to max_batch
+// requests and (with max_launch_us) that many estimated microseconds: first
+// every request, in arrival order, whose remaining work fits whole; then a
+// slice of the oldest one that did not fit (at least a quarter of the budget,
+// so a large request progresses while small ones keep arriving).  A sliced
+// request stays at its place in the queue, tied to this lane.  Returns the
+// number of slices.
+int form_batch(sg_server* v, int li) {
+    Lane& L = v->lanes[li];
+    const double budget = v->opts.max_launch_us > 0 ? (double)v->opts.max_launch_us * kBytesPerUs
+                                                    : std::numeric_limits<double>::infinity();
+    double used = 0.0;
+    std::vector<Req*> cancelled;
+    Req* big = nullptr;
+    auto remaining = [](const Req* r) {
+        return 16.0 * (double)(r->gen_n - r->gen_done) + r->block_bytes * (double)(r->blocks - r->blocks_done);
+    };
+    for (Req* r : v->ready) {
+        if (r->lane >= 0 && r->lane != li) continue;      // its slices run on another stream
+        if (r->cancel && r->lane >= 0) {                  // sliced, cancelled, nothing of it in flight
+            cancelled.push_back(r);
+            continue;
+        }
+        if ((int)L.batch.size() + (big ? 1 : 0) >= v->opts.max_batch) break;
+        const double need = remaining(r);
+        if (need <= budget - used) {
+            L.batch.push_back(Slice{r, r->gen_done, r->gen_n, r->blocks_done, r->blocks, !r->staged, true});
+            used += need;
+        } else if (!big) {
+            big = r;
+        }
     }
-    v->max_batch_seen = std::max<int64_t>(v->max_batch_seen, nb);
+    if (big && (int)L.batch.size() < v->opts.max_batch) {
+        Req* r = big;
+        double room = std::max(budget - used, 0.25 * budget);
+        Slice c{r, r->gen_done, r->gen_done, r->blocks_done, r->blocks_done, !r->staged, false};
+        const int64_t grem = r->gen_n - r->gen_done, brem = r->blocks - r->blocks_done;
+        int64_t g = 0, b = 0;
+        if (grem > 0) {
+            g = std::min(grem, std::max<int64_t>(kGenSlice, (int64_t)(room / 16.0) / kGenSlice * kGenSlice));
+            room -= 16.0 * (double)g;
+        }
+        if (g == grem && room > 0.0)
+            b = std::min<int64_t>(brem, (int64_t)(room / std::max(1.0, r->block_bytes)));
+        if (g == 0 && b == 0) b = 1;                     // every slice makes progress
+        c.g1 = c.g0 + g;
+        c.b1 = c.b0 + b;
+        c.last = c.g1 == r->gen_n && c.b1 == r->blocks;
+        L.batch.push_back(c);
+    }
+    for (Req* r : cancelled) {
+        drop_ready(v, r);
+        retire(v, r, CANCELLED, SG_E_CANCELLED);
+        release(v, r);
+    }
+    return (int)L.batch.size();
+}
+
+double slice_us(const Slice& c) {
+    return (16.0 * (double)(c.g1 - c.g0) + c.r->block_bytes * (double)(c.b1 - c.b0)) / kBytesPerUs;
+}
+
+// Enqueue lane li's batch (device work only; called with the lock held).
+bool launch_batch(sg_server* v, Lane& L, int li) {
+    const int64_t t = now_ns();
+    for (Slice& c : L.batch) {
+        Req* r = c.r;
+        if (c.first) {
+            r->state = LAUNCHED;
+            r->st.launch_ns = t;
+            r->st.batch_size = (int32_t)L.batch.size();
+            r->lane = li;
+        }
+        r->gen_done = c.g1;
+        r->blocks_done = c.b1;
+    }
+    v->max_batch_seen = std::max<int64_t>(v->max_batch_seen, (int64_t)L.batch.size());
     const bool inject = (v->launches == v->fault_launch);
     v->launches++;
     if (v->opts.fake_executor) {
-        L.fake_ready_ns = t + v->opts.fake_us * 1000;
+        double us = (double)v->opts.fake_us;
+        for (const Slice& c : L.batch) us += slice_us(c);
+        L.fake_ready_ns = t + (int64_t)(us * 1000.0);
         L.failed = inject;
+        for (Slice& c : L.batch) c.r->staged = true;
         return true;
     }
     if (inject) {
@@ -307,44 +478,54 @@ bool launch_batch(sg_server* v, Lane& L) {
         return true;
     }
     hipStream_t st = L.stream;
-    // per request: p, fields, stage (resolved fields, support boxes, extrusion tables, zeroed gradient)
-    for (Req* r : L.batch) {
+    // per request: p and stage (first slice), field generation slices
+    for (Slice& c : L.batch) {
+        Req* r = c.r;
         sg_scene* sc = r->s->scene;
         Buf* b = r->buf;
-        std::memcpy(b->h_p, r->p.data(), r->s->n_params * sizeof(double));
-        if (r->s->n_params && hipMemcpyAsync(b->p, b->h_p, r->s->n_params * sizeof(double), hipMemcpyHostToDevice, st))
-            return false;
-        if (launch_fieldgen(b->e, b->a, (int64_t)sc->ncomp * sc->plane, r->seed, st) != hipSuccess) return false;
-        StageParams sp = stage_params(sc, b->p);
-        sp.fval[0] = b->fval;
-        sp.bbox[0] = b->bbox;
-        sp.prec[0] = b->prec;
-        if (!sc->static_w) {
-            sp.ztab[0] = b->ztab;
-            sp.code[0] = b->code;
-            sp.gcode[0] = b->gcode;
+        if (c.first) {
+            std::memcpy(b->h_p, r->p.data(), r->s->n_params * sizeof(double));
+            if (r->s->n_params &&
+                hipMemcpyAsync(b->p, b->h_p, r->s->n_params * sizeof(double), hipMemcpyHostToDevice, st))
+                return false;
+            StageParams sp = stage_params(sc, b->p);
+            sp.fval[0] = b->fval;
+            sp.bbox[0] = b->bbox;
+            sp.prec[0] = b->prec;
+            if (!sc->static_w) {
+                sp.ztab[0] = b->ztab;
+                sp.code[0] = b->code;
+                sp.gcode[0] = b->gcode;
+            }
+            sp.zero_ptr = b->grad;
+            sp.zero_n = sc->n_params;
+            if (launch_stage(sp, 1, st) != hipSuccess) return false;
+            if (r->s->det && sc->n_params > 0 &&
+                launch_fill(reinterpret_cast<double*>(b->fx), 0.0, 3 * sc->n_params + 1, st) != hipSuccess)
+                return false;
+            r->staged = true;
         }
-        sp.zero_ptr = b->grad;
-        sp.zero_n = sc->n_params;
-        if (launch_stage(sp, 1, st) != hipSuccess) return false;
-        if (r->s->det && sc->n_params > 0 &&
-            launch_fill(reinterpret_cast<double*>(b->fx), 0.0, 3 * sc->n_params + 1, st) != hipSuccess)
-            return false;
+        if (c.g1 > c.g0 && launch_fieldgen(b->e, b->a, c.g0, c.g1, r->seed, st) != hipSuccess) return false;
     }
-    // one batched launch per kernel specialization; a group of g requests uses
-    // h_plist[g0, g0 + g) and the prefix h_first[g0, g0 + g] (terminated by its total)
-    std::vector<bool> done(nb, false);
+    // one batched column launch per kernel specialization over the slices'
+    // blocks; a group of g slices uses h_plist[g0, g0 + g) and the prefix
+    // h_first[g0, g0 + g] (terminated by its total)
+    const int nb = (int)L.batch.size();
+    std::vector<bool> grouped(nb, false);
     int slot = 0;
     for (int i = 0; i < nb; ++i) {
-        if (done[i]) continue;
-        const int tree = L.batch[i]->s->scene->tree, var = L.batch[i]->s->scene->variant;
+        if (grouped[i] || L.batch[i].b1 == L.batch[i].b0) continue;
+        const int tree = L.batch[i].r->s->scene->tree, var = L.batch[i].r->s->scene->variant;
         const int g0 = slot;
-        int ng = 0, blocks = 0;
+        int ng = 0;
+        int64_t blocks = 0;
         for (int j = i; j < nb; ++j) {
-            sg_scene* sc = L.batch[j]->s->scene;
-            if (done[j] || sc->tree != tree || sc->variant != var) continue;
-            done[j] = true;
-            Buf* b = L.batch[j]->buf;
+            const Slice& c = L.batch[j];
+            sg_scene* sc = c.r->s->scene;
+            if (grouped[j] || c.b1 == c.b0 || sc->tree != tree || sc->variant != var) continue;
+            grouped[j] = true;
+            Req* r = c.r;
+            Buf* b = r->buf;
             KParams kp = column_params(sc);
             kp.fval = b->fval;
             kp.bbox = b->bbox;
@@ -355,29 +536,32 @@ bool launch_batch(sg_server* v, Lane& L) {
                 kp.gcode = b->gcode;
             }
             kp.grad = b->grad;
-            if (L.batch[j]->s->det && sc->n_params > 0) {
+            if (r->s->det && sc->n_params > 0) {
                 kp.fx = b->fx;
                 kp.fx_n = sc->n_params;
             }
-            for (int c = 0; c < kMaxComp; ++c) {
-                const int cc = std::min(c, sc->ncomp - 1);
-                kp.ef[c] = b->e + (int64_t)cc * sc->plane;
-                kp.ea[c] = b->a + (int64_t)cc * sc->plane;
+            for (int cc = 0; cc < kMaxComp; ++cc) {
+                const int k = std::min(cc, sc->ncomp - 1);
+                kp.ef[cc] = r->caller ? r->ce[k] : b->e + (int64_t)k * sc->plane;
+                kp.ea[cc] = r->caller ? r->ca[k] : b->a + (int64_t)k * sc->plane;
             }
-            kp.two_omega = (float)(2.0 * L.batch[j]->omega);
+            kp.two_omega = (float)(2.0 * r->omega);
+            kp.block0 = (int32_t)c.b0;
             L.h_plist[g0 + ng] = kp;
-            L.h_first[g0 + ng] = blocks;
-            blocks += kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
+            L.h_first[g0 + ng] = (int)blocks;
+            blocks += c.b1 - c.b0;
             ++ng;
         }
-        L.h_first[g0 + ng] = blocks;
+        L.h_first[g0 + ng] = (int)blocks;
         if (hipMemcpyAsync(L.d_plist + g0, L.h_plist + g0, ng * sizeof(KParams), hipMemcpyHostToDevice, st)) return false;
         if (hipMemcpyAsync(L.d_first + g0, L.h_first + g0, (ng + 1) * sizeof(int), hipMemcpyHostToDevice, st))
             return false;
         if (launch_column_batch(tree, var, L.d_plist + g0, L.d_first + g0, ng, blocks, st) != hipSuccess) return false;
         slot = g0 + ng + 1;
     }
-    for (Req* r : L.batch) {
+    for (const Slice& c : L.batch) {
+        if (!c.last) continue;
+        Req* r = c.r;
         if (r->s->det && r->s->n_params > 0 &&
             launch_fx_finish(r->buf->fx, r->s->n_params, r->buf->grad, st) != hipSuccess)
             return false;
@@ -402,7 +586,7 @@ void scheduler(sg_server* v) {
                 fin = now_ns() >= L.fake_ready_ns;
                 ok = !L.failed;
             } else if (L.failed) {
-                // an injected failure: wait for whatever reached the stream, then fail the batch
+                // a failed launch: wait for whatever reached the stream, then fail the batch
                 fin = hipStreamQuery(L.stream) != hipErrorNotReady;
                 ok = false;
             } else {
@@ -420,17 +604,14 @@ void scheduler(sg_server* v) {
         admit(v);
         // launches
         for (int k = 0; k < (int)v->lanes.size() && !v->ready.empty(); ++k) {
-            Lane& L = v->lanes[(v->next_lane + k) % v->lanes.size()];
+            const int li = (v->next_lane + k) % (int)v->lanes.size();
+            Lane& L = v->lanes[li];
             if (L.busy) continue;
-            while (!v->ready.empty() && (int)L.batch.size() < v->opts.max_batch) {
-                Req* r = v->ready.front();
-                v->ready.pop_front();
-                L.batch.push_back(r);
-            }
+            if (form_batch(v, li) == 0) continue;
             L.busy = true;
-            if (!launch_batch(v, L)) L.failed = true;
+            if (!launch_batch(v, L, li)) L.failed = true;
             any_busy = true;
-            v->next_lane = (v->next_lane + k + 1) % v->lanes.size();
+            v->next_lane = (li + 1) % (int)v->lanes.size();
         }
         if (v->stop && v->pending.empty() && v->ready.empty() && !any_busy) break;
         if (any_busy) {
@@ -450,7 +631,7 @@ void scheduler(sg_server* v) {
 extern "C" sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* stream) {
     if (!e_fwd || !e_adj || n < 0) return fail(SG_E_INVALID, "sg_fieldgen: bad arguments");
     if (n == 0) return SG_OK;
-    HIP_OK(launch_fieldgen((float2*)e_fwd, (float2*)e_adj, n, seed, (hipStream_t)stream));
+    HIP_OK(launch_fieldgen((float2*)e_fwd, (float2*)e_adj, 0, n, seed, (hipStream_t)stream));
     return SG_OK;
 }
 
@@ -463,18 +644,18 @@ extern "C" sg_status sg_server_create(sg_ctx* ctx, const sg_server_opts* o, sg_s
         budget = int64_t(8) << 30;
         if (const char* b = std::getenv("SG_HBM_BUDGET")) {
             char* end = nullptr;
-            const long long v = std::strtoll(b, &end, 10);
+            const long long val = std::strtoll(b, &end, 10);
             int shift = 0;
             if (end && (*end == 'K' || *end == 'k')) shift = 10, ++end;
             else if (end && (*end == 'M' || *end == 'm')) shift = 20, ++end;
             else if (end && (*end == 'G' || *end == 'g')) shift = 30, ++end;
-            if (end == b || !end || *end != '\0' || v <= 0 || v > (std::numeric_limits<int64_t>::max() >> shift))
+            if (end == b || !end || *end != '\0' || val <= 0 || val > (std::numeric_limits<int64_t>::max() >> shift))
                 return fail(SG_E_INVALID, "sg_server_create: SG_HBM_BUDGET=\"%s\" is not a positive size", b);
-            budget = (int64_t)v << shift;
+            budget = (int64_t)val << shift;
         }
     }
     if (budget <= 0 || o->max_slots < 1 || o->max_batch < 1 || o->n_streams < 1 || o->n_streams > 8 ||
-        o->fake_us < 0)
+        o->fake_us < 0 || o->max_launch_us < 0)
         return fail(SG_E_INVALID, "sg_server_create: bad options");
     auto* v = new sg_server;
     v->ctx = ctx;
@@ -516,12 +697,20 @@ extern "C" sg_status sg_server_destroy(sg_server* v) {
             r->status = SG_E_CANCELLED;
         }
         v->pending.clear();
+        // requests with nothing launched are cancelled; sliced ones finish
+        // the slices in flight and are cancelled by the scheduler
+        std::deque<Req*> keep;
         for (Req* r : v->ready) {
+            if (r->lane >= 0) {
+                r->cancel = true;
+                keep.push_back(r);
+                continue;
+            }
             r->state = CANCELLED;
             r->status = SG_E_CANCELLED;
             release(v, r);
         }
-        v->ready.clear();
+        v->ready.swap(keep);
     }
     v->cv_work.notify_all();
     if (v->th.joinable()) v->th.join();
@@ -544,13 +733,15 @@ extern "C" sg_status sg_server_destroy(sg_server* v) {
     return SG_OK;
 }
 
-static sg_status open_session(sg_server* v, sg_scene* sc, int64_t n_params, int64_t bytes, bool det, uint32_t* id) {
+static sg_status open_session(sg_server* v, sg_scene* sc, int64_t n_params, int64_t stage_bytes,
+                              int64_t field_bytes, bool det, uint32_t* id) {
     std::lock_guard<std::mutex> lk(v->mu);
     auto s = std::make_unique<Session>();
     s->id = (uint32_t)v->sessions.size();
     s->scene = sc;
     s->n_params = n_params;
-    s->req_bytes = bytes;
+    s->stage_bytes = stage_bytes;
+    s->field_bytes = field_bytes;
     s->det = det;
     *id = s->id;
     v->sessions.push_back(std::move(s));
@@ -566,21 +757,21 @@ extern "C" sg_status serve_open_session(sg_server* v, sg_scene* sc, uint32_t* id
         std::lock_guard<std::mutex> lk(sc->mu);
         det = sc->deterministic;
     }
-    const int64_t bytes = 16 * (int64_t)sc->ncomp * sc->plane + staging_bytes(sc) +
-                          (det ? 8 * (3 * std::max<int64_t>(1, sc->n_params) + 1) : 0);
-    return open_session(v, sc, sc->n_params, bytes, det, id);
+    const int64_t stage = staging_bytes(sc) + (det ? 8 * (3 * std::max<int64_t>(1, sc->n_params) + 1) : 0);
+    return open_session(v, sc, sc->n_params, stage, 16 * (int64_t)sc->ncomp * sc->plane, det, id);
 }
 
 extern "C" sg_status serve_open_fake_session(sg_server* v, int64_t n_params, int64_t bytes, uint32_t* id) {
     if (!v || !id) return fail(SG_E_INVALID, "serve_open_fake_session: NULL argument");
     if (!v->opts.fake_executor) return fail(SG_E_INVALID, "only fake-executor servers take fake sessions");
     if (n_params < 0 || bytes < 0) return fail(SG_E_INVALID, "bad sizes");
-    return open_session(v, nullptr, n_params, bytes, false, id);
+    return open_session(v, nullptr, n_params, bytes, 0, false, id);
 }
 
-extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, uint64_t seed, double omega,
-                                  uint64_t* ticket) {
+static sg_status submit(sg_server* v, uint32_t sid, const double* p, uint64_t seed, const void* const* e_fwd,
+                        const void* const* e_adj, double omega, uint64_t* ticket) {
     if (!v || !ticket) return fail(SG_E_INVALID, "serve_submit: NULL argument");
+    const bool caller = e_fwd != nullptr || e_adj != nullptr;
     Req* r;
     {
         std::lock_guard<std::mutex> lk(v->mu);
@@ -590,8 +781,15 @@ extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, u
         for (int64_t k = 0; k < s->n_params; ++k)
             if (!std::isfinite(p[k])) return fail(SG_E_INVALID, "serve_submit: p[%lld] not finite", (long long)k);
         if (!std::isfinite(omega)) return fail(SG_E_INVALID, "serve_submit: omega not finite");
-        if (s->req_bytes > v->opts.hbm_budget_bytes)
-            return fail(SG_E_TOO_LARGE, "request needs %lld bytes, budget is %lld", (long long)s->req_bytes,
+        if (caller) {
+            if (!s->scene) return fail(SG_E_INVALID, "serve_submit_fields: a fake session has no planes");
+            if (!e_fwd || !e_adj) return fail(SG_E_INVALID, "serve_submit_fields: field pointer arrays are NULL");
+            for (int c = 0; c < s->scene->ncomp; ++c)
+                if (!e_fwd[c] || !e_adj[c]) return fail(SG_E_INVALID, "serve_submit_fields: field plane %d is NULL", c);
+        }
+        const int64_t need = s->stage_bytes + (caller ? 0 : s->field_bytes);
+        if (need > v->opts.hbm_budget_bytes)
+            return fail(SG_E_TOO_LARGE, "request needs %lld bytes, budget is %lld", (long long)need,
                         (long long)v->opts.hbm_budget_bytes);
         if (v->stop) return fail(SG_E_INVALID, "server is shutting down");
         r = new Req;
@@ -599,6 +797,12 @@ extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, u
         r->s = s;
         r->p.assign(p, p + s->n_params);
         r->seed = seed;
+        r->caller = caller;
+        if (caller)
+            for (int c = 0; c < s->scene->ncomp; ++c) {
+                r->ce[c] = (const float2*)e_fwd[c];
+                r->ca[c] = (const float2*)e_adj[c];
+            }
         r->omega = omega;
         r->st.submit_ns = now_ns();
         v->reqs[r->ticket] = r;
@@ -607,6 +811,17 @@ extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, u
     }
     v->cv_work.notify_one();
     return SG_OK;
+}
+
+extern "C" sg_status serve_submit(sg_server* v, uint32_t sid, const double* p, uint64_t seed, double omega,
+                                  uint64_t* ticket) {
+    return submit(v, sid, p, seed, nullptr, nullptr, omega, ticket);
+}
+
+extern "C" sg_status serve_submit_fields(sg_server* v, uint32_t sid, const double* p, const void* const* e_fwd,
+                                         const void* const* e_adj, double omega, uint64_t* ticket) {
+    if (!e_fwd || !e_adj) return fail(SG_E_INVALID, "serve_submit_fields: field pointer arrays are NULL");
+    return submit(v, sid, p, 0, e_fwd, e_adj, omega, ticket);
 }
 
 extern "C" sg_status serve_poll(sg_server* v, uint64_t ticket, double* grad_out, int64_t timeout_us,
@@ -649,14 +864,15 @@ extern "C" sg_status serve_cancel(sg_server* v, uint64_t ticket) {
         r->state = CANCELLED;
         r->status = SG_E_CANCELLED;
     } else if (r->state == ADMITTED) {
-        v->ready.erase(std::find(v->ready.begin(), v->ready.end(), r));
+        drop_ready(v, r);
         r->state = CANCELLED;
         r->status = SG_E_CANCELLED;
         release(v, r);
     } else if (r->state == LAUNCHED) {
-        r->cancel = true;
+        r->cancel = true;      // its slices in flight finish; no more are launched
     }
     v->cv_done.notify_all();
+    v->cv_work.notify_one();
     return SG_OK;
 }
 

@@ -258,6 +258,61 @@ def make_c2(seed=BASE_SEED + 1, with_fields=True, **kw):
     return out
 
 
+def blazed_scene(rng, nx=4000, ny=600, n_periods=50, x_start=5.0, period=1.2):
+    """The paper's blazed-grating composition (Sec. "Single-polarization
+    blazed grating coupler in 2D", steps i-vi): substrate union (waveguide
+    minus the union of the full- and shallow-etch scatterers), each etch
+    reaching down from the waveguide top by its own depth.  Parameters: the
+    four x-edges of every period, the two etch depths and the buried-oxide
+    thickness (the substrate's top lies that far below the waveguide)."""
+    X = graded_nodes(raised_cosine_widths(nx, 10.0, 25.0, coarse_at_ends=False))
+    Y = uniform_nodes(ny, 0.01)
+    Z = np.array([0.0, 1.0])
+    yb = Y[ny // 2] - 0.1063                  # waveguide bottom, off the lattice faces
+    yt = yb + 0.22
+    p = []
+    prims = []
+    for q in range(n_periods):
+        xf0 = x_start + period * q + rng.uniform(0.0, 0.05)
+        xf1 = xf0 + rng.uniform(0.10, 0.30)
+        xs0 = xf1 + rng.uniform(0.05, 0.15)
+        xs1 = xs0 + rng.uniform(0.15, 0.40)
+        p += [safe_point(X, v, rng) for v in (xf0, xf1, xs0, xs1)]
+    kd_full, kd_sh, k_box = len(p), len(p) + 1, len(p) + 2
+    # depths and the oxide thickness, each moved off the y lattice's kinks
+    p += [yt - safe_point(Y, yt - 0.15, rng), yt - safe_point(Y, yt - 0.07, rng), yb - safe_point(Y, yb - 0.5, rng)]
+    top = K(yt + 0.0437)                      # the etches open into the cladding above
+    full, shallow = [], []
+    for q in range(n_periods):
+        k = 4 * q
+        full.append(box(x=(P(k), P(k + 1)), y=(P(kd_full, -1.0, yt), top)))
+        shallow.append(box(x=(P(k + 2), P(k + 3)), y=(P(kd_sh, -1.0, yt), top)))
+    substrate = box(y=(K(Y[0] - 1.0), P(k_box, -1.0, yb)))
+    waveguide = box(x=(K(1.0), K(X[-1] - 1.0)), y=(K(yb), K(yt)))
+    prims = [substrate, waveguide] + full + shallow
+    etches = list(range(2, len(prims)))
+    scene = {"name": "blazed", "dim": 2, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "union", "children": [
+                 0, {"op": "difference", "children": [1, {"op": "union", "children": etches}]}]}}
+    return scene, np.array(p)
+
+
+def make_blazed(seed=BASE_SEED + 8, with_fields=True, **kw):
+    """2D blazed grating with the paper's own composition (three op levels,
+    etch depths and the oxide thickness as parameters): 4000x600 by default."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    scene, p = blazed_scene(rng, **kw)
+    out = {"scene": scene, "p": p, "omega": _wl_omega(1.55), "h": 1e-5}
+    if with_fields:
+        out["E"], out["A"] = make_fields(scene, seed)
+    return out
+
+
+def make_blazed_small(seed=BASE_SEED + 18):
+    return make_blazed(seed, nx=300, ny=96, n_periods=3, x_start=1.2, period=1.0)
+
+
 def c3_scene(rng, nx=600, ny=240, nz=100, nvert=96, w_in=0.5, w_out=8.0,
              x_a=1.013, x_b=22.013, y_m=4.807, noise=0.15):
     X = uniform_nodes(nx, 0.04)
@@ -613,6 +668,12 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     elif root == "difference":
         tree = {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3, 4, 6, 7]},
                                                  {"op": "union", "children": [1, 5]}]}
+    elif root == "deep":
+        # six op nodes, three levels below the root, differences on both sides
+        tree = {"op": "union", "children": [
+            {"op": "difference", "children": [{"op": "union", "children": [0, 2, 3]},
+                                              {"op": "intersection", "children": [4, 5]}]},
+            {"op": "difference", "children": [6, {"op": "union", "children": [1, 7]}]}]}
     else:
         tree = {"op": "intersection", "children": [{"op": "union", "children": [0, 1, 2, 3, 5, 6, 7]},
                                                    {"op": "union", "children": [4]}]}
@@ -624,7 +685,7 @@ def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
     return out
 
 
-def make_levels(seed=BASE_SEED + 22, dim=2, levels=(0.1, 0.34, 0.62, 1.0)):
+def make_levels(seed=BASE_SEED + 22, dim=2, levels=(0.1, 0.34, 0.62, 1.0), deep=False):
     """Four material sets under the non-binary union (Alg. cap): a circle from
     each quadrant, brought towards the center so that all four overlap there
     (the paper's Fig. nonbinary_union), the second set with an extra box and
@@ -650,8 +711,9 @@ def make_levels(seed=BASE_SEED + 22, dim=2, levels=(0.1, 0.34, 0.62, 1.0)):
     prims.append(box(x=(par(0.0537), par(0.2561)), y=(K(0.7013), K(0.8488)), z=z,
                      sig=(LIN, ("quadratic", "local", 1.0), LIN)))
     prims.append(ellipse(par(0.8537), par(0.7461), par(0.0813), z=z, sig=("erf", "fixed", 30.0)))
+    third = {"op": "difference", "children": [2, 5]} if deep else {"op": "union", "children": [2, 5]}
     tree = {"op": "levels", "levels": list(levels),
-            "children": [0, {"op": "union", "children": [1, 4]}, {"op": "union", "children": [2, 5]}, 3]}
+            "children": [0, {"op": "union", "children": [1, 4]}, third, 3]}
     scene = {"name": f"levels{dim}d", "dim": dim, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
              "eps_bg": 1.0, "eps_fg": 1.0 + levels[-1], "n_params": len(p), "prims": prims, "tree": tree}
     out = {"scene": scene, "p": np.array(p), "omega": 2 * math.pi / 1.4, "h": 1e-7}
@@ -729,6 +791,8 @@ CONFIGS = {
     "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
     "taper3_sine": make_taper_sine, "taper3_sine_small": make_taper_sine_small,
     "levels2": lambda: make_levels(dim=2), "levels3": lambda: make_levels(dim=3),
+    "levels2_deep": lambda: make_levels(dim=2, deep=True),
+    "blazed": make_blazed, "blazed_small": make_blazed_small,
 }
 
 

@@ -1,8 +1,12 @@
 """Parity at the full workload sizes (the launch configuration bench.py
-times): eps on randomly sampled samples of every component, and the fused
-gradient on sampled parameters, each computed by the oracle over every
-sample where that parameter's derivative can be non-zero; plus the GPU
+times): eps on randomly sampled samples of every component; the fused
+gradient of every parameter against the oracle's whole-grid gradient (summed
+over in-plane tiles, tests/oracle_tiles.py) on the 3D workloads, and on
+sampled parameters of the 2D blazed grating, each computed by the oracle over
+every sample where that parameter's derivative can be non-zero; plus the GPU
 finite-difference Jacobian against the fused gradient at full size."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -11,6 +15,7 @@ from oracle import primitives as prm
 from oracle import scene as S
 from oracle.lattice import component_samples
 from tests.gpu_util import api, rel, to_dev
+from tests.oracle_tiles import tiled_grad
 from paper_2311_05646_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -19,13 +24,14 @@ _CACHE = {}
 
 
 def _setup(name):
+    # every full-size workload stays resident once generated (a few GB of
+    # host and device memory for all of them), so that the tests of one
+    # workload need not follow each other
     if name not in _CACHE:
-        _CACHE.clear()
-        torch.cuda.empty_cache()
         print(f"[fullsize] generating {name}", flush=True)
         cfg = W.CONFIGS[name]()
         sc = api().Scene(cfg["scene"])
-        E, A = cfg["E"].astype(np.complex64), cfg["A"].astype(np.complex64)
+        E, A = np.asarray(cfg["E"], dtype=np.complex64), np.asarray(cfg["A"], dtype=np.complex64)
         _CACHE[name] = (cfg, sc, E, A, to_dev(E), to_dev(A))
     return _CACHE[name]
 
@@ -65,7 +71,15 @@ def _param_region(desc, p, k, ci):
     return np.unique(np.concatenate(out)) if out else np.zeros(0, dtype=np.int64)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
+def _workers():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "psgc3", "taper3_sine"])
 def test_eps_sampled(name):
     cfg, sc, E, A, Ed, Ad = _setup(name)
     eps = api().eps_build(sc, cfg["p"]).cpu().numpy()
@@ -80,6 +94,31 @@ def test_eps_sampled(name):
         ref = S.eps_at(cfg["scene"], cfg["p"], ci, idx)
         print(f"[fullsize] {name} comp {ci}: {idx.size} samples", flush=True)
         assert np.max(np.abs(flat[idx] - ref)) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["c3", "c4", "psgc3", "taper3_sine"])
+def test_vjp_whole_grid_oracle(name):
+    """Every parameter of the 3D workloads against the oracle's gradient over
+    the whole grid: the taper's 192 sidewall vertices, the grating coupler's
+    4800 hole parameters, the Fourier-scatterer grating's 1600 radii and its
+    12 shape coefficients that every scatterer shares (they take the spread
+    accumulation and the LDS coefficient slots), and the sine-series taper's
+    100 terms (each reaches the whole boundary)."""
+    cfg, sc, E, A, Ed, Ad = _setup(name)
+    got = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
+    print(f"[fullsize] {name}: oracle over the whole grid", flush=True)
+    ref = tiled_grad(cfg["scene"], cfg["p"], E, A, cfg["omega"], tile=(40, 40), workers=_workers())
+    r = rel(got, ref)
+    print(f"[fullsize] {name}: whole-gradient rel L2 {r:.3e}", flush=True)
+    assert np.count_nonzero(ref) == ref.size
+    assert r <= 1e-4
+    if name == "psgc3":
+        rg = rel(got[:12], ref[:12])
+        print(f"[fullsize] psgc3 shared coefficients rel L2 {rg:.3e}", flush=True)
+        assert rg <= 1e-4
+    if name == "taper3_sine":
+        # every term on its own, not only in the norm of the whole vector
+        assert np.max(np.abs(got - ref) / np.abs(ref)) <= 1e-3
 
 
 @pytest.mark.parametrize("name,nk", [("c2", 16), ("c3", 10), ("c4", 12)])
@@ -120,8 +159,9 @@ def test_vjp_sparse_full_size(name):
 def test_vjp_psgc_full_size():
     """Fourier-radius scatterers at full size: sampled per-scatterer radii
     against the oracle over their regions, and the 12 global shape
-    coefficients (every scatterer's boundary feeds them) against the GPU
-    finite-difference Jacobian."""
+    coefficients (every scatterer's boundary feeds them) also against the GPU
+    finite-difference Jacobian (the oracle check of every parameter is
+    test_vjp_whole_grid_oracle)."""
     cfg, sc, E, A, Ed, Ad = _setup("psgc3")
     got = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
     rng = np.random.default_rng(4)
@@ -144,10 +184,10 @@ def test_vjp_psgc_full_size():
 
 
 def test_vjp_taper_sine_full_size():
-    """The taper's 100 sine-series coefficients at full size (each reaches the
-    whole boundary, too many samples for the oracle one by one): the fused
-    gradient against the GPU finite-difference Jacobian, and the sparse VJP
-    against the dense one."""
+    """The taper's 100 sine-series coefficients at full size: the fused
+    gradient also against the GPU finite-difference Jacobian, and the sparse
+    VJP against the dense one (the oracle check is
+    test_vjp_whole_grid_oracle)."""
     cfg, sc, E, A, Ed, Ad = _setup("taper3_sine")
     got = api().eps_grad_vjp(sc, cfg["p"], Ed, Ad, cfg["omega"])
     fd = api().eps_grad_fd(sc, cfg["p"], Ed, Ad, cfg["omega"], cfg["h"])

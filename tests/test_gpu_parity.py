@@ -16,10 +16,15 @@ pytestmark = pytest.mark.gpu
 # primitives than one candidate scan pass; psgc3_small(_local): Fourier-radius
 # scatterers with global (shared) or per-scatterer shape coefficients;
 # taper3_sine_small: the taper's sine-series boundary (every parameter reaches
-# every column of it); levels2/3: the non-binary union over four material sets
+# every column of it); levels2/3: the non-binary union over four material sets;
+# blazed_small: the paper's three-level blazed-grating composition with etch
+# depths and the oxide thickness as parameters; zoo*_deep: six op nodes with
+# differences on both sides of a union; levels2_deep: a difference as one
+# material set of the non-binary union
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
          "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
-         "psgc3_small", "psgc3_small_local", "taper3_sine_small", "levels2", "levels3"]
+         "psgc3_small", "psgc3_small_local", "taper3_sine_small", "levels2", "levels3",
+         "blazed_small", "zoo2_deep", "zoo3_deep", "levels2_deep"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 
@@ -225,10 +230,17 @@ def test_invalid_inputs_raise():
         api().eps_build(sc, bad)
     with pytest.raises(ValueError):
         api().eps_build(sc, cfg["p"][:5])
+    # op trees of any depth compile, up to six op nodes; seven are refused
     d = dict(cfg["scene"])
     d["tree"] = {"op": "union", "children": [{"op": "union", "children": [{"op": "union", "children": [0]}]}, 1]}
-    with pytest.raises(SGError):
+    api().Scene(d)
+    chain = 7
+    for i in range(6, -1, -1):
+        chain = {"op": "union", "children": [i, chain]}
+    d["tree"] = chain
+    with pytest.raises(SGError) as e:
         api().Scene(d)
+    assert e.value.code == -7
     # the non-binary union: levels ascending, the top one = eps_fg - eps_bg, at the root only
     lv = W.make_levels(dim=2)["scene"]
     for tree in ({"op": "levels", "levels": [0.34, 0.1, 0.62, 1.0], "children": lv["tree"]["children"]},

@@ -80,3 +80,77 @@ def test_served_gradient_matches_oracle(name):
     ref = S.grad_analytic(cfg["scene"], cfg["p"], S.sensitivity(E, A, cfg["omega"]))
     assert rel(g, ref) <= 1e-4
     srv.close()
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["atomic", "deterministic"])
+def test_caller_fields_equal_vjp(det):
+    """Requests on the caller's field planes (serve_submit_fields): each result
+    equals eps_grad_vjp on the same planes, batched with seeded requests."""
+    rng = np.random.default_rng(13)
+    names = ["c2_small", "c3_small", "c4_small", "zoo3_union"]
+    cfgs = {n: config(n) for n in names}
+    scenes = {n: api().Scene(c["scene"]) for n, c in cfgs.items()}
+    for sc in scenes.values():
+        sc.set_deterministic(det)
+    planes = {n: (torch.from_numpy(c["E"].astype(np.complex64)).cuda(),
+                  torch.from_numpy(c["A"].astype(np.complex64)).cuda()) for n, c in cfgs.items()}
+    srv = api().Server(hbm_budget_bytes=1 << 30, max_slots=16, max_batch=8, n_streams=2)
+    sids = {n: srv.open_session(sc) for n, sc in scenes.items()}
+    sent = []
+    for i in range(12):
+        n = names[i % len(names)]
+        p = cfgs[n]["p"] + 1e-4 * rng.standard_normal(cfgs[n]["p"].shape)
+        if i % 3 == 2:      # a seeded request among them
+            seed = int(rng.integers(1, 2 ** 62))
+            sent.append((n, p, seed, srv.submit(sids[n], p, seed, cfgs[n]["omega"])))
+        else:
+            E, A = planes[n]
+            sent.append((n, p, None, srv.submit_fields(sids[n], p, E, A, cfgs[n]["omega"])))
+    print(f"[serve] {len(sent)} caller-field / seeded requests", flush=True)
+    for n, p, seed, t in sent:
+        st, g, _ = srv.poll(t, scenes[n].n_params)
+        assert st == "ok"
+        E, A = planes[n] if seed is None else api().fieldgen(scenes[n], seed)
+        ref = api().eps_grad_vjp(scenes[n], p, E, A, cfgs[n]["omega"])
+        if det:
+            assert np.array_equal(g, ref), n
+        else:
+            assert rel(g, ref) <= 1e-10, n
+    srv.close()
+
+
+@pytest.mark.parametrize("det", [False, True], ids=["atomic", "deterministic"])
+def test_sliced_requests_equal_whole(det):
+    """max_launch_us slices the 3D taper's requests (about 300 us of estimated
+    work each: field generation, then column blocks) over several batches of
+    one stream, beside whole small requests; every result equals the whole
+    computation."""
+    from paper_2311_05646_amd import workloads as W
+    rng = np.random.default_rng(17)
+    cfgs = {"c3": W.make_c3(with_fields=False), "c4_small": config("c4_small"), "c1": config("c1")}
+    names = list(cfgs)
+    scenes = {n: api().Scene(c["scene"]) for n, c in cfgs.items()}
+    for sc in scenes.values():
+        sc.set_deterministic(det)
+    srv = api().Server(hbm_budget_bytes=8 << 30, max_slots=16, max_batch=8, n_streams=2, max_launch_us=50)
+    sids = {n: srv.open_session(sc) for n, sc in scenes.items()}
+    sent = []
+    for i in range(9):
+        n = names[i % len(names)]
+        p = cfgs[n]["p"] + 1e-4 * rng.standard_normal(cfgs[n]["p"].shape)
+        seed = int(rng.integers(1, 2 ** 62))
+        sent.append((n, p, seed, srv.submit(sids[n], p, seed, cfgs[n]["omega"])))
+    for n, p, seed, t in sent:
+        st, g, _ = srv.poll(t, scenes[n].n_params)
+        assert st == "ok"
+        E, A = api().fieldgen(scenes[n], seed)
+        ref = api().eps_grad_vjp(scenes[n], p, E, A, cfgs[n]["omega"])
+        if det:
+            assert np.array_equal(g, ref), n
+        else:
+            assert rel(g, ref) <= 1e-10, n
+        del E, A
+    c = srv.counters()
+    print(f"[serve] sliced: {c}", flush=True)
+    assert c["batches"] >= 3 * sum(1 for n, *_ in sent if n == "c3")     # the taper requests were sliced
+    srv.close()

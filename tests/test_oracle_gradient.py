@@ -32,7 +32,8 @@ def test_central_fd_matches_analytic(name, h, tol):
     assert _rel(gf[sel], ga[sel]) < tol
 
 
-@pytest.mark.parametrize("dim,root", [(2, "union"), (3, "union"), (3, "difference"), (2, "intersection")])
+@pytest.mark.parametrize("dim,root", [(2, "union"), (3, "union"), (3, "difference"), (2, "intersection"),
+                                      (2, "deep"), (3, "deep")])
 def test_zoo_fd_matches_analytic(dim, root):
     cfg = W.make_zoo(dim=dim, root=root)
     g = S.sensitivity(cfg["E"], cfg["A"], cfg["omega"])
@@ -51,6 +52,15 @@ def test_levels_fd_matches_analytic(dim):
     gf = S.grad_fd(cfg["scene"], cfg["p"], g, 1e-6)
     assert _rel(gf, ga) < 1e-6
     assert np.count_nonzero(ga) >= 12
+
+
+def test_blazed_composition_fd_matches_analytic():
+    # three op levels, etch depths and the oxide thickness as parameters
+    cfg = W.make_blazed_small()
+    g = S.sensitivity(cfg["E"], cfg["A"], cfg["omega"])
+    ga = S.grad_analytic(cfg["scene"], cfg["p"], g)
+    assert _rel(S.grad_fd(cfg["scene"], cfg["p"], g, 1e-5), ga) < 1e-9
+    assert np.count_nonzero(ga) == cfg["scene"]["n_params"]
 
 
 def test_forward_fd_matches_analytic_c1():

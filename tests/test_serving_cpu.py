@@ -239,3 +239,50 @@ srv.close()
     r = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, env=env, timeout=60)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == "['ok', -2, -2] 0"
+
+
+def _latency(stats):
+    return (stats["done_ns"] - stats["submit_ns"]) * 1e-6
+
+
+@pytest.mark.parametrize("sliced", [True, False])
+def test_large_request_does_not_hold_small_ones(sliced):
+    # one stream; a request estimated at 20 ms (bytes at 4.5 TB/s) and a small
+    # one right behind it: with max_launch_us the large one is sliced and the
+    # small one runs after at most one slice, else it waits for all of it
+    srv = _server(hbm_budget_bytes=1 << 40, max_slots=8, max_batch=8, n_streams=1, fake_us=0,
+                  max_launch_us=1000 if sliced else 0)
+    big = srv.open_fake_session(2, int(4.5e6 * 20000))
+    small = srv.open_fake_session(1, 1000)
+    tb = srv.submit(big, [1.0, 2.0], 5, 1.0)
+    time.sleep(0.002)
+    ts = srv.submit(small, [3.0], 6, 1.0)
+    st, gs, ss = srv.poll(ts, 1)
+    st2, gb, sb = srv.poll(tb, 2)
+    assert st == st2 == "ok"
+    assert np.array_equal(gb, _expect([1.0, 2.0], 5)) and np.array_equal(gs, _expect([3.0], 6))
+    if sliced:
+        assert _latency(ss) < 5.0 and _latency(sb) > 15.0
+        assert srv.counters()["batches"] >= 20
+    else:
+        assert ss["done_ns"] >= sb["done_ns"] - 1_000_000
+    srv.close()
+
+
+def test_cancel_a_sliced_request():
+    srv = _server(hbm_budget_bytes=1 << 40, max_slots=8, max_batch=8, n_streams=1, fake_us=0, max_launch_us=1000)
+    big = srv.open_fake_session(1, int(4.5e6 * 30000))
+    small = srv.open_fake_session(1, 1000)
+    tb = srv.submit(big, [1.0], 1, 1.0)
+    time.sleep(0.004)
+    srv.cancel(tb)
+    from paper_2311_05646_amd._lib import SGError
+    with pytest.raises(SGError) as e:
+        srv.poll(tb, 1, timeout_us=5_000_000)
+    assert e.value.code == -5
+    # the stream is free again and the budget released
+    st, g, _ = srv.poll(srv.submit(small, [2.0], 3, 1.0), 1, timeout_us=5_000_000)
+    assert st == "ok" and np.array_equal(g, _expect([2.0], 3))
+    c = srv.counters()
+    assert c["bytes_in_use"] == 0 and c["batches"] < 15
+    srv.close()
