@@ -4,7 +4,8 @@
 // One scheduler thread owns all device work.  Each turn it
 //   1. admits queued requests in arrival order while a request slot is free and
 //      the request's buffers fit the HBM budget (a request that does not fit
-//      waits at the head of the queue);
+//      waits at the head of the queue, one whose session already has a request
+//      in flight waits for that session's buffer);
 //   2. polls the events of the batches in flight and completes their requests;
 //   3. when a stream is free, forms a batch of admitted requests and enqueues
 //      it on that stream: per request its p upload and stage (first slice
@@ -290,12 +291,20 @@ void retire(sg_server* v, Req* r, int state, sg_status status) {
 
 // Admit queued requests in arrival order while slots and budget allow.  The
 // budget bounds every request buffer that exists: a session keeps its idle
-// buffers for its next requests, and the least recently released idle
-// buffers of any session are freed when a new buffer would not fit.
+// buffers for its next requests.  A session with a request in flight grows
+// only into free budget; when none is left its next request waits for one of
+// the session's own buffers (later requests of other sessions may pass it, up
+// to kMaxPassed of them).  Only a session with nothing in flight frees the
+// least recently released idle buffers of other sessions to make room, so a
+// deep queue does not turn into a cycle of freeing and reallocating buffers
+// (each free waits for the device).
+constexpr int kMaxPassed = 64;
 void admit(sg_server* v) {
     const bool fake = v->opts.fake_executor != 0;
-    while (!v->pending.empty()) {
-        Req* r = v->pending.front();
+    size_t i = 0;
+    int passed = 0;
+    while (i < v->pending.size()) {
+        Req* r = v->pending[i];
         Session* s = r->s;
         if (v->slots_used >= v->opts.max_slots) return;
         const bool fields = !r->caller;
@@ -306,7 +315,15 @@ void admit(sg_server* v) {
         const int64_t extra = !b ? s->stage_bytes + (fields ? s->field_bytes : 0)
                                  : ((fields && !b->fields) ? s->field_bytes : 0);
         if (extra > 0) {
-            if (!make_room(v, extra, b)) return;       // busy buffers hold the budget
+            if (v->bytes_held + extra > v->opts.hbm_budget_bytes) {
+                if (s->all_bufs.size() > s->free_bufs.size()) {
+                    // its session has a request in flight: wait for that buffer
+                    if (++passed > kMaxPassed) return;
+                    ++i;
+                    continue;
+                }
+                if (!make_room(v, extra, b)) return;   // busy buffers hold the budget
+            }
             const bool had = b != nullptr;
             const int64_t before = had ? b->bytes : 0;
             if (!provide(v, s, b, fields)) {
@@ -315,7 +332,7 @@ void admit(sg_server* v) {
                 if (!provide(v, s, b, fields)) {
                     if (v->slots_used > 0) return;     // in-flight requests will free memory
                     // nothing runs that could free memory: the request cannot be served now
-                    v->pending.pop_front();
+                    v->pending.erase(v->pending.begin() + (std::ptrdiff_t)i);
                     retire(v, r, FAILED, SG_E_NOMEM);
                     continue;
                 }
@@ -330,7 +347,7 @@ void admit(sg_server* v) {
         }
         r->buf = b;
         r->need = s->stage_bytes + (fields ? s->field_bytes : 0);
-        v->pending.pop_front();
+        v->pending.erase(v->pending.begin() + (std::ptrdiff_t)i);
         v->bytes_used += r->need;
         v->slots_used += 1;
         r->state = ADMITTED;

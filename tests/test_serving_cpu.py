@@ -213,6 +213,32 @@ def test_idle_buffers_count_against_the_budget():
     srv.close()
 
 
+def test_deep_queue_waits_for_its_own_buffers():
+    # a session with a request in flight takes another buffer only from
+    # unused budget: its queued requests then wait for its own buffers instead
+    # of freeing the idle buffer of another session (every free waits for the
+    # device), and that other session's request passes them
+    srv = _server(hbm_budget_bytes=1000, max_slots=8, max_batch=8, n_streams=1, fake_us=20000)
+    a = srv.open_fake_session(1, 400)
+    b = srv.open_fake_session(1, 400)
+    assert srv.poll(srv.submit(b, [1.0], 1, 1.0), 1)[0] == "ok"
+    assert srv.counters()["bytes_held"] == 400
+    ta = [srv.submit(a, [float(i)], 10 + i, 1.0) for i in range(6)]
+    time.sleep(0.005)
+    tb = srv.submit(b, [2.0], 2, 1.0)
+    st, g, sb = srv.poll(tb, 1, timeout_us=5_000_000)
+    assert st == "ok" and np.array_equal(g, _expect([2.0], 2))
+    done = []
+    for i, t in enumerate(ta):
+        st, g, sa = srv.poll(t, 1, timeout_us=5_000_000)
+        assert st == "ok" and np.array_equal(g, _expect([float(i)], 10 + i))
+        assert srv.counters()["bytes_held"] == 800
+        done.append(sa["done_ns"])
+    # b's request did not wait for a's queue (a's requests run one or two at a time)
+    assert sb["done_ns"] < done[2]
+    srv.close()
+
+
 def test_allocation_failure_with_nothing_running_is_retired():
     # every buffer allocation after the first fails: a request that needs a
     # new buffer while nothing runs (so nothing can free memory) comes back
