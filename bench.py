@@ -12,8 +12,9 @@ Infinity Cache, so one field set is read from HBM on every step.
 
 Printed JSON line: value = gradient evaluations per second on the taper;
 roofline of the dominant kernel (the fused VJP column kernel, timed with HIP
-events on the call's stream inside the library, on every 7th launch of the
-timed loop; traffic from the committed rocprofv3 counter summary); the 3D
+events attached to the launch itself inside the library, so they take the
+kernel's own start and end, on every 7th launch of the timed loop; traffic
+from the committed rocprofv3 counter summary); the 3D
 grating coupler (400 x 400 x 80, 1601 primitives, n = 4800) and the 2D
 blazed grating with the same structure; the GPU finite-difference Jacobian
 baseline on all three at matched accuracy; the paper's own 3D
@@ -98,11 +99,11 @@ class Fast:
     """Pre-marshalled C-ABI calls for the timed loop (no per-call Python
     argument checks; the checked wrappers in api are used everywhere else)."""
 
-    def __init__(self, api, scene, p_dev, eps_out, grad_out, sets, omega, stream):
+    def __init__(self, api, scene, p_devs, eps_out, grad_out, sets, omega, stream):
         from paper_2311_05646_amd._lib import lib
         self.L = lib()
         self.ctx, self.sc = scene.ctx, scene.handle
-        self.p = C.c_void_p(p_dev.data_ptr())
+        self.ps = [C.c_void_p(p.data_ptr()) for p in p_devs]
         self.eps = C.c_void_p(eps_out.data_ptr())
         self.grad = C.c_void_p(grad_out.data_ptr())
         self.sets = [(api._plane_ptrs(scene, E), api._plane_ptrs(scene, A)) for E, A in sets]
@@ -110,9 +111,13 @@ class Fast:
         self.st = C.c_void_p(stream.cuda_stream)
 
     def step(self, i):
+        # an optimizer's step: a new p (the library then re-evaluates the
+        # in-plane sums in eps_build and reuses them in the gradient at the
+        # same p), eps at p, the gradient at p on the step's fields
         fe, fa = self.sets[i % len(self.sets)]
-        r1 = self.L.eps_build(self.ctx, self.sc, self.p, 1, self.eps, self.st)
-        r2 = self.L.eps_grad_vjp(self.ctx, self.sc, self.p, 1, fe, fa, self.omega, self.grad, 1, self.st)
+        p = self.ps[i % len(self.ps)]
+        r1 = self.L.eps_build(self.ctx, self.sc, p, 1, self.eps, self.st)
+        r2 = self.L.eps_grad_vjp(self.ctx, self.sc, p, 1, fe, fa, self.omega, self.grad, 1, self.st)
         if r1 or r2:
             raise RuntimeError(self.L.sg_last_error().decode())
 
@@ -125,18 +130,19 @@ def run_steps(api, W, cfg, sets, steps, warmup, traffic_name=None):
     dev = torch.device("cuda", 0)
     scene = api.Scene(cfg["scene"])
     p_dev = torch.tensor(cfg["p"], dtype=torch.float64, device=dev)
+    # a new p every step, as in an optimization (4 points 0.1 pm apart, cycled)
+    p_devs = [p_dev + 1e-7 * k for k in range(4)]
     eps_out = torch.empty(scene.shape, dtype=torch.float32, device=dev)
     grad_out = torch.empty(scene.n_params, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    fast = Fast(api, scene, p_dev, eps_out, grad_out, sets, cfg["omega"], stream)
+    fast = Fast(api, scene, p_devs, eps_out, grad_out, sets, cfg["omega"], stream)
     scene.set_timing(True)          # also fills the event pool the timed loop reuses
     for i in range(max(warmup, 2 * TIMING_EVERY)):
         fast.step(i)
     torch.cuda.synchronize()
-    # every TIMING_EVERY-th column launch of each kind is bracketed by HIP
-    # events on the call's stream (an event pair adds device time to its
-    # launch); 7 is odd, so with several field sets the timed launches cycle
-    # through all of them
+    # every TIMING_EVERY-th column launch of each kind carries a pair of HIP
+    # events that take the kernel's start and end; 7 is odd, so with several
+    # field sets the timed launches cycle through all of them
     scene.set_timing(True, every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -207,8 +213,12 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
     reads = scene.sparse_reads()
     sparse_rel = float(torch.linalg.norm(gs - g) / torch.linalg.norm(g))
     scene.set_timing(True)
-    for _ in range(reps):
-        api.eps_build(scene, p_dev, out=e)
+    # eps_build at alternating p: every call evaluates the in-plane sums (and
+    # keeps them); each gradient at the p of an eps_build before it, as in an
+    # optimization step (the in-plane sums come from the cache)
+    p_alt = (p_dev + 1e-7, p_dev)
+    for i in range(reps):
+        api.eps_build(scene, p_alt[i % 2], out=e)
     torch.cuda.synchronize()
     for _ in range(reps):
         api.eps_grad_vjp(scene, p_dev, E, A, omega, grad=g)
@@ -345,36 +355,59 @@ def bench_serving(api, W, seconds=3.0, think_us=200.0):
             "think_us": think_us}
 
 
-def serve_open_loop(api, W, capacity, loads=(0.1, 0.3, 0.5, 0.7, 0.9), seconds=1.0, max_launch_us=200):
-    """Open-loop Poisson arrivals from the serving mix's 64 sessions at a
-    fraction of the measured closed-loop capacity: submitted at their arrival
-    times whatever is in flight, latency = completion - submission (both
-    stamped by the server).  The same arrival trace is then replayed one
-    request at a time on one stream (field generation + eps_grad_vjp, a
-    request starting when it has arrived and the previous one is done), its
-    latency counted from the arrival."""
+def serve_open_loop(api, W, loads=(0.1, 0.3, 0.5, 0.7, 0.9), seconds=1.0, max_launch_us=200, n_streams=2,
+                    budget=24 << 30, n_burst=3000):
+    """Open-loop Poisson arrivals from the serving mix's 64 sessions, each
+    request for a session drawn uniformly.  The capacity these loads are
+    fractions of is measured for that same draw: a burst of n_burst requests
+    submitted at once, completions per second until the last is done (the
+    same burst replayed one request at a time gives the sequential capacity).
+    At each load the requests are submitted at their arrival times whatever
+    is in flight, latency = completion - submission (both stamped by the
+    server).  The same arrival trace is then replayed one request at a time on
+    one stream (field generation + eps_grad_vjp, a request starting when it
+    has arrived and the previous one is done), its latency counted from the
+    arrival."""
     import numpy as np
     mix = W.make_serving_mix()
     scenes = [api.Scene(c["scene"]) for c in mix]
     rng = np.random.default_rng(23)
-    out = {"max_launch_us": max_launch_us, "seconds_per_load": seconds, "capacity_grads_per_s": capacity,
-           "loads": []}
-    srv = api.Server(hbm_budget_bytes=24 << 30, max_slots=64, max_batch=16, n_streams=2,
+    srv = api.Server(hbm_budget_bytes=budget, max_slots=64, max_batch=16, n_streams=n_streams,
                      max_launch_us=max_launch_us)
     sids = [srv.open_session(sc) for sc in scenes]
     warm = [(i, srv.submit(sids[i], mix[i]["p"], 1000 + i, mix[i]["omega"])) for i in range(len(mix))]
     for i, t in warm:
         srv.poll(t, scenes[i].n_params)
     seed = [(W.BASE_SEED << 20)]
+
+    def draw():
+        i = int(rng.integers(len(mix)))
+        seed[0] += 1
+        return i, mix[i]["p"] + mix[i]["jitter"] * rng.standard_normal(mix[i]["p"].shape), seed[0]
+
+    def sequential(i, p, sd):
+        E, A = api.fieldgen(scenes[i], sd)
+        api.eps_grad_vjp(scenes[i], p, E, A, mix[i]["omega"])     # host grad: waits for the result
+
+    burst = [draw() for _ in range(n_burst)]
+    t0 = time.perf_counter()
+    tickets = [(i, srv.submit(sids[i], p, sd, mix[i]["omega"])) for i, p, sd in burst]
+    for i, t in tickets:
+        srv.poll(t, scenes[i].n_params)
+    capacity = n_burst / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for i, p, sd in burst:
+        sequential(i, p, sd)
+    seq_capacity = n_burst / (time.perf_counter() - t0)
+    log(f"[bench] open-loop capacity: served {capacity:.0f}/s, one at a time {seq_capacity:.0f}/s")
+    out = {"max_launch_us": max_launch_us, "n_streams": n_streams, "hbm_budget_bytes": budget,
+           "seconds_per_load": seconds, "capacity_grads_per_s": capacity,
+           "sequential_capacity_grads_per_s": seq_capacity, "capacity_burst": n_burst, "loads": []}
     for f in loads:
         lam = f * capacity
         arr = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * seconds * 1.5) + 10))
         arr = arr[arr < seconds]
-        trace = []
-        for a in arr:
-            i = int(rng.integers(len(mix)))
-            seed[0] += 1
-            trace.append((a, i, mix[i]["p"] + mix[i]["jitter"] * rng.standard_normal(mix[i]["p"].shape), seed[0]))
+        trace = [(a,) + draw() for a in arr]
         log(f"[bench] open loop at {f:.0%} of capacity: {len(trace)} requests")
         tickets = []
         t0 = time.perf_counter()
@@ -394,8 +427,7 @@ def serve_open_loop(api, W, capacity, loads=(0.1, 0.3, 0.5, 0.7, 0.9), seconds=1
         for a, i, p, sd in trace:
             while time.perf_counter() - t0 < a:
                 pass
-            E, A = api.fieldgen(scenes[i], sd)
-            api.eps_grad_vjp(scenes[i], p, E, A, mix[i]["omega"])     # host grad: waits for the result
+            sequential(i, p, sd)
             seq.append((time.perf_counter() - t0 - a) * 1e3)
         lat, seq = np.array(lat), np.array(seq)
         out["loads"].append({"load": f, "rate_per_s": lam, "requests": len(trace),
@@ -403,6 +435,8 @@ def serve_open_loop(api, W, capacity, loads=(0.1, 0.3, 0.5, 0.7, 0.9), seconds=1
                              "server": {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))},
                              "sequential": {"p50_ms": float(np.percentile(seq, 50)),
                                             "p99_ms": float(np.percentile(seq, 99))}})
+    c = srv.counters()
+    out["bytes_held_end"] = c["bytes_held"]
     srv.close()
     return out
 
@@ -497,10 +531,6 @@ def main():
     dev = torch.device("cuda", 0)
     gen = torch.Generator(device=dev)
     gen.manual_seed(W.BASE_SEED)
-    if args.kernels_3d:
-        print(json.dumps({"3d": kernels_3d(api, W, gen, max(1, args.steps))}), flush=True)
-        return
-
     if args.calib_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -508,6 +538,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("[bench] reference copy of 1 GiB done")
+
+    if args.kernels_3d:
+        print(json.dumps({"3d": kernels_3d(api, W, gen, max(1, args.steps))}), flush=True)
+        return
 
     def randset(shape):
         return tuple(torch.complex(torch.randn(shape, device=dev, generator=gen),
@@ -587,7 +621,7 @@ def main():
     # ---- serving: continuous batching vs one-at-a-time launches
     log("[bench] serving")
     out["serve"] = bench_serving(api, W, seconds=args.serve_seconds)
-    out["serve"]["open_loop"] = serve_open_loop(api, W, out["serve"]["grads_per_s"])
+    out["serve"]["open_loop"] = serve_open_loop(api, W)
 
     # ---- CPU oracle on this host (and the whole taper gradient checked)
     log("[bench] cpu baseline (oracle)")

@@ -283,7 +283,9 @@ sg_status sg_fieldgen(void* e_fwd, void* e_adj, int64_t n, uint64_t seed, void* 
  * parameter counts.  A scheduler thread admits queued requests in arrival
  * order while request slots and the HBM budget allow, gives each admitted
  * request its own device buffers (seeded fields, staging, gradient; reused per
- * session), groups admitted requests into batched launches (one kernel launch
+ * session; a session with a request in flight takes another buffer only from
+ * unused budget, else its next request waits for one of its own, while only a
+ * session with nothing in flight frees other sessions' idle buffers), groups admitted requests into batched launches (one kernel launch
  * covers the tiles of every request of the same kernel specialization) and
  * issues batches on several streams in turn, so requests that arrive while
  * others run are admitted and overlap with them on the device.  Completion is
@@ -354,14 +356,12 @@ sg_status serve_cancel(sg_server* server, uint64_t ticket);
 sg_status serve_counters(sg_server* server, int64_t* completed, int64_t* batches, int64_t* max_batch_seen,
                          int64_t* bytes_in_use, int64_t* bytes_held);
 
-/* Kernel tracing.  With timing enabled the scene records a pair of HIP events
- * on the call's stream around every launch of its column kernel (the kernel
- * that evaluates eps or its reverse mode; a call also runs a small staging
- * kernel before it).  sg_scene_set_timing(scene, k) with k >= 1 clears the
- * records and then brackets the 1st, (k+1)-th, (2k+1)-th ... launch of each
- * kind (an event pair adds a few microseconds of device time to its launch,
- * so a period above 1 keeps a timed loop close to its untimed speed); 0
- * disables.  sg_scene_kernel_time() waits for the recorded launches
+/* Kernel tracing.  With timing enabled the scene attaches a pair of HIP
+ * events to launches of its column kernel (the kernel that evaluates eps or
+ * its reverse mode; a call also runs a small staging kernel before it): they
+ * take the kernel's own start and end times, dispatch gaps excluded.
+ * sg_scene_set_timing(scene, k) with k >= 1 clears the records and then
+ * times the 1st, (k+1)-th, (2k+1)-th ... launch of each kind; 0 disables.  sg_scene_kernel_time() waits for the recorded launches
  * of one kind (mode: 0 eps_build, 1 eps_grad_vjp, 2 eps_grad_vjp_geps,
  * 3 eps_grad_fd rasterization, 4 eps_grad_vjp_sparse, 5 eps_grad_fd_sparse) and returns their summed duration (ms) and
  * count. */

@@ -69,7 +69,7 @@ class Scene:
 
     def kernel_time(self, mode):
         """(summed ms, launches) of the traced column kernels of one kind:
-        'eps', 'vjp', 'geps', 'fd' or 'sparse'."""
+        'eps', 'vjp', 'geps', 'fd', 'sparse' or 'fd_sparse'."""
         t = C.c_double()
         n = C.c_int64()
         check(lib().sg_scene_kernel_time(self.handle, _lib.MODE[mode], C.byref(t), C.byref(n)))

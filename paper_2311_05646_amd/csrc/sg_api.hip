@@ -110,6 +110,9 @@ static void free_scene(sg_scene* s) {
     hipFree(s->d_nread);
     hipFree(s->d_fx);
     hipFree(s->d_gspread);
+    hipFree(s->d_fplane);
+    hipFree(s->d_fprev);
+    hipFree(s->d_chg);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
     if (s->h_p) hipHostFree(s->h_p);
@@ -734,6 +737,16 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     {
         const char* det = std::getenv("SG_DETERMINISTIC");
         s->deterministic = det != nullptr && std::atoi(det) != 0;
+        const char* rect = std::getenv("SG_EPS_RECT_TILES");
+        s->linear_tiles = !(rect != nullptr && std::atoi(rect) != 0);
+        // the F cache pays where the in-plane evaluation is costly (sigmoid
+        // ellipses, Fourier radii, sine series, the catch-all set): measured
+        // on the Fourier-scatterer coupler, gradient after eps_build 200 ->
+        // 169 us; with boxes and piecewise-linear boundaries its plane traffic
+        // costs about what it saves (taper: 183.5 vs 187.9 us per step)
+        const char* fc = std::getenv("SG_F_CACHE");
+        if (fc != nullptr) s->fcache = std::atoi(fc) != 0;
+        else s->fcache = !(s->variant == VAR_BOX_LIN || s->variant == VAR_GCART_LIN);
     }
     *out = s;
     return SG_OK;
@@ -815,7 +828,7 @@ StageParams sg::stage_params(sg_scene* s, const double* dp) {
     return sp;
 }
 
-KParams sg::column_params(sg_scene* s, int64_t target_blocks) {
+KParams sg::column_params(sg_scene* s, int64_t target_blocks, bool linear) {
     KParams kp{};
     kp.nu = s->nu;
     kp.nv = s->nv;
@@ -832,6 +845,17 @@ KParams sg::column_params(sg_scene* s, int64_t target_blocks) {
     kp.tv = kBlock / tu;
     kp.tiles_u = (s->nu + tu - 1) / tu;
     kp.tiles_v = (s->nv + kp.tv - 1) / kp.tv;
+    // linear tiles only where the automatic choice is wide rows: with many
+    // small primitives a 64-sample strip per wavefront meets about twice as
+    // many of them as a 16 x 4 patch (measured: eps_build on the 1601-hole
+    // grating 59 -> 108 us)
+    if (linear && s->sv == s->nu && s->linear_tiles && s->block_x == 0 && tu >= 128) {
+        kp.linear = 1;
+        kp.tu = kBlock;
+        kp.tv = 1;
+        kp.tiles_u = (int32_t)(((int64_t)s->nu * s->nv + kBlock - 1) / kBlock);
+        kp.tiles_v = 1;
+    }
     int nseg = s->nseg;
     if (nseg == 0) {
         const int64_t base = (int64_t)s->ncomp * kp.tiles_u * kp.tiles_v;
@@ -922,7 +946,8 @@ static hipError_t take_event(sg_scene* s, hipEvent_t* e) {
     return hipEventCreate(e);
 }
 
-// Launches the column kernel, bracketed by events when tracing is on.
+// Launches the column kernel; when tracing is on, a pair of events takes the
+// kernel's start and end times (no dispatch gap counted).
 static sg_status run_column(sg_scene* s, int mode, const KParams& kp, hipStream_t st) {
     if (!s->timing || (s->launches[mode & 7]++ % s->timing) != 0) {
         HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));
@@ -931,10 +956,36 @@ static sg_status run_column(sg_scene* s, int mode, const KParams& kp, hipStream_
     sg_scene::Rec r{mode, nullptr, nullptr};
     HIP_OK(take_event(s, &r.a));
     HIP_OK(take_event(s, &r.b));
-    HIP_OK(hipEventRecord(r.a, st));
-    HIP_OK(launch_column(mode, s->tree, s->variant, kp, st));
-    HIP_OK(hipEventRecord(r.b, st));
+    HIP_OK(launch_column(mode, s->tree, s->variant, kp, st, r.a, r.b));
     s->recs.push_back(r);
+    return SG_OK;
+}
+
+// The F cache around one call: the planes and comparison buffers exist
+// (allocated at first use, the first call's stage kernel forced to flag a
+// change), the stage kernel compares the fields with those the planes were
+// computed from, and the column kernel reads (no change) or writes the planes.
+static sg_status fcache_prepare(sg_scene* s, StageParams& sp, KParams& kp, hipStream_t st) {
+    const int64_t nuv = (int64_t)s->nu * s->nv;
+    int force = 0;
+    if (!s->d_fplane) {
+        HIP_OK(hipMalloc((void**)&s->d_fplane, (size_t)s->ncomp * std::max(1, s->nclass) * nuv * sizeof(double)));
+        HIP_OK(hipMalloc((void**)&s->d_fprev, std::max<int64_t>(1, s->nfield) * sizeof(double)));
+        HIP_OK(hipMalloc((void**)&s->d_chg, 4 * sizeof(int32_t)));
+        HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_chg), 0.0, 2, st));     // all-zero bits
+        force = 1;
+    }
+    const int gen = s->fgen;
+    s->fgen = (gen + 1) % 3;
+    sp.fprev = s->d_fprev;
+    sp.chg = s->d_chg;
+    sp.gen = gen;
+    sp.force = force;
+    kp.fplane = s->d_fplane;
+    kp.fprev = s->d_fprev;
+    kp.chg = s->d_chg;
+    kp.gen = gen;
+    kp.nfield = (int32_t)s->nfield;
     return SG_OK;
 }
 
@@ -982,11 +1033,16 @@ extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_
     const double* dp;
     if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
     StageParams sp = stage_params(s, dp);
-    HIP_OK(launch_stage(sp, 1, st));
     // eps_build writes 4 B per sample against the VJP's 16 B read: on short
     // columns its blocks are shorter than their prologue, and a quarter more
-    // of them measured faster (blazed grating: 18.6 vs 19.4 us)
-    KParams kp = column_params(s, 960);
+    // of them measured faster (blazed grating: 18.6 vs 19.4 us).
+    // Linear tiles: every wavefront stores 64 consecutive floats per step, so
+    // whole 128-byte lines leave with the non-temporal stores (a 128 x 2 tile
+    // on a 600-wide grid writes 256-byte runs that straddle line boundaries;
+    // measured on the taper: 71.6 -> 40.2 us)
+    KParams kp = column_params(s, 960, true);
+    if (s->fcache && (rc = fcache_prepare(s, sp, kp, st)) != SG_OK) return rc;
+    HIP_OK(launch_stage(sp, 1, st));
     kp.out = eps;
     return run_column(s, MODE_EPS, kp, st);
 }
@@ -1082,8 +1138,9 @@ static sg_status vjp_common(sg_ctx* ctx, sg_scene* s, const double* p, int p_on_
     }
     sp.zero_ptr = g;
     sp.zero_n = s->n_params;
-    HIP_OK(launch_stage(sp, 1, st));
     KParams kp = column_params(s);
+    if (s->fcache && !noalloc && mode != MODE_VJP_SPARSE && (rc = fcache_prepare(s, sp, kp, st)) != SG_OK) return rc;
+    HIP_OK(launch_stage(sp, 1, st));
     kp.fval = stg.fval;
     kp.bbox = stg.bbox;
     kp.prec = stg.prec;

@@ -16,6 +16,8 @@
 //            atomic per parameter field touched by the wavefront.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "sg_device.h"
 
 namespace sg {
@@ -196,7 +198,6 @@ __device__ __forceinline__ void add_to_class(double (&F)[NC], int cls, double v)
         if (c == cls) F[c] += v;
 }
 
-constexpr int kStageRec = 32;   // candidate records staged in LDS per round
 
 // Copies the records of candidates s_cand[j0, j0 + n) (n <= kStageRec) to
 // s_rec, one thread per candidate; barriers before (earlier readers) and after.
@@ -300,9 +301,13 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
                                              const PrimRec* __restrict__ prec, const double* __restrict__ fval,
                                              const Tile& T, int comp, int u, double uc, double uw, double vc,
                                              double vw, int* s_cand, int* s_cnt, PrimRec* s_rec, double (&F)[NC],
-                                             int& ncand, bool& staged_all, Hook&& after_stage, bool* live = nullptr) {
+                                             int& ncand, bool& staged_all, Hook&& after_stage, bool* live = nullptr,
+                                             bool eval = true) {
+    // eval false: F is given (the F cache); only the candidates are listed and staged
+    if (eval) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) F[c] = 0.0;
+        for (int c = 0; c < NC; ++c) F[c] = 0.0;
+    }
     if constexpr (PROBE) *live = false;
     ncand = 0;
     staged_all = false;
@@ -321,7 +326,7 @@ __device__ __forceinline__ void inplane_sums(const KParams& P, const float4* __r
                 after_stage();
                 hooked = true;
             }
-            if (!T.wave_live) continue;
+            if (!T.wave_live || !eval) continue;
             for (int j = 0; j < nj; ++j) {
                 if (!wave_meets(T, s_rec[j].bb)) continue;
                 double f;
@@ -968,9 +973,48 @@ struct TileGeom {
     Tile T;
 };
 
+// Linear tiles: the block's samples are in-plane indices [i0, i0 + 256) in
+// row-major order; a span of indices covers the u range of its rows (the
+// whole row width when it crosses a row end).
+__device__ __forceinline__ void span_box(const KParams& P, const double* ucs, const double* vcs, int first, int last,
+                                         double& ulo, double& uhi, double& vlo, double& vhi) {
+    const int v0 = first / P.nu, v1 = last / P.nu;
+    const int u0 = (v0 == v1) ? first - v0 * P.nu : 0;
+    const int u1 = (v0 == v1) ? last - v1 * P.nu : P.nu - 1;
+    ulo = ucs[u0];
+    uhi = ucs[u1];
+    vlo = vcs[v0];
+    vhi = vcs[v1];
+}
+
 __device__ __forceinline__ TileGeom tile_geom(const KParams& P, int b) {
     const int tid = threadIdx.x, wave = tid >> 6;
     TileGeom G;
+    if (P.linear) {
+        const int nuv = P.nu * P.nv;
+        const int ti = b % P.tiles_u;
+        G.comp = b / P.tiles_u;
+        const int first = ti * kBlock, last = min(first + kBlock, nuv) - 1;
+        const int idx = first + tid;
+        G.act = idx < nuv;
+        const int ic = min(idx, nuv - 1);
+        G.vv = ic / P.nu;
+        G.uu = ic - G.vv * P.nu;
+        G.u = G.act ? G.uu : P.nu;
+        G.v = G.vv;
+        const double* __restrict__ ucs = P.uc[G.comp];
+        const double* __restrict__ vcs = P.vc[G.comp];
+        G.uc = ucs[G.uu];
+        G.uw = P.uw[G.comp][G.uu];
+        G.vc = vcs[G.vv];
+        G.vw = P.vw[G.comp][G.vv];
+        Tile& T = G.T;
+        span_box(P, ucs, vcs, first, last, T.ulo, T.uhi, T.vlo, T.vhi);
+        const int wf = first + wave * 64;
+        T.wave_live = wf < nuv;
+        span_box(P, ucs, vcs, min(wf, nuv - 1), min(wf + 64, nuv) - 1, T.wulo, T.wuhi, T.wvlo, T.wvhi);
+        return G;
+    }
     const int tvi = b % P.tiles_v;
     b /= P.tiles_v;
     const int tui = b % P.tiles_u;
@@ -1241,8 +1285,44 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     int ncand = 0;
     bool staged_all = false;
     bool live = true;    // sparse: some in-plane partial of the sample can be nonzero
-    inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw, s_cand,
-                                          s_cnt, s_rec, F, ncand, staged_all, first_loads, &live);
+    // F cache (eps_build, eps_grad_vjp, eps_grad_vjp_geps): when no field
+    // has changed since the planes were written (chg[gen % 3] == 0, set by
+    // the stage kernel), F comes from the planes and the prologue only lists
+    // and stages the candidates (for the partials); otherwise the kernel
+    // evaluates F and writes it there (and the fields it came from) for the
+    // next call at the same p.
+    constexpr bool CACHE = (MODE == MODE_EPS || MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
+    const int64_t nuv = (int64_t)P.nu * P.nv;
+    const int64_t fidx = (int64_t)comp * P.nclass * nuv + (int64_t)G.uu + (int64_t)G.vv * P.nu;
+    bool cached = false;
+    if constexpr (CACHE) {
+        if (P.fplane != nullptr)
+            cached = __builtin_amdgcn_readfirstlane(*(volatile const int*)(P.chg + P.gen % 3)) == 0;
+    }
+    if (cached) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) F[c] = (c < P.nclass) ? P.fplane[fidx + (int64_t)c * nuv] : 0.0;
+    }
+    if constexpr (VJP) {
+        inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
+                                              s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads, &live,
+                                              !cached);
+    } else if (!cached) {
+        inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
+                                              s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads, &live);
+    }
+    if (!cached) {
+        if constexpr (CACHE) {
+            if (P.fplane != nullptr) {
+                if (seg == 0 && act) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (c < P.nclass) P.fplane[fidx + (int64_t)c * nuv] = F[c];
+                }
+                for (int i = b * kBlock + tid; i < P.nfield; i += (int)gridDim.x * kBlock) P.fprev[i] = P.fval[i];
+            }
+        }
+    }
     if constexpr (FDM) {
         int nc2;
         bool sa2;
@@ -1368,11 +1448,15 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                 }
             }
             if (act) {
+                // eps goes out non-temporal (the nt bit of the buffer store):
+                // its lines leave the caches at once instead of being written
+                // back while the next kernel streams its own inputs
+                constexpr int kStorePolicy = (MODE == MODE_EPS) ? 2 : 0;
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q)
                     if (w + q < w1)
                         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[q]), ro, out_lane,
-                                                              (int)(q * out_step), 0);
+                                                              (int)(q * out_step), kStorePolicy);
             }
         }
         return;
@@ -1580,19 +1664,21 @@ __global__ __launch_bounds__(256) void k_column_batch(const KParams* __restrict_
 
 // ------------------------------------------------------------------ launch templates
 template <int MODE, int TYPES, int SIGS>
-static hipError_t launch_variant(int tree, const KParams& kp, hipStream_t st) {
+static hipError_t launch_variant(int tree, const KParams& kp, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int64_t blocks = (int64_t)kp.ncomp * kp.tiles_u * kp.tiles_v * kp.nseg;
     const dim3 grid((unsigned)blocks), blk(256);
+    // e0 / e1 (optional) take the kernel's own start and end times
+    auto go = [&](auto kern) { hipExtLaunchKernelGGL(kern, grid, blk, 0, st, e0, e1, 0, kp); };
     switch (tree) {
-        case TR_U1: hipLaunchKernelGGL((k_column<MODE, TR_U1, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        case TR_U2: hipLaunchKernelGGL((k_column<MODE, TR_U2, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        case TR_D11: hipLaunchKernelGGL((k_column<MODE, TR_D11, TYPES, SIGS>), grid, blk, 0, st, kp); break;
-        case TR_D12: hipLaunchKernelGGL((k_column<MODE, TR_D12, TYPES, SIGS>), grid, blk, 0, st, kp); break;
+        case TR_U1: go(k_column<MODE, TR_U1, TYPES, SIGS>); break;
+        case TR_U2: go(k_column<MODE, TR_U2, TYPES, SIGS>); break;
+        case TR_D11: go(k_column<MODE, TR_D11, TYPES, SIGS>); break;
+        case TR_D12: go(k_column<MODE, TR_D12, TYPES, SIGS>); break;
         default:
             // generic op trees only come with the catch-all feature set
             if constexpr (TYPES == T_ALL && SIGS == S_ALL) {
-                if (tree == TR_GEN4) hipLaunchKernelGGL((k_column<MODE, TR_GEN4, TYPES, SIGS>), grid, blk, 0, st, kp);
-                else hipLaunchKernelGGL((k_column<MODE, TR_GEN8, TYPES, SIGS>), grid, blk, 0, st, kp);
+                if (tree == TR_GEN4) go(k_column<MODE, TR_GEN4, TYPES, SIGS>);
+                else go(k_column<MODE, TR_GEN8, TYPES, SIGS>);
             } else {
                 return hipErrorInvalidValue;
             }
@@ -1625,23 +1711,23 @@ static hipError_t launch_batch_variant(int tree, const KParams* plist, const int
 }
 
 template <int MODE>
-hipError_t launch_mode(int tree, int variant, const KParams& kp, hipStream_t st) {
+hipError_t launch_mode(int tree, int variant, const KParams& kp, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     switch (variant) {
-        case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(tree, kp, st);
-        case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(tree, kp, st);
-        case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, kp, st);
-        case VAR_POLAR_SIGMOID: return launch_variant<MODE, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, kp, st);
-        case VAR_SERIES_LIN: return launch_variant<MODE, T_BOX | T_SERIES, S_LIN>(tree, kp, st);
-        default: return launch_variant<MODE, T_ALL, S_ALL>(tree, kp, st);
+        case VAR_BOX_LIN: return launch_variant<MODE, T_BOX, S_LIN>(tree, kp, st, e0, e1);
+        case VAR_GCART_LIN: return launch_variant<MODE, T_BOX | T_GCART, S_LIN>(tree, kp, st, e0, e1);
+        case VAR_ELL_SIGMOID: return launch_variant<MODE, T_BOX | T_ELL, S_LIN | S_SIGMOID>(tree, kp, st, e0, e1);
+        case VAR_POLAR_SIGMOID: return launch_variant<MODE, T_BOX | T_POLAR, S_LIN | S_SIGMOID>(tree, kp, st, e0, e1);
+        case VAR_SERIES_LIN: return launch_variant<MODE, T_BOX | T_SERIES, S_LIN>(tree, kp, st, e0, e1);
+        default: return launch_variant<MODE, T_ALL, S_ALL>(tree, kp, st, e0, e1);
     }
 }
 
 // launch_mode is instantiated once per mode, in its own translation unit
-extern template hipError_t launch_mode<MODE_EPS>(int, int, const KParams&, hipStream_t);
-extern template hipError_t launch_mode<MODE_VJP_FIELDS>(int, int, const KParams&, hipStream_t);
-extern template hipError_t launch_mode<MODE_VJP_GEPS>(int, int, const KParams&, hipStream_t);
-extern template hipError_t launch_mode<MODE_FD>(int, int, const KParams&, hipStream_t);
-extern template hipError_t launch_mode<MODE_VJP_SPARSE>(int, int, const KParams&, hipStream_t);
-extern template hipError_t launch_mode<MODE_FD_SPARSE>(int, int, const KParams&, hipStream_t);
+extern template hipError_t launch_mode<MODE_EPS>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_mode<MODE_VJP_FIELDS>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_mode<MODE_VJP_GEPS>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_mode<MODE_FD>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_mode<MODE_VJP_SPARSE>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
+extern template hipError_t launch_mode<MODE_FD_SPARSE>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace sg

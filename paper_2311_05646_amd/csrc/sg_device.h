@@ -286,8 +286,12 @@ __device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __r
     const int N = __builtin_amdgcn_readfirstlane(pr.nvert);
     const ConstF64 f = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0));
     const double dx = uc - f[0], dy = vc - f[1];
-    const double r = sqrt(dx * dx + dy * dy);
-    const double c1 = r > 0.0 ? dx / r : 1.0, s1 = r > 0.0 ? dy / r : 0.0;
+    const double r2 = dx * dx + dy * dy;
+    // one reciprocal square root gives r and the direction cosines (within
+    // 2 ulp of sqrt and of the quotients; no FP64 division)
+    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r = r2 * ir;
+    const double c1 = r2 > 0.0 ? dx * ir : 1.0, s1 = r2 > 0.0 ? dy * ir : 0.0;
     double R = f[2], d = 0.0, cn = 1.0, sn = 0.0;
     for (int n = 1; n <= N; ++n) {
         const double c = cn * c1 - sn * s1;

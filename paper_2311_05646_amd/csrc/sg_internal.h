@@ -17,6 +17,7 @@ constexpr int kBlock = 256;        // threads (= in-plane samples) per block
 // block serializes them)
 constexpr int kGradSpread = 32;
 constexpr int kCandCap = 2048;     // candidate primitives listed in LDS per pass
+constexpr int kStageRec = 32;      // candidate records staged in LDS per round
 constexpr int kZStage = 512;       // extrusion-table entries staged in LDS per chunk
 constexpr int kReadSlots = 256;    // partial counters of the sparse VJP's read statistic
 
@@ -125,12 +126,24 @@ struct StageParams {
     int32_t tables;              // write the extrusion tables and codes (0: the scene's are static)
     double* zero_ptr;            // zeroed by variant 0 (gradient accumulator)
     int64_t zero_n;
+    // F cache: variant 0's fields are compared with fprev (the fields the F
+    // planes were computed from); any difference, or force, sets
+    // chg[gen % 3]; chg[(gen + 1) % 3] is cleared for the next call.
+    // fprev == nullptr: no comparison.
+    const double* fprev;
+    int32_t* chg;
+    int32_t gen, force;
 };
 
 struct KParams {
     int32_t nu, nv, nw, ncomp;
     int64_t sv, sw, plane;       // element strides of v and w, elements per component plane
     int32_t tu, tv, tiles_u, tiles_v;        // in-plane tiles of the column kernel's blocks
+    // 1: a block's samples are 256 consecutive in-plane samples (row-major,
+    // rows joined: tiles_u = ceil(nu nv / 256), tiles_v = 1), so each
+    // wavefront's samples are 64 consecutive elements of memory; eps_build
+    // uses it when the rows are contiguous (sv == nu)
+    int32_t linear;
     int32_t nseg, seglen;                    // column segments (seglen a multiple of kGroup)
     int32_t nprim, nclass;
     int32_t cls_wparam[kMaxClasses];
@@ -193,11 +206,22 @@ struct KParams {
     // spread accumulation: block b adds into grad + (b mod kGradSpread) * gstride
     // (gstride = n: kGradSpread copies, summed by k_spread_finish; 0: one copy)
     int64_t gstride;
+    // F cache (eps_build, eps_grad_vjp, eps_grad_vjp_geps): the in-plane sums
+    // F_c of every sample as FP64 planes fplane[comp][class][v][u], valid
+    // while chg[gen % 3] == 0 (no field differs from fprev, the nfield fields
+    // they were computed from); a kernel that evaluates F writes both.
+    // nullptr: no cache.
+    double* fplane;
+    double* fprev;
+    const int32_t* chg;
+    int32_t gen, nfield;
 };
 
 // kernel launchers (sg_kernels.hip)
 hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st);
-hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st);
+// e0 / e1: optional events that take the kernel's own start and end times
+hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 // fused VJP (E, Eadj fields) over several requests of one kernel specialization:
 // plist / first in device memory, blocks = first[nreq]
 hipError_t launch_column_batch(int tree, int variant, const KParams* plist, const int* first, int nreq,

@@ -39,6 +39,10 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         return r.a + r.b * pv;
     };
     const int prim_blocks = (sp.nprim + 3) / 4;
+    if (sp.fprev != nullptr && var == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        sp.chg[(sp.gen + 1) % 3] = 0;
+        if (sp.force) sp.chg[sp.gen % 3] = 1;
+    }
     if ((int)blockIdx.x < prim_blocks) {
         const int lane = threadIdx.x & 63;
         const int pi = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
@@ -59,6 +63,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         double v0 = 0.0, b0 = 0.0;
         double vabs = 0.0;    // SERIES: sum of |v_i| over this lane's sine coefficients
         int idx0 = -1;
+        bool changed = false;
         for (int i = lane; i < nf; i += 64) {
             const sg_field r = sp.fref[pr.f0 + i];
             double v = r.a;
@@ -68,6 +73,10 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
                 v = r.a + r.b * pv;
             }
             fv[pr.f0 + i] = v;
+            // bitwise comparison (a NaN field always counts as changed)
+            if (sp.fprev != nullptr && var == 0 &&
+                __double_as_longlong(sp.fprev[pr.f0 + i]) != __double_as_longlong(v))
+                changed = true;
             if (i >= 2 && i < 2 + pr.nvert) vabs += fabs(v);
             if (i == lane) {
                 v0 = v;
@@ -75,6 +84,9 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
                 b0 = r.b;
             }
         }
+        // a plain store (every writer writes 1): an atomic from each of
+        // thousands of primitives to one address serializes
+        if (__ballot(changed) != 0 && lane == 0) sp.chg[sp.gen % 3] = 1;
         const double inf = __builtin_huge_val();
         double4 b = make_double4(-inf, inf, -inf, inf);
         // lanes 0-3 fetch field f0 + koff: a box's u0 u1 v0 v1, otherwise the
@@ -314,14 +326,15 @@ hipError_t launch_stage(const StageParams& sp, int nvariant, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st) {
+hipError_t launch_column(int mode, int tree, int variant, const KParams& kp, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1) {
     switch (mode) {
-        case MODE_EPS: return launch_mode<MODE_EPS>(tree, variant, kp, st);
-        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(tree, variant, kp, st);
-        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(tree, variant, kp, st);
-        case MODE_VJP_SPARSE: return launch_mode<MODE_VJP_SPARSE>(tree, variant, kp, st);
-        case MODE_FD_SPARSE: return launch_mode<MODE_FD_SPARSE>(tree, variant, kp, st);
-        default: return launch_mode<MODE_FD>(tree, variant, kp, st);
+        case MODE_EPS: return launch_mode<MODE_EPS>(tree, variant, kp, st, e0, e1);
+        case MODE_VJP_FIELDS: return launch_mode<MODE_VJP_FIELDS>(tree, variant, kp, st, e0, e1);
+        case MODE_VJP_GEPS: return launch_mode<MODE_VJP_GEPS>(tree, variant, kp, st, e0, e1);
+        case MODE_VJP_SPARSE: return launch_mode<MODE_VJP_SPARSE>(tree, variant, kp, st, e0, e1);
+        case MODE_FD_SPARSE: return launch_mode<MODE_FD_SPARSE>(tree, variant, kp, st, e0, e1);
+        default: return launch_mode<MODE_FD>(tree, variant, kp, st, e0, e1);
     }
 }
 

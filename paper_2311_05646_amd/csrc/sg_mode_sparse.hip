@@ -3,6 +3,6 @@
 
 namespace sg {
 
-template hipError_t launch_mode<MODE_VJP_SPARSE>(int, int, const KParams&, hipStream_t);
+template hipError_t launch_mode<MODE_VJP_SPARSE>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace sg

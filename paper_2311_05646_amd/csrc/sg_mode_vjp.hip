@@ -3,7 +3,7 @@
 
 namespace sg {
 
-template hipError_t launch_mode<MODE_VJP_FIELDS>(int, int, const KParams&, hipStream_t);
+template hipError_t launch_mode<MODE_VJP_FIELDS>(int, int, const KParams&, hipStream_t, hipEvent_t, hipEvent_t);
 
 hipError_t launch_column_batch(int tree, int variant, const KParams* plist, const int* first, int nreq,
                                int64_t blocks, hipStream_t st) {

@@ -51,6 +51,7 @@ struct sg_scene {
     std::vector<sg::DevClass> classes;
     std::vector<sg_field> fields;
     int block_x = 0, nseg = 0;        // 0: automatic
+    bool linear_tiles = true;         // eps_build on linear tiles (SG_EPS_RECT_TILES=1 at creation: off)
     // device tables
     double* d_lat = nullptr;          // per component: uc uw vc vw wc ww
     int64_t lat_off[sg::kMaxComp][6] = {};
@@ -79,6 +80,15 @@ struct sg_scene {
     // a sine-series term): the VJP spreads its atomics over kGradSpread copies
     bool spread = false;
     double* d_gspread = nullptr;             // kGradSpread x n
+    // F cache (eps_build, eps_grad_vjp, eps_grad_vjp_geps): the in-plane
+    // sums of every sample (ncomp x nclass x nu nv FP64) and the fields they
+    // were computed from, allocated at first use; the stage kernel of call
+    // `fgen` compares the fields and flags d_chg[fgen % 3]
+    bool fcache = true;                      // by feature set; SG_F_CACHE=0 / 1 at creation: off / on
+    double* d_fplane = nullptr;
+    double* d_fprev = nullptr;
+    int32_t* d_chg = nullptr;
+    int32_t fgen = 0;
     // sparse FD: the primitives (device order) whose fields reference each
     // parameter, CSR; and the parameters an extrusion bound references
     std::vector<int32_t> kprim_off, kprim;
@@ -104,8 +114,9 @@ struct sg_scene {
 namespace sg {
 // launch parameters of a scene's kernels, pointing at its own staging buffers
 StageParams stage_params(sg_scene* s, const double* dp);
-// target_blocks: the block count the automatic column split aims for
-KParams column_params(sg_scene* s, int64_t target_blocks = 768);
+// target_blocks: the block count the automatic column split aims for;
+// linear: linear tiles where the scene's rows are contiguous
+KParams column_params(sg_scene* s, int64_t target_blocks = 768, bool linear = false);
 // bytes of device staging one gradient evaluation of the scene needs
 int64_t staging_bytes(const sg_scene* s);
 }  // namespace sg
