@@ -112,6 +112,7 @@ static void free_scene(sg_scene* s) {
     hipFree(s->d_gspread);
     hipFree(s->d_fplane);
     hipFree(s->d_fprev);
+    hipFree(s->d_grun);
     hipFree(s->d_chg);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
@@ -729,6 +730,21 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         sp.tables = 1;
         e = launch_stage(sp, 1, nullptr);
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        // runs of equal group codes: grun[comp][g] = the first group after g
+        // whose code differs (eps_build stores a run with no per-group code)
+        const int ngw = (s->nw + kGroup - 1) / kGroup;
+        std::vector<uint32_t> gc((size_t)s->ncomp * ngw);
+        std::vector<int32_t> run(gc.size());
+        if (e == hipSuccess) e = hipMemcpy(gc.data(), s->d_gcode[0], gc.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) {
+            for (int c = 0; c < s->ncomp; ++c) {
+                const uint32_t* g = gc.data() + (size_t)c * ngw;
+                int32_t* r = run.data() + (size_t)c * ngw;
+                for (int i = ngw - 1; i >= 0; --i) r[i] = (i + 1 < ngw && g[i + 1] == g[i]) ? r[i + 1] : i + 1;
+            }
+            e = hipMalloc((void**)&s->d_grun, run.size() * sizeof(int32_t));
+            if (e == hipSuccess) e = hipMemcpy(s->d_grun, run.data(), run.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        }
     }
     if (e != hipSuccess) {
         free_scene(s);
@@ -901,6 +917,7 @@ KParams sg::column_params(sg_scene* s, int64_t target_blocks, bool linear) {
     kp.fref = s->d_fref;
     kp.consts = s->d_consts;
     kp.gseg = s->d_gseg;
+    kp.grun = s->d_grun;
     kp.fval = s->d_fval[0];
     kp.bbox = s->d_bbox[0];
     kp.prec = s->d_prec[0];

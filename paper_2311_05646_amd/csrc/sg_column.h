@@ -1303,7 +1303,22 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) F[c] = (c < P.nclass) ? P.fplane[fidx + (int64_t)c * nuv] : 0.0;
     }
-    if constexpr (VJP) {
+    // feature sets that use the F cache: the first loads go out before the
+    // staging only when F comes from the planes; an evaluating call issues them
+    // after its FP64 in-plane sums, so the loads' registers are not live during
+    // the evaluation (which lets the kernel fit one more wavefront per SIMD)
+    constexpr bool CACHED_SET = (TYPES & (T_ELL | T_POLAR | T_SERIES)) != 0 && !SPARSE;
+    if constexpr (VJP && CACHED_SET) {
+        if (cached) {
+            inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
+                                                  s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads, &live,
+                                                  false);
+        } else {
+            inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
+                                                  s_cand, s_cnt, s_rec, F, ncand, staged_all, [] {}, &live, true);
+            first_loads();
+        }
+    } else if constexpr (VJP) {
         inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
                                               s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads, &live,
                                               !cached);
@@ -1408,10 +1423,61 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
         const uint32_t out_lane = (uint32_t)b0 * 4;
         uint32_t cur = 0xFFFFFFFFu;    // mask of the current run (none yet)
         float run_out = 0.0f;
+        // scalar bookkeeping kept to a minimum (the scalar unit is shared by
+        // the CU's wavefronts): the group's resource and the next group's code
+        // advance incrementally, and a whole group's stores go out unguarded
+        const int64_t gbytes = (int64_t)kGroup * out_step;
+        const char* ob = outb + (int64_t)w0 * out_step;
+        int64_t left = out_bytes - (int64_t)w0 * out_step;
+        int gi = w0 / kGroup;          // segments start at a group boundary
+        uint32_t gc_next = combine(gcode[gi], FDM ? gcode2[gi] : 0u);
+        // eps_build with static codes: a run of full groups with one binary
+        // code is one value and a loop of stores (one resource for the run,
+        // the step offset in the scalar offset, the lanes' q offsets fixed)
+        const ConstU32 grun = const_space<ConstU32>(P.grun != nullptr ? P.grun + (int64_t)comp * ngw : nullptr);
+        const int gfull = w1 / kGroup;     // groups [w0 / kGroup, gfull) hold kGroup steps of the segment
+        uint32_t vq[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) vq[q] = out_lane + (uint32_t)(q * out_step);
         for (int w = w0; w < w1; w += kGroup) {
-            const int64_t off = (int64_t)w * out_step;
-            const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(outb + off, out_bytes - off);
-            const uint32_t gc = group_code(w);
+            if constexpr (MODE == MODE_EPS) {
+                const uint32_t gc = gc_next;
+                if (P.grun != nullptr && !(gc & kCodeGeneral) && gi < gfull) {
+                    // groups [gi, ge): code gc, all full; at most 2^31 bytes of offsets
+                    const int64_t capg = ((int64_t)0x7FFFFFFF - 3 * out_step) / gbytes;
+                    const int cap = (int)(capg < (1 << 20) ? capg : (1 << 20));
+                    const int ge = min(min((int)grun[gi], gfull), gi + max(cap, 1));
+                    if (gc != cur) {
+                        double Z[NC];
+                        mask_z<NC>(gc & 0xFFu, Z);
+                        run_out = value(Z, Z);
+                        cur = gc;
+                    }
+                    if (act) {
+                        const __amdgpu_buffer_rsrc_t rr = buffer_rsrc(ob, (int64_t)(ge - gi) * gbytes);
+                        uint32_t so = 0;
+                        for (int g = gi; g < ge; ++g) {
+#pragma unroll
+                            for (int q = 0; q < kGroup; ++q)
+                                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, run_out), rr,
+                                                                      vq[q], (int)so, 2);
+                            so += (uint32_t)gbytes;
+                        }
+                    }
+                    ob += (int64_t)(ge - gi) * gbytes;
+                    left -= (int64_t)(ge - gi) * gbytes;
+                    w = (ge - 1) * kGroup;          // the loop adds kGroup
+                    gi = min(ge, ngw - 1);
+                    gc_next = gcode[gi];
+                    continue;
+                }
+            }
+            const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(ob, left);
+            const uint32_t gc = gc_next;
+            gi = min(gi + 1, ngw - 1);
+            gc_next = combine(gcode[gi], FDM ? gcode2[gi] : 0u);
+            ob += gbytes;
+            left -= gbytes;
             float out[kGroup];
             if (!(gc & kCodeGeneral) && w + kGroup <= w1) {
                 if (gc != cur) {
@@ -1452,11 +1518,18 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                 // its lines leave the caches at once instead of being written
                 // back while the next kernel streams its own inputs
                 constexpr int kStorePolicy = (MODE == MODE_EPS) ? 2 : 0;
+                if (w + kGroup <= w1) {
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q)
-                    if (w + q < w1)
+                    for (int q = 0; q < kGroup; ++q)
                         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[q]), ro, out_lane,
                                                               (int)(q * out_step), kStorePolicy);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q)
+                        if (w + q < w1)
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, out[q]), ro, out_lane,
+                                                                  (int)(q * out_step), kStorePolicy);
+                }
             }
         }
         return;

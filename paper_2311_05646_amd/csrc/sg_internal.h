@@ -182,6 +182,7 @@ struct KParams {
     const uint32_t* code;        // step codes [comp][w]
     const uint32_t* code2;
     const uint32_t* gcode;       // group codes [comp][group]
+    const int32_t* grun;         // [comp][group]: the first group after it with another code (nullptr: none)
     const uint32_t* gcode2;
     float* out;                  // eps (MODE_EPS) or difference plane (MODE_FD)
     const float2* ef[kMaxComp];

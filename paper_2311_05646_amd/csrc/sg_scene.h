@@ -67,6 +67,7 @@ struct sg_scene {
     double* d_ztab[2] = {nullptr, nullptr};
     uint32_t* d_code[2] = {nullptr, nullptr};   // column-step codes
     uint32_t* d_gcode[2] = {nullptr, nullptr};  // group codes
+    int32_t* d_grun = nullptr;                  // static codes only: ends of the runs of equal group codes
     double* d_grad = nullptr;
     // no extrusion bound references a parameter: the extrusion tables and
     // step / group codes (index 0) are computed once, at scene creation, and
