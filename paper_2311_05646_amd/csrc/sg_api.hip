@@ -113,6 +113,7 @@ static void free_scene(sg_scene* s) {
     hipFree(s->d_fplane);
     hipFree(s->d_fprev);
     hipFree(s->d_grun);
+    hipFree(s->d_tlist);
     hipFree(s->d_chg);
     hipFree(s->d_kprim_off);
     hipFree(s->d_kprim);
@@ -992,6 +993,19 @@ static sg_status fcache_prepare(sg_scene* s, StageParams& sp, KParams& kp, hipSt
         HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_chg), 0.0, 2, st));     // all-zero bits
         force = 1;
     }
+    // candidate lists for the rectangular split (the gradient's); a larger
+    // split (set_launch) reallocates them, and the header then reads 0
+    const KParams kr = column_params(s);
+    const int64_t tiles = (int64_t)kr.ncomp * kr.tiles_u * kr.tiles_v;
+    if (tiles > s->tlist_tiles) {
+        hipFree(s->d_tlist);
+        s->d_tlist = nullptr;
+        s->tlist_tiles = 0;
+        const int64_t words = 1 + tiles * (1 + kStageRec);
+        HIP_OK(hipMalloc((void**)&s->d_tlist, ((words + 1) / 2) * 2 * sizeof(int32_t)));
+        HIP_OK(launch_fill(reinterpret_cast<double*>(s->d_tlist), 0.0, 1, st));     // header 0: no lists
+        s->tlist_tiles = tiles;
+    }
     const int gen = s->fgen;
     s->fgen = (gen + 1) % 3;
     sp.fprev = s->d_fprev;
@@ -1003,6 +1017,7 @@ static sg_status fcache_prepare(sg_scene* s, StageParams& sp, KParams& kp, hipSt
     kp.chg = s->d_chg;
     kp.gen = gen;
     kp.nfield = (int32_t)s->nfield;
+    kp.tlist = s->d_tlist;
     return SG_OK;
 }
 

@@ -1310,9 +1310,24 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     constexpr bool CACHED_SET = (TYPES & (T_ELL | T_POLAR | T_SERIES)) != 0 && !SPARSE;
     if constexpr (VJP && CACHED_SET) {
         if (cached) {
-            inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
-                                                  s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads, &live,
-                                                  false);
+            // the tile's candidates from the list the evaluating call kept (no scan)
+            bool listed = false;
+            if (P.tlist != nullptr && !P.linear && __builtin_amdgcn_readfirstlane(P.tlist[0]) == P.tu) {
+                const int32_t* tl = P.tlist + 1 + (int64_t)(b / P.nseg) * (1 + kStageRec);
+                const int cnt = __builtin_amdgcn_readfirstlane(tl[0]);
+                if (cnt >= 0) {
+                    if (tid < cnt) s_cand[tid] = tl[1 + tid];
+                    stage_cands(P.prec, s_cand, 0, cnt, s_rec);     // barriers before and after
+                    ncand = cnt;
+                    staged_all = true;
+                    listed = true;
+                    first_loads();
+                }
+            }
+            if (!listed)
+                inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc,
+                                                      G.vw, s_cand, s_cnt, s_rec, F, ncand, staged_all, first_loads,
+                                                      &live, false);
         } else {
             inplane_sums<NC, TYPES, SIGS, SPARSE>(P, P.bbox, P.prec, P.fval, G.T, comp, G.uu, G.uc, G.uw, G.vc, G.vw,
                                                   s_cand, s_cnt, s_rec, F, ncand, staged_all, [] {}, &live, true);
@@ -1335,6 +1350,15 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                         if (c < P.nclass) P.fplane[fidx + (int64_t)c * nuv] = F[c];
                 }
                 for (int i = b * kBlock + tid; i < P.nfield; i += (int)gridDim.x * kBlock) P.fprev[i] = P.fval[i];
+                if (P.tlist != nullptr) {
+                    // the tile's candidates (s_cand holds them when they fit one staging round)
+                    if (b == 0 && tid == 0) P.tlist[0] = P.linear ? -1 : P.tu;
+                    if (!P.linear && seg == 0) {
+                        int32_t* tl = P.tlist + 1 + (int64_t)(b / P.nseg) * (1 + kStageRec);
+                        if (tid == 0) tl[0] = staged_all ? ncand : -1;
+                        if (staged_all && tid < ncand) tl[1 + tid] = s_cand[tid];
+                    }
+                }
             }
         }
     }

@@ -216,6 +216,10 @@ struct KParams {
     double* fprev;
     const int32_t* chg;
     int32_t gen, nfield;
+    // with the planes, each rectangular tile's candidate list: tlist[0] = the
+    // tile width the lists are for (0 or -1: none), then per tile (block / nseg) a
+    // count (-1: more than one staging round) and kStageRec primitive indices
+    int32_t* tlist;
 };
 
 // kernel launchers (sg_kernels.hip)

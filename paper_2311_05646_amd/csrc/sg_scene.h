@@ -90,6 +90,8 @@ struct sg_scene {
     double* d_fprev = nullptr;
     int32_t* d_chg = nullptr;
     int32_t fgen = 0;
+    int32_t* d_tlist = nullptr;              // the tiles' candidate lists (room for tlist_tiles tiles)
+    int64_t tlist_tiles = 0;
     // sparse FD: the primitives (device order) whose fields reference each
     // parameter, CSR; and the parameters an extrusion bound references
     std::vector<int32_t> kprim_off, kprim;
