@@ -82,6 +82,11 @@ enum {
  *                                               the polar coordinates about (x0, y0),
  *                                               R = R0 + sum_n c_n cos(n theta + pi) + s_n sin(n theta + pi);
  *                                               sigma[0] boundary (FIXED k), sigma[2] z
+ *   SG_PRIM_POLAR2D x0 y0 R delta z0 z1         (nvert = alpha, 1 <= alpha <= 64)
+ *                                               Polar2D: sigma_k(R (1 + delta cos(alpha theta)) - r),
+ *                                               r and theta the polar coordinates about (x0, y0)
+ *                                               (theta over the full turn, so alpha is an integer);
+ *                                               sigma[0] boundary (FIXED k), sigma[2] z
  *   SG_PRIM_SERIES  xs xe v_1..v_K z0 z1        (nvert = K, 1 <= K <= 4096)
  *                                               two-sided boundary with the sine series of
  *                                               eq:taper_boundary: Rect1D(x; xs, xe)
@@ -94,7 +99,7 @@ enum {
  * z0 z1 are the extrusion along z (Rect1D in z), used when bounded[2] != 0.
  * In 2D scenes (dim = 2) nothing may be bounded along z. */
 enum { SG_PRIM_BOX = 0, SG_PRIM_ELLIPSE = 1, SG_PRIM_POLY = 2, SG_PRIM_GCART = 3, SG_PRIM_POLAR = 4,
-       SG_PRIM_SERIES = 5 };
+       SG_PRIM_SERIES = 5, SG_PRIM_POLAR2D = 6 };
 
 /* sigma_k kinds (Tab. nonlinearfunctions).  sigmoid and erf are taken as exactly
  * 0 / 1 beyond |k x| = 24 / 6 (tails below 4e-11 / 2e-17). */

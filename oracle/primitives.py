@@ -214,6 +214,38 @@ def polar(prim, vals, pts):
     return f * zv, out
 
 
+def polar2d(prim, vals, pts):
+    """Polar2D (Tab. autodiffgeo): sigma_k(R (1 + delta cos(alpha theta)) - r)
+    with r, theta the polar coordinates of the sample about (x0, y0) (note 5
+    and 6 of the table; theta = atan2(y - y0, x - x0), the arctan of the ratio
+    over the full turn) and alpha a positive integer (the lobes of a
+    star-convex shape; nvert = alpha).  Fields x0 y0 R delta z0 z1.  At the
+    center (r = 0) theta is taken as 0 and the center partials as 0."""
+    alpha = int(prim["nvert"])
+    x0, y0, R, delta = vals[0], vals[1], vals[2], vals[3]
+    (xc, xw), (yc, _) = pts["x"], pts["y"]
+    dx, dy = xc - x0, yc - y0
+    r = np.hypot(dx, dy)
+    th = np.arctan2(dy, dx)
+    ca, sa = np.cos(alpha * th), np.sin(alpha * th)
+    Rth = R * (1.0 + delta * ca)
+    dR = -R * delta * alpha * sa               # d R(theta) / d theta
+    kind = prim["sigma"][0][0]
+    k = kval(prim["sigma"][0], xw)
+    t = k * (Rth - r)
+    f = sigma(kind, t)
+    df = k * dsigma(kind, t)                  # d f / d (R(theta) - r)
+    safe = np.where(r > 0.0, r, 1.0)
+    # d r / d x0 = -dx / r, d theta / d x0 = dy / r^2 (and the y0 pair)
+    d_x0 = np.where(r > 0.0, dR * dy / (safe * safe) + dx / safe, 0.0)
+    d_y0 = np.where(r > 0.0, -dR * dx / (safe * safe) + dy / safe, 0.0)
+    zv, zparts = _z_factor(prim, vals, pts, 4)
+    g = df * zv
+    out = [(0, g * d_x0), (1, g * d_y0), (2, g * (1.0 + delta * ca)), (3, g * R * ca)]
+    out += [(fi, f * d) for fi, d in zparts]
+    return f * zv, out
+
+
 def series(prim, vals, pts):
     """Two-sided GeneralCartesian2D whose boundary is the taper's sine series
     (eq:taper_boundary): Rect1D(x; xs, xe) sigma_k(f(x) - (y - yc))
@@ -249,7 +281,8 @@ def series(prim, vals, pts):
     return rx * fy * zv, out
 
 
-EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart, "polar": polar, "series": series}
+EVAL = {"box": box, "ellipse": ellipse, "poly": poly, "gcart": gcart, "polar": polar, "polar2d": polar2d,
+        "series": series}
 
 
 def evaluate(prim, vals, pts):
@@ -290,6 +323,12 @@ def bbox(prim, vals, wmax):
         lo[0], hi[0] = vals[0] - rmax, vals[0] + rmax
         lo[1], hi[1] = vals[1] - rmax, vals[1] + rmax
         zf = 3 + 2 * N
+    elif t == "polar2d":
+        # R (1 + delta cos) <= R (1 + |delta|) for R >= 0, and <= |R| (1 + |delta|) always
+        rmax = max(abs(vals[2]) * (1.0 + abs(vals[3])), 0.0) + reach(prim["sigma"][0], 0)
+        lo[0], hi[0] = vals[0] - rmax, vals[0] + rmax
+        lo[1], hi[1] = vals[1] - rmax, vals[1] + rmax
+        zf = 4
     elif t == "series":
         # |f| <= the larger end of the linear ramp over [xs, xe] + sum |v_i| (envelope <= 1)
         K = prim["nvert"]

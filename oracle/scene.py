@@ -64,7 +64,7 @@ def check_scene(desc):
         raise ValueError("a primitive appears twice in the tree")
     for i in seen:
         pr = desc["prims"][i]
-        if pr["type"] in ("ellipse", "poly", "polar") and pr["sigma"][0][1] != "fixed":
+        if pr["type"] in ("ellipse", "poly", "polar", "polar2d") and pr["sigma"][0][1] != "fixed":
             raise ValueError("radial / oblique sigma arguments need a fixed k")
         for a, b, idx in pr["fields"]:
             if idx >= desc["n_params"]:

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("SG_LIB_PATH") or os.path.join(HERE, "libshapegrad.so"
 SG_OK, SG_EAGAIN = 0, 1
 STATUS = {0: "SG_OK", 1: "SG_EAGAIN", -1: "SG_E_INVALID", -2: "SG_E_NOMEM", -3: "SG_E_TOO_LARGE",
           -4: "SG_E_DEVICE", -5: "SG_E_CANCELLED", -6: "SG_E_TIMEOUT", -7: "SG_E_UNSUPPORTED"}
-PRIM = {"box": 0, "ellipse": 1, "poly": 2, "gcart": 3, "polar": 4, "series": 5}
+PRIM = {"box": 0, "ellipse": 1, "poly": 2, "gcart": 3, "polar": 4, "series": 5, "polar2d": 6}
 SIGMA = {"sigmoid": 0, "erf": 1, "sin": 2, "linear": 3, "quadratic": 4}
 KMODE = {"local": 0, "fixed": 1}
 OP = {"union": 0, "intersection": 1, "difference": 2, "levels": 3}

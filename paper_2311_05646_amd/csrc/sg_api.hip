@@ -148,6 +148,7 @@ static int expected_nfield(const sg_prim_desc& p) {
         case SG_PRIM_GCART: return 2 * p.nvert + 4;
         case SG_PRIM_POLAR: return 2 * p.nvert + 5;
         case SG_PRIM_SERIES: return p.nvert + 4;
+        case SG_PRIM_POLAR2D: return 6;
         default: return -1;
     }
 }
@@ -160,6 +161,7 @@ static int zfield(const sg_prim_desc& p) {
         case SG_PRIM_POLY: return 2 * p.nvert;
         case SG_PRIM_POLAR: return 2 * p.nvert + 3;
         case SG_PRIM_SERIES: return p.nvert + 2;
+        case SG_PRIM_POLAR2D: return 4;
         default: return 2 * p.nvert + 2;
     }
 }
@@ -214,6 +216,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         if (p.type == SG_PRIM_GCART && (p.nvert < 2 || p.nvert > 100000)) return fail(SG_E_INVALID, "gcart %d: nvert", i);
         if (p.type == SG_PRIM_POLAR && (p.nvert < 1 || p.nvert > 29)) return fail(SG_E_INVALID, "polar %d: order", i);
         if (p.type == SG_PRIM_SERIES && (p.nvert < 1 || p.nvert > 4096)) return fail(SG_E_INVALID, "series %d: terms", i);
+        if (p.type == SG_PRIM_POLAR2D && (p.nvert < 1 || p.nvert > 64)) return fail(SG_E_INVALID, "polar2d %d: alpha", i);
         if (p.nfield != nf) return fail(SG_E_INVALID, "primitive %d: nfield %d, expected %d", i, p.nfield, nf);
         if (p.field_off < 0 || p.field_off + nf > d->nfield) return fail(SG_E_INVALID, "primitive %d: fields", i);
         const int nc = p.type == SG_PRIM_ELLIPSE ? 2 : p.type == SG_PRIM_GCART ? p.nvert : p.type == SG_PRIM_SERIES ? 5 : 0;
@@ -226,7 +229,8 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             if (used && bnd && !valid_sigma(p.sigma[a])) return fail(SG_E_INVALID, "primitive %d: sigma[%d]", i, a);
         }
         if (d->dim == 2 && p.bounded[2]) return fail(SG_E_INVALID, "primitive %d: bounded along z in a 2D scene", i);
-        if ((p.type == SG_PRIM_ELLIPSE || p.type == SG_PRIM_POLY || p.type == SG_PRIM_POLAR) &&
+        if ((p.type == SG_PRIM_ELLIPSE || p.type == SG_PRIM_POLY || p.type == SG_PRIM_POLAR ||
+             p.type == SG_PRIM_POLAR2D) &&
             p.sigma[0].kmode != SG_K_FIXED)
             return fail(SG_E_INVALID, "primitive %d: radial/oblique boundary needs a FIXED k", i);
         if (p.type == SG_PRIM_ELLIPSE) {
@@ -624,7 +628,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
         for (int i = 0; i < d->nprim; ++i) {
             if (!used[i]) continue;
             const sg_prim_desc& p = d->prims[i];
-            tmask |= 1 << p.type;
+            tmask |= p.type == SG_PRIM_POLAR2D ? T_POLAR : 1 << p.type;     // one radial feature set
             if (p.type == SG_PRIM_BOX) {
                 if (p.bounded[0]) smask |= sigma_bit(p.sigma[0].kind);
                 if (p.bounded[axis_v]) smask |= sigma_bit(p.sigma[axis_v].kind);

@@ -687,9 +687,37 @@ __device__ __forceinline__ void polar_emit(const KParams& P, const FieldWin& w, 
     }
 }
 
-template <int SIGS>
+// A wavefront's per-lane sums of the Fourier-coefficient partials over the
+// candidates it has processed, while they reference the same parameters (the
+// global shape coefficients of a lattice of scatterers): one reduction per
+// coefficient per wavefront instead of one per candidate.  kw is the first
+// such candidate's field window (its coefficient lanes are the key); n = 0:
+// empty.  Orders above kAccN take the per-candidate reductions.
+constexpr int kAccN = 6;
+struct PolarAcc {
+    float c[kAccN], s[kAccN];
+    int n;
+    FieldWin kw;
+};
+__device__ __forceinline__ void polar_acc_clear(PolarAcc& a) { a.n = 0; }
+
+// Reduces and emits the accumulated sums (then empty).
+__device__ __forceinline__ void polar_acc_flush(const KParams& P, PolarAcc& a, double* s_pacc, int* s_pkey) {
+    const int N = a.n;
+    if (N == 0) return;
+#pragma unroll
+    for (int n = 1; n <= kAccN; ++n) {
+        if (n <= N) {
+            polar_emit(P, a.kw, a.kw.base + 2 + n, n - 1, a.c[n - 1], s_pacc, s_pkey);
+            polar_emit(P, a.kw, a.kw.base + 2 + N + n, N + n - 1, a.s[n - 1], s_pacc, s_pkey);
+        }
+    }
+    a.n = 0;
+}
+
+template <int SIGS, bool ACC>
 __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& pr, const float* sAc,
-                                               const SampleLat& L, double* s_pacc, int* s_pkey) {
+                                               const SampleLat& L, double* s_pacc, int* s_pkey, PolarAcc& acc) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
     const int N = uniform_int(pr.nvert);
@@ -765,6 +793,36 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
         cn[q] = 1.0f;
         sn[q] = 0.0f;
     }
+    if (ACC && N <= kAccN) {
+        // into the wavefront's running sums when the coefficients reference the
+        // same parameters as the ones there (else those go out first)
+        const bool same = acc.n == N &&
+                          __ballot(lane >= 3 && lane < 3 + 2 * N && (w.idx != acc.kw.idx || w.b != acc.kw.b)) == 0;
+        if (!same) {
+            polar_acc_flush(P, acc, s_pacc, s_pkey);
+            acc.n = N;
+            acc.kw = w;
+#pragma unroll
+            for (int n = 0; n < kAccN; ++n) acc.c[n] = acc.s[n] = 0.0f;
+        }
+#pragma unroll
+        for (int n = 1; n <= kAccN; ++n) {
+            if (n <= N) {
+                float pc = 0.0f, ps = 0.0f;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const float c = cn[q] * c1[q] - sn[q] * s1[q];
+                    sn[q] = sn[q] * c1[q] + cn[q] * s1[q];
+                    cn[q] = c;
+                    pc -= g[q] * cn[q];
+                    ps -= g[q] * sn[q];
+                }
+                acc.c[n - 1] += pc;
+                acc.s[n - 1] += ps;
+            }
+        }
+        return;
+    }
     for (int n = 1; n <= N; ++n) {
         float pc = 0.0f, ps = 0.0f;
 #pragma unroll
@@ -778,6 +836,57 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
         polar_emit(P, w, pr.f0 + 2 + n, n - 1, pc, s_pacc, s_pkey);
         polar_emit(P, w, pr.f0 + 2 + N + n, N + n - 1, ps, s_pacc, s_pkey);
     }
+}
+
+// Partials of a Polar2D boundary, times the column sums, over the kBlock
+// samples of the tile handled by this wavefront: with t = k (R(theta) - r),
+// R(theta) = R (1 + delta cos(alpha theta)), d / d R = 1 + delta cos(alpha
+// theta), d / d delta = R cos(alpha theta), and the center pair as for the
+// Fourier radius with R'(theta) = -R delta alpha sin(alpha theta).  FP32 after
+// the FP64 coordinate differences.
+template <int SIGS>
+__device__ __forceinline__ void polar2d_partials(const KParams& P, const DevPrim& pr, const float* sAc,
+                                                 const SampleLat& L) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int A = uniform_int(pr.nvert);
+    FieldWin w;           // x0, y0, R, delta
+    load_win(P, w, pr.f0, pr.f0 + 4);
+    const double* f = P.fval + pr.f0;
+    const float k0 = (float)pr.k0;
+    const float R = (float)f[2], dl = (float)f[3];
+    float sx = 0.0f, sy = 0.0f, sR = 0.0f, sd = 0.0f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int t = q * 64 + lane;
+        const float a = sAc[t];
+        if (__ballot(a != 0.0f) == 0) continue;
+        if (a != 0.0f) {
+            const float dx = (float)(L.uc(t) - f[0]), dy = (float)(L.vc(t) - f[1]);
+            const float r = sqrtf(dx * dx + dy * dy);
+            const float ir = r > 0.0f ? 1.0f / r : 0.0f;
+            const float c1 = r > 0.0f ? dx * ir : 1.0f, s1 = r > 0.0f ? dy * ir : 0.0f;
+            float cn = 1.0f, sn = 0.0f;
+            for (int n = 0; n < A; ++n) {
+                const float c = cn * c1 - sn * s1;
+                sn = sn * c1 + cn * s1;
+                cn = c;
+            }
+            const float Rth = R * (1.0f + dl * cn);
+            const float dR = -R * dl * (float)A * sn;
+            const float gg = a * k0 * sig_d32(pr.sk0, k0 * (Rth - r));     // a * d F / d (R(theta) - r)
+            if (r > 0.0f) {
+                sx += gg * (dR * s1 * ir + c1);
+                sy += gg * (-dR * c1 * ir + s1);
+            }
+            sR += gg * (1.0f + dl * cn);
+            sd += gg * R * cn;
+        }
+    }
+    emit_win(P, w, pr.f0, sx);
+    emit_win(P, w, pr.f0 + 1, sy);
+    emit_win(P, w, pr.f0 + 2, sR);
+    emit_win(P, w, pr.f0 + 3, sd);
 }
 
 // Partials of the taper's sine-series boundary, times the column sums, over
@@ -854,7 +963,8 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
 // the wavefront, and added with one atomic per parameter field.
 template <int TYPES, int SIGS>
 __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& cr, const float* sAc, const SampleLat& L,
-                               const Tile& T, int comp, int u0, float* sg, double* s_pacc, int* s_pkey) {
+                               const Tile& T, int comp, int u0, float* sg, double* s_pacc, int* s_pkey,
+                               PolarAcc& acc) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
     const DevPrim& pr = cr.pr;
@@ -942,8 +1052,14 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
         }
     }
     if constexpr ((TYPES & T_POLAR) != 0) {
+        if (type == SG_PRIM_POLAR2D) {
+            polar2d_partials<SIGS>(P, pr, sAc, L);
+            return;
+        }
         if (type == SG_PRIM_POLAR) {
-            polar_partials<SIGS>(P, pr, sAc, L, s_pacc, s_pkey);
+            // the running sums only in the Fourier feature set (the catch-all
+            // kernel has no registers to spare for them)
+            polar_partials<SIGS, TYPES == (T_BOX | T_POLAR)>(P, pr, sAc, L, s_pacc, s_pkey, acc);
             return;
         }
     }
@@ -987,10 +1103,11 @@ __device__ __forceinline__ void span_box(const KParams& P, const double* ucs, co
     vhi = vcs[v1];
 }
 
+template <bool LINEAR = false>
 __device__ __forceinline__ TileGeom tile_geom(const KParams& P, int b) {
     const int tid = threadIdx.x, wave = tid >> 6;
     TileGeom G;
-    if (P.linear) {
+    if (LINEAR && P.linear) {
         const int nuv = P.nu * P.nv;
         const int ti = b % P.tiles_u;
         G.comp = b / P.tiles_u;
@@ -1136,7 +1253,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     const int tid = threadIdx.x, wave = tid >> 6;
 
     const int seg = b % P.nseg;
-    const TileGeom G = tile_geom(P, b / P.nseg);
+    const TileGeom G = tile_geom<MODE == MODE_EPS>(P, b / P.nseg);     // linear tiles: eps_build only
     const int comp = G.comp;
     const bool act = G.act;
     const int ngw = (P.nw + kGroup - 1) / kGroup;
@@ -1291,7 +1408,10 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     // and stages the candidates (for the partials); otherwise the kernel
     // evaluates F and writes it there (and the fields it came from) for the
     // next call at the same p.
-    constexpr bool CACHE = (MODE == MODE_EPS || MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS);
+    // (not in the 8-class catch-all kernel, nor the catch-all backward of
+    // eps_grad_vjp_geps: their registers do not hold both prologues)
+    constexpr bool CACHE = (MODE == MODE_EPS || MODE == MODE_VJP_FIELDS || MODE == MODE_VJP_GEPS) &&
+                           TREE != TR_GEN8 && !(MODE == MODE_VJP_GEPS && TREE == TR_GEN4);
     const int64_t nuv = (int64_t)P.nu * P.nv;
     const int64_t fidx = (int64_t)comp * P.nclass * nuv + (int64_t)G.uu + (int64_t)G.vv * P.nu;
     bool cached = false;
@@ -1702,11 +1822,13 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                 s_pacc[tid] = 0.0;
             }
         }
+        PolarAcc pacc;
+        polar_acc_clear(pacc);
         if (staged_all) {
             __syncthreads();
             for (int j = wave; j < ncand; j += kBlock / 64)
                 block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0, sgw,
-                                            s_pacc, s_pkey);
+                                            s_pacc, s_pkey, pacc);
             series_split<TYPES, SIGS>(P, s_rec, ncand, sA, L);
         } else {
             for (int next = 0; next < P.nprim;) {
@@ -1717,12 +1839,13 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                     stage_cands(P.prec, s_cand, j0, nj, s_rec);
                     for (int j = wave; j < nj; j += kBlock / 64)
                         block_partials<TYPES, SIGS>(P, s_rec[j], sA + s_rec[j].pr.cls * kBlock, L, G.T, comp, u0,
-                                                    sgw, s_pacc, s_pkey);
+                                                    sgw, s_pacc, s_pkey, pacc);
                     series_split<TYPES, SIGS>(P, s_rec, nj, sA, L);
                 }
             }
         }
         if constexpr ((TYPES & T_POLAR) != 0) {
+            polar_acc_flush(P, pacc, s_pacc, s_pkey);
             // one atomic per combined coefficient parameter
             __syncthreads();
             if (tid < kPolarSlots && s_pkey[tid] >= 0 && s_pacc[tid] != 0.0)

@@ -308,6 +308,29 @@ __device__ __forceinline__ double polar_arg(const DevPrim& pr, const double* __r
     return pr.k0 * (R - r);
 }
 
+// Polar2D (Tab. autodiffgeo): the radius R (1 + delta cos(alpha theta)) about
+// (x0, y0), cos(alpha theta) by alpha rotations from (dx, dy) / r (theta = 0 at
+// the center); the sigma argument k (R(theta) - r).
+__device__ __forceinline__ double polar2d_arg(const DevPrim& pr, const double* __restrict__ fv, double uc,
+                                              double vc) {
+    // called for one primitive at a time by the whole wavefront: its fields
+    // sit at a uniform address
+    const int A = __builtin_amdgcn_readfirstlane(pr.nvert);
+    const ConstF64 f = const_space<ConstF64>(fv + __builtin_amdgcn_readfirstlane(pr.f0));
+    const double dx = uc - f[0], dy = vc - f[1];
+    const double r2 = dx * dx + dy * dy;
+    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double r = r2 * ir;
+    const double c1 = r2 > 0.0 ? dx * ir : 1.0, s1 = r2 > 0.0 ? dy * ir : 0.0;
+    double cn = 1.0, sn = 0.0;
+    for (int n = 0; n < A; ++n) {
+        const double c = cn * c1 - sn * s1;
+        sn = sn * c1 + cn * s1;
+        cn = c;
+    }
+    return pr.k0 * (f[2] * (1.0 + f[3] * cn) - r);
+}
+
 // Half-width f(x) of the taper's sine-series boundary (eq:taper_boundary):
 // phi = pi (x - x0) / L, sin i phi by repeated rotation from (cos phi, sin phi),
 // envelope 0.1 + 0.45 (1 - cos 2 phi) = 0.1 + 0.9 sin^2 phi.  cst: x0 L w_in w_out yc.
@@ -398,6 +421,7 @@ __device__ __forceinline__ double prim_value(const DevPrim& pr, const double* __
     }
     if constexpr ((TYPES & T_POLAR) != 0) {
         if (pr.type == SG_PRIM_POLAR) return sig_v<SIGS>(pr.sk0, polar_arg(pr, fv, uc, vc));
+        if (pr.type == SG_PRIM_POLAR2D) return sig_v<SIGS>(pr.sk0, polar2d_arg(pr, fv, uc, vc));
     }
     if constexpr ((TYPES & T_SERIES) != 0) {
         if (pr.type == SG_PRIM_SERIES) {
@@ -488,8 +512,8 @@ __device__ __forceinline__ double prim_value_live(const DevPrim& pr, const doubl
         }
     }
     if constexpr ((TYPES & T_POLAR) != 0) {
-        if (pr.type == SG_PRIM_POLAR) {
-            const double t = polar_arg(pr, fv, uc, vc);
+        if (pr.type == SG_PRIM_POLAR || pr.type == SG_PRIM_POLAR2D) {
+            const double t = pr.type == SG_PRIM_POLAR ? polar_arg(pr, fv, uc, vc) : polar2d_arg(pr, fv, uc, vc);
             live = sig_live<SIGS>(pr.sk0, t, kSupportSlack32);
             return sig_v<SIGS>(pr.sk0, t);
         }

@@ -55,6 +55,7 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             case SG_PRIM_ELLIPSE: nf = 5; break;
             case SG_PRIM_POLY: nf = 2 * pr.nvert + 2; break;
             case SG_PRIM_POLAR: nf = 2 * pr.nvert + 5; break;
+            case SG_PRIM_POLAR2D: nf = 6; break;
             case SG_PRIM_SERIES: nf = pr.nvert + 4; break;
             default: nf = 2 * pr.nvert + 4; break;
         }
@@ -140,6 +141,10 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             const double rb = fabs(0.5 * c[2] + 0.5 * (c[3] - c[2]) * (r1 - c[0]) / c[1]);
             const double R = fmax(ra, rb) + vabs + pr.reach1;
             b = make_double4(r0 - pr.reach0, r1 + pr.reach0, c[4] - R, c[4] + R);
+        } else if (pr.type == SG_PRIM_POLAR2D) {
+            // |R (1 + delta cos)| <= |R| (1 + |delta|): a square about the center
+            const double R = fabs(r2) * (1.0 + fabs(r3)) + pr.reach0;
+            b = make_double4(r0 - R, r0 + R, r1 - R, r1 + R);
         } else if (pr.type == SG_PRIM_POLAR) {
             // R(theta) <= R0 + sum_n |c_n| + |s_n|: a square about the center
             double av = (lane >= 3 && lane < 3 + 2 * pr.nvert) ? fabs(v0) : 0.0;

@@ -23,7 +23,7 @@ Scene description (plain Python data, consumed by the C-ABI marshalling in
                "children": [prim index | tree, ...]},
     }
 
-    prim = {"type": "box"|"ellipse"|"poly"|"gcart"|"polar"|"series",
+    prim = {"type": "box"|"ellipse"|"poly"|"gcart"|"polar"|"polar2d"|"series",
             "fields": [(a, b, idx), ...],   # value = a + b * p[idx]; idx < 0: a
             "consts": [float, ...],         # gcart vertex x's; ellipse aspect
             "nvert": int,
@@ -123,6 +123,48 @@ def polar(x0, y0, R0, cs, ss, z=None, sig=("sigmoid", "fixed", 50.0), sig_z=LIN)
     zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
     return {"type": "polar", "fields": [x0, y0, R0] + list(cs) + list(ss) + zf, "consts": [], "nvert": len(cs),
             "bounded": [True, True, z is not None], "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
+
+
+def polar2d(x0, y0, R, delta, alpha, z=None, sig=("sigmoid", "fixed", 50.0), sig_z=LIN):
+    """Polar2D: sigma_k(R (1 + delta cos(alpha theta)) - r) about (x0, y0), alpha a
+    positive integer (the star-convex shape of Tab. autodiffgeo)."""
+    assert int(alpha) == alpha and alpha >= 1
+    zf = [_NOF, _NOF] if z is None else [z[0], z[1]]
+    return {"type": "polar2d", "fields": [x0, y0, R, delta] + zf, "consts": [], "nvert": int(alpha),
+            "bounded": [True, True, z is not None], "sigma": [tuple(sig), tuple(sig), tuple(sig_z)]}
+
+
+def make_polar2d_small(seed=BASE_SEED + 17, dim=3):
+    """Star-convex Polar2D shapes (alpha = 3, 4, 5; R, delta, x0, y0 each a
+    parameter, the paper's example R = 0.5, delta = 0.2, alpha = 4 among
+    them) etched into a slab, a sigmoid boundary at k = 4 sqrt2 / dx and one
+    linear; Ex / Ey / Ez in 3D.  Not one of the paper's devices: a parity
+    case for the primitive."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    dx = 0.04
+    X = uniform_nodes(66, dx)
+    Y = uniform_nodes(61, dx)
+    if dim == 3:
+        Z = uniform_nodes(10, 0.03)
+        zc = Z[5]
+        zr = (K(zc - 0.0905), K(zc + 0.1005))
+    else:
+        Z, zr = np.array([0.0, 1.0]), None
+    k = 4.0 * math.sqrt(2.0) / dx
+    p, prims = [], [box(x=None, y=None, z=zr)]
+    shapes = [(0.72, 0.70, 0.50, 0.20, 4, ("sigmoid", "fixed", k)), (1.95, 0.62, 0.40, -0.15, 3, ("sigmoid", "fixed", k)),
+              (1.30, 1.72, 0.45, 0.25, 5, ("linear", "fixed", 1.0 / dx))]
+    for cx, cy, R, d, a, sig in shapes:
+        q = len(p)
+        p += [cx + rng.uniform(-0.01, 0.01), cy + rng.uniform(-0.01, 0.01), R, d]
+        prims.append(polar2d(P(q), P(q + 1), P(q + 2), P(q + 3), a, z=zr, sig=sig))
+    scene = {"name": "polar2d", "dim": dim, "nodes": [X, Y, Z],
+             "components": ("x", "y", "z") if dim == 3 else ("z",),
+             "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
+             "tree": {"op": "difference", "children": [0, {"op": "union", "children": list(range(1, len(prims)))}]}}
+    out = {"scene": scene, "p": np.array(p), "omega": _wl_omega(1.31), "h": 1e-7}
+    out["E"], out["A"] = make_fields(scene, seed)
+    return out
 
 
 def series(xs, xe, vs, x0, L, w_in, w_out, yc, z=None, sig_x=LIN, sig_y=LIN, sig_z=LIN):
@@ -793,6 +835,7 @@ CONFIGS = {
     "levels2": lambda: make_levels(dim=2), "levels3": lambda: make_levels(dim=3),
     "levels2_deep": lambda: make_levels(dim=2, deep=True),
     "blazed": make_blazed, "blazed_small": make_blazed_small,
+    "polar2d_small": make_polar2d_small, "polar2d_small2": lambda: make_polar2d_small(dim=2),
 }
 
 

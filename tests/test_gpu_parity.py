@@ -20,11 +20,12 @@ pytestmark = pytest.mark.gpu
 # blazed_small: the paper's three-level blazed-grating composition with etch
 # depths and the oxide thickness as parameters; zoo*_deep: six op nodes with
 # differences on both sides of a union; levels2_deep: a difference as one
-# material set of the non-binary union
+# material set of the non-binary union; polar2d_small*: star-convex Polar2D
+# shapes (alpha = 3, 4, 5, sigmoid and linear) etched into a slab, 3D and 2D
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
          "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
          "psgc3_small", "psgc3_small_local", "taper3_sine_small", "levels2", "levels3",
-         "blazed_small", "zoo2_deep", "zoo3_deep", "levels2_deep"]
+         "blazed_small", "zoo2_deep", "zoo3_deep", "levels2_deep", "polar2d_small", "polar2d_small2"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
 

@@ -1,10 +1,13 @@
 """Prop. 2 study (Sec. "Experimental choice of nonlinear function for
 Prop. 2", Fig. psgc_jac_fitting): on a plane of etched Fourier-radius
 scatterers with a global first cosine coefficient c_1, the AutoDiffGeo
-derivative map d eps / d c_1 (from the GPU map: central differences of
-eps_build, which is smooth in p) is fitted against the exact volume-weighted
+derivative map d eps / d c_1 (reverse mode of the GPU map: one
+eps_grad_vjp_geps call per sample, with grad_eps the unit vector of that
+sample, over the samples where the exact map or the map's central
+differences are nonzero) is fitted against the exact volume-weighted
 derivative map (the oracle's boundary integral of the covered fraction) with
-a zero-intercept linear model, per sigma kind and k.  Checked: the fitted
+a zero-intercept linear model, per sigma kind and k.  Checked: the
+reverse-mode map agrees with central differences of eps_build, the fitted
 slope grows with k for every kind (the paper's observation: the peak
 derivative grows with k), the maps are correlated, and the GPU gradient for
 c_1 equals the map contracted with g."""
@@ -44,13 +47,31 @@ def _exact_map(cfg):
     return -(d["eps_fg"] - d["eps_bg"]) * out
 
 
-def _ad_map(cfg, sc, h=5e-5):
+def _fd_map(cfg, sc, h=5e-5):
     p1, p2 = cfg["p"].copy(), cfg["p"].copy()
     p1[0] += h
     p2[0] -= h
     e1 = api().eps_build(sc, p1).double()
     e2 = api().eps_build(sc, p2).double()
     return ((e1 - e2) / (2 * h)).cpu().numpy()[0, 0]
+
+
+def _ad_map(cfg, sc, band):
+    """d eps / d c_1 at the samples of `band` by reverse mode: the gradient of
+    sum_x grad_eps(x) eps(x) with grad_eps the unit vector of one sample."""
+    p_dev = torch.tensor(cfg["p"], dtype=torch.float64, device="cuda")
+    geps = torch.zeros(sc.shape, dtype=torch.float32, device="cuda")
+    g = torch.empty(sc.n_params, dtype=torch.float64, device="cuda")
+    iy, ix = np.nonzero(band)
+    res = torch.empty(len(iy), dtype=torch.float64, device="cuda")
+    for k, (y, x) in enumerate(zip(iy.tolist(), ix.tolist())):
+        geps[0, 0, y, x] = 1.0
+        api().eps_grad_vjp_geps(sc, p_dev, geps, grad=g)
+        res[k] = g[0]
+        geps[0, 0, y, x] = 0.0
+    out = np.zeros(band.shape)
+    out[iy, ix] = res.cpu().numpy()
+    return out
 
 
 def test_prop2_fit_slope_and_rmse():
@@ -61,7 +82,10 @@ def test_prop2_fit_slope_and_rmse():
             cfg = W.make_prop2_plane(kind, kr)
             sc = api().Scene(cfg["scene"])
             fd = _exact_map(cfg)
-            ad = _ad_map(cfg, sc)
+            cd = _fd_map(cfg, sc)
+            ad = _ad_map(cfg, sc, (fd != 0.0) | (cd != 0.0))
+            # reverse mode against central differences of the same map (h^2 terms near kinks)
+            assert float(np.sum(ad * cd) / np.sqrt(np.sum(ad * ad) * np.sum(cd * cd))) > 0.999, (kind, kr)
             slope = float(np.sum(ad * fd) / np.sum(fd * fd))
             rmse = float(np.sqrt(np.mean((ad - slope * fd) ** 2)))
             nrmse = rmse / float(np.sqrt(np.mean(fd ** 2)))

@@ -54,6 +54,16 @@ def test_levels_fd_matches_analytic(dim):
     assert np.count_nonzero(ga) >= 12
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_polar2d_scene_fd_matches_analytic(dim):
+    cfg = W.make_polar2d_small(dim=dim)
+    g = S.sensitivity(cfg["E"], cfg["A"], cfg["omega"])
+    ga = S.grad_analytic(cfg["scene"], cfg["p"], g)
+    gf = S.grad_fd(cfg["scene"], cfg["p"], g, 1e-6)
+    assert _rel(gf, ga) < 1e-6
+    assert np.count_nonzero(ga) == cfg["scene"]["n_params"]
+
+
 def test_blazed_composition_fd_matches_analytic():
     # three op levels, etch depths and the oxide thickness as parameters
     cfg = W.make_blazed_small()

@@ -8,6 +8,11 @@ radius of eq:PSGCboundary):
 * rotating the sample about the center by phi and the coefficients by n phi
   (R'(theta) = R(theta - phi)) leaves the value unchanged, in every quadrant;
 * every analytic partial matches central differences of the value;
+of Polar2D (Tab. autodiffgeo, sigma_k(R (1 + delta cos(alpha theta)) - r)):
+with delta = 0 it is Circ2D, value and the x0, y0, R partials; on the rays
+theta = 0 and theta = pi / alpha the boundary sits at R (1 + delta) and
+R (1 - delta); it is the Fourier primitive with R0 = R and c_alpha = -R delta,
+in value; its partials match central differences;
 and of the taper's sine-series boundary (eq:taper_boundary): with no sine
 terms and equal end widths it is a box; at mid-length (envelope 1) the
 boundary sits where the series, evaluated by hand, puts it; its partials
@@ -94,6 +99,64 @@ def test_partials_match_central_differences(kind):
         vm[fi] -= h
         fd = (prm.polar(pr, vp, pts)[0] - prm.polar(pr, vm, pts)[0]) / (2 * h)
         assert np.max(np.abs(fd - d)) < 1e-5 * max(1.0, np.max(np.abs(d))), fi
+
+
+# ---- Polar2D (Tab. autodiffgeo)
+def test_polar2d_zero_delta_is_circ2d():
+    rng = np.random.default_rng(11)
+    x, y = rng.uniform(-0.5, 0.5, 500), rng.uniform(-0.5, 0.5, 500)
+    p2 = W.polar2d(W.K(0.03), W.K(-0.02), W.K(0.31), W.K(0.0), 4, sig=SIG)
+    ell = W.ellipse(W.K(0.03), W.K(-0.02), W.K(0.31), sig=SIG)
+    f2, q2 = prm.polar2d(p2, _vals(p2), _pts(x, y))
+    fe, qe = prm.ellipse(ell, _vals(ell), _pts(x, y))
+    assert np.max(np.abs(f2 - fe)) < 1e-14
+    d2, de = dict(q2), dict(qe)
+    for i in range(3):            # x0, y0, R <-> x0, y0, r
+        assert np.max(np.abs(d2[i] - de[i])) < 1e-10 * max(1.0, np.max(np.abs(de[i])))
+
+
+@pytest.mark.parametrize("kind", ["sigmoid", "linear"])
+@pytest.mark.parametrize("alpha", [3, 4])
+def test_polar2d_boundary_on_rays(kind, alpha):
+    # theta = 0: R (1 + delta); theta = pi / alpha: R (1 - delta); the paper's example R = 0.5, delta = 0.2
+    R, d, x0, y0 = 0.5, 0.2, 0.07, -0.04
+    pr = W.polar2d(W.K(x0), W.K(y0), W.K(R), W.K(d), alpha, sig=(kind, "fixed", 60.0))
+    th = np.pi / alpha
+    xs = [x0 + R * (1 + d), x0 + R * (1 - d) * np.cos(th)]
+    ys = [y0, y0 + R * (1 - d) * np.sin(th)]
+    f, _ = prm.polar2d(pr, _vals(pr), _pts(xs, ys))
+    assert np.max(np.abs(f - 0.5)) < 1e-12
+
+
+def test_polar2d_is_the_fourier_radius_with_one_product_coefficient():
+    rng = np.random.default_rng(12)
+    R, d, a = 0.27, -0.13, 5
+    x, y = 0.01 + rng.uniform(-0.4, 0.4, 600), -0.02 + rng.uniform(-0.4, 0.4, 600)
+    p2 = W.polar2d(W.K(0.01), W.K(-0.02), W.K(R), W.K(d), a, sig=SIG)
+    cs = [W.K(0.0)] * a
+    cs[a - 1] = W.K(-R * d)           # R(theta) = R0 - c_a cos(a theta) (the pi shift)
+    pf = W.polar(W.K(0.01), W.K(-0.02), W.K(R), cs, [W.K(0.0)] * a, sig=SIG)
+    f2, _ = prm.polar2d(p2, _vals(p2), _pts(x, y))
+    ff, _ = prm.polar(pf, _vals(pf), _pts(x, y))
+    assert np.max(np.abs(f2 - ff)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["sigmoid", "erf", "sin", "quadratic"])
+def test_polar2d_partials_match_central_differences(kind):
+    rng = np.random.default_rng(13)
+    vals0 = [0.01, -0.02, 0.3, 0.18, 0.0, 0.0]
+    pr = W.polar2d(W.K(0), W.K(0), W.K(0), W.K(0), 4, sig=(kind, "fixed", 25.0))
+    th = rng.uniform(-np.pi, np.pi, 300)
+    rr = 0.3 * (1 + 0.18 * np.cos(4 * th)) + rng.uniform(-0.05, 0.05, 300)
+    pts = _pts(0.01 + rr * np.cos(th), -0.02 + rr * np.sin(th))
+    _, parts = prm.polar2d(pr, vals0, pts)
+    h = 1e-6
+    for fi, dd in parts[:4]:
+        vp, vm = list(vals0), list(vals0)
+        vp[fi] += h
+        vm[fi] -= h
+        fd = (prm.polar2d(pr, vp, pts)[0] - prm.polar2d(pr, vm, pts)[0]) / (2 * h)
+        assert np.max(np.abs(fd - dd)) < 1e-5 * max(1.0, np.max(np.abs(dd))), fi
 
 
 # ---- the taper's sine-series boundary (eq:taper_boundary, eq:taper_eps)
