@@ -464,13 +464,13 @@ def _oracle_slice(i0_i1):
     return g, time.perf_counter() - t, E2.size
 
 
-def cpu_baseline(cfg, cols=25, single_chunks=8):
+def cpu_baseline(cfg, cols=25, single_chunks=24, reps=3):
     """The oracle (FP64 NumPy, not tuned) on this host: the taper split into
     x-slabs of `cols` columns (a uniform x lattice, so a slab's samples and
     their widths are exactly those of the whole grid).  One core runs
     `single_chunks` slabs; then a process pool on all allowed cores (at most
-    the 16 of one GPU's share) computes the whole gradient, which is compared
-    with the GPU's."""
+    the 16 of one GPU's share) computes the whole gradient `reps` times (about
+    25 s of CPU work in all), and the last is compared with the GPU's."""
     import multiprocessing as mp
     import numpy as np
     nx = len(cfg["scene"]["nodes"][0]) - 1
@@ -486,15 +486,16 @@ def cpu_baseline(cfg, cols=25, single_chunks=8):
     t1 = time.perf_counter() - t
     host = host_info()
     workers = max(1, min(CPU_WORKERS_MAX, host["cpus_allowed"] or 1))
-    t = time.perf_counter()
     with mp.get_context("fork").Pool(workers) as pool:
-        parts = pool.map(_oracle_slice, chunks, chunksize=1)
-    tall = time.perf_counter() - t
+        t = time.perf_counter()
+        for _ in range(reps):
+            parts = pool.map(_oracle_slice, chunks, chunksize=1)
+        tall = (time.perf_counter() - t) / reps
     grad = np.sum([g for g, _, _ in parts], axis=0)
     _CPU.clear()
     return {"value": 1.0 / tall, "unit": "evals/s", "cores": workers, "kind": "oracle",
             "sample": f"the whole taper gradient (eps + reverse mode, {total} samples) in {len(chunks)} x-slabs of "
-                      f"{cols} columns over a {workers}-process pool, {tall:.1f} s wall",
+                      f"{cols} columns over a {workers}-process pool, {reps} times, {tall:.2f} s wall each",
             "seconds_per_eval": tall,
             "single_core": {"value": 1.0 / (t1 * total / done), "cores": 1,
                             "sample": f"{single_chunks} x-slabs ({done} of {total} samples), {t1:.1f} s, scaled by "

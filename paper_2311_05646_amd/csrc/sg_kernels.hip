@@ -60,29 +60,51 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             default: nf = 2 * pr.nvert + 4; break;
         }
         // lane i resolves fields f0 + i, f0 + i + 64, ...; the first one stays
-        // in the lane for the boxes' and ellipses' record fields
+        // in the lane for the boxes' and ellipses' record fields.  Each round
+        // of kStageUnroll fields per lane issues all its loads (references,
+        // previous fields, then parameters) before any store: the stores to
+        // fval may alias the inputs as far as the compiler knows, so a
+        // load-store-load loop would wait out one memory latency per field.
+        constexpr int kStageUnroll = 4;
         double v0 = 0.0, b0 = 0.0;
         double vabs = 0.0;    // SERIES: sum of |v_i| over this lane's sine coefficients
+        double ylo = __builtin_huge_val(), yhi = -__builtin_huge_val();   // GCART: extent of y+ and y-
         int idx0 = -1;
         bool changed = false;
-        for (int i = lane; i < nf; i += 64) {
-            const sg_field r = sp.fref[pr.f0 + i];
-            double v = r.a;
-            if (r.idx >= 0) {
-                double pv = sp.p[r.idx];
-                if (r.idx == sp.pert_idx) pv += delta;
-                v = r.a + r.b * pv;
+        const bool cmp = sp.fprev != nullptr && var == 0;
+        for (int base = 0; base < nf; base += 64 * kStageUnroll) {
+            sg_field r[kStageUnroll];
+            double prev[kStageUnroll], pv[kStageUnroll];
+#pragma unroll
+            for (int k = 0; k < kStageUnroll; ++k) {
+                const int i = base + k * 64 + lane;
+                r[k] = (i < nf) ? sp.fref[pr.f0 + i] : sg_field{0.0, 0.0, -1};
+                prev[k] = (cmp && i < nf) ? sp.fprev[pr.f0 + i] : 0.0;
             }
-            fv[pr.f0 + i] = v;
-            // bitwise comparison (a NaN field always counts as changed)
-            if (sp.fprev != nullptr && var == 0 &&
-                __double_as_longlong(sp.fprev[pr.f0 + i]) != __double_as_longlong(v))
-                changed = true;
-            if (i >= 2 && i < 2 + pr.nvert) vabs += fabs(v);
-            if (i == lane) {
-                v0 = v;
-                idx0 = r.idx;
-                b0 = r.b;
+#pragma unroll
+            for (int k = 0; k < kStageUnroll; ++k) {
+                pv[k] = (r[k].idx >= 0) ? sp.p[r[k].idx] : 0.0;
+                if (r[k].idx >= 0 && r[k].idx == sp.pert_idx) pv[k] += delta;
+            }
+#pragma unroll
+            for (int k = 0; k < kStageUnroll; ++k) {
+                const int i = base + k * 64 + lane;
+                if (i >= nf) break;
+                const double v = (r[k].idx >= 0) ? r[k].a + r[k].b * pv[k] : r[k].a;
+                fv[pr.f0 + i] = v;
+                // bitwise comparison (a NaN field always counts as changed)
+                if (cmp && __double_as_longlong(prev[k]) != __double_as_longlong(v)) changed = true;
+                if (i >= 2 && i < 2 + pr.nvert) {
+                    vabs += fabs(v);
+                    yhi = fmax(yhi, v);
+                } else if (i >= 2 + pr.nvert && i < 2 + 2 * pr.nvert) {
+                    ylo = fmin(ylo, v);
+                }
+                if (i == lane) {
+                    v0 = v;
+                    idx0 = r[k].idx;
+                    b0 = r[k].b;
+                }
             }
         }
         // a plain store (every writer writes 1): an atomic from each of
@@ -152,15 +174,8 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
             for (int o = 32; o > 0; o >>= 1) av += __shfl_xor(av, o, 64);
             const double R = fmax(r2 + av, 0.0) + pr.reach0;
             b = make_double4(r0 - R, r0 + R, r1 - R, r1 + R);
-        } else {  // GCART
-            const int M = pr.nvert;
-            double ymax = -inf, ymin = inf;
-            for (int j = lane; j < M; j += 64) {
-                ymax = fmax(ymax, resolve(pr.f0 + 2 + j));
-                ymin = fmin(ymin, resolve(pr.f0 + 2 + M + j));
-            }
-            ymax = wave_max(ymax);
-            ymin = wave_min(ymin);
+        } else {  // GCART: y+ are fields 2 .. M + 1, y- fields M + 2 .. 2 M + 1 (resolved above)
+            const double ymax = wave_max(yhi), ymin = wave_min(ylo);
             b = make_double4(r0 - pr.reach0, r1 + pr.reach0, ymin - pr.reach1, ymax + pr.reach1);
         }
         // the record, written by the lanes together: the primitive's dwords,
@@ -203,15 +218,31 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         }
         uint32_t mask[kGroup] = {0, 0, 0, 0};
         bool binary[kGroup] = {true, true, true, true};
+        // every class's bounds resolved before the first table store (one
+        // chain of loads, not one per class)
+        double clo[kMaxClasses], chi[kMaxClasses];
+        bool cwp[kMaxClasses];
+#pragma unroll
+        for (int c = 0; c < kMaxClasses; ++c) {
+            clo[c] = chi[c] = 0.0;
+            cwp[c] = false;
+            if (c < sp.nclass && sp.cls[c].bounded) {
+                clo[c] = resolve(sp.cls[c].flo);
+                chi[c] = resolve(sp.cls[c].fhi);
+                cwp[c] = sp.fref[sp.cls[c].flo].idx >= 0 || sp.fref[sp.cls[c].fhi].idx >= 0;
+            }
+        }
         for (int c = 0; c < sp.nclass; ++c) {
             const DevClass cl = sp.cls[c];
             double lo = 0.0, hi = 0.0;
             bool wparam = false;
-            if (cl.bounded) {
-                lo = resolve(cl.flo);
-                hi = resolve(cl.fhi);
-                wparam = sp.fref[cl.flo].idx >= 0 || sp.fref[cl.fhi].idx >= 0;
-            }
+#pragma unroll
+            for (int k = 0; k < kMaxClasses; ++k)
+                if (k == c) {
+                    lo = clo[k];
+                    hi = chi[k];
+                    wparam = cwp[k];
+                }
             double* zt = sp.ztab[var] + 3 * (((int64_t)comp * sp.nclass + c) * sp.nw + wb);
 #pragma unroll
             for (int q = 0; q < kGroup; ++q) {
