@@ -31,6 +31,21 @@ __device__ __forceinline__ float dpp_add(float v) {
     const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
     return v + __int_as_float(moved);
 }
+// One exchange stage of a reduce-scatter over a 16-lane row: a[0 .. 2H) hold
+// the lane's values for 2H terms; the lane keeps the half its H bit selects,
+// adds the partner's values for that half (the partner, reached by the DPP
+// control CTRL, has the other H bit) and leaves them in a[0 .. H).
+template <int H, int CTRL>
+__device__ __forceinline__ void row_scatter_sum(float (&a)[16], int lane) {
+    const bool hi = (lane & H) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const float keep = hi ? a[H + j] : a[j];
+        const float send = hi ? a[j] : a[H + j];
+        a[j] = keep + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xF, 0xF, false));
+    }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
     v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
     v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
@@ -892,17 +907,16 @@ __device__ __forceinline__ void polar2d_partials(const KParams& P, const DevPrim
 // Partials of the taper's sine-series boundary, times the column sums, over
 // the kBlock samples of the tile handled by this wavefront: the x-range pair
 // like a Rect1D, and d F / d v_i = (d F / d f) envelope(x) sin(i phi), the
-// sines by repeated FP32 rotation (error linear in i), one reduction per term;
-// a wavefront whose samples all have d F / d f = 0 skips the terms.
+// sines by repeated FP32 rotation (error linear in i), the terms reduced 16 at
+// a time; a wavefront whose samples all have d F / d f = 0 skips the terms.
 template <int SIGS, int Q>
 __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim& pr, const float* sAc,
                                                 const SampleLat& L, int qbase) {
     const int lane = threadIdx.x & 63;
     const double* fv = P.fval;
     const double* c = P.consts + pr.c0;
-    const int fend = pr.f0 + 2 + pr.nvert;
-    FieldWin fw;          // xs, xe and the first 62 terms; later terms 64 at a time
-    load_win(P, fw, pr.f0, fend);
+    FieldWin fw;          // xs, xe
+    load_win(P, fw, pr.f0, pr.f0 + 2);
     float w[Q], s1[Q], c1[Q];
     float sxs = 0.0f, sxe = 0.0f;
     bool any = false;
@@ -942,18 +956,36 @@ __device__ __forceinline__ void series_partials(const KParams& P, const DevPrim&
         si[q] = s1[q];
         ci[q] = c1[q];
     }
-    for (int i = 0; i < pr.nvert; ++i) {
-        float acc = 0.0f;
+    // the terms 16 at a time: each lane forms its products for 16 terms, a
+    // reduce-scatter over each 16-lane row (four DPP exchanges, one term
+    // index bit each) leaves term (lane mod 16)'s row sum in the lane, two
+    // cross-row exchanges complete the wavefront sums, and lanes 0-15 add
+    // their terms together (about 3 instructions per term where a wavefront
+    // reduction and an atomic each took about 15)
+    for (int i0 = 0; i0 < pr.nvert; i0 += 16) {
+        const int term = i0 + (lane & 15);
+        sg_field r{0.0, 0.0, -1};
+        if (lane < 16 && term < pr.nvert) r = P.fref[pr.f0 + 2 + term];
+        float a[16];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            acc += w[q] * si[q];
-            const float sn = si[q] * c1[q] + ci[q] * s1[q];
-            ci[q] = ci[q] * c1[q] - si[q] * s1[q];
-            si[q] = sn;
+        for (int k = 0; k < 16; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                acc += w[q] * si[q];
+                const float sn = si[q] * c1[q] + ci[q] * s1[q];
+                ci[q] = ci[q] * c1[q] - si[q] * s1[q];
+                si[q] = sn;
+            }
+            a[k] = acc;
         }
-        const int f = pr.f0 + 2 + i;
-        if (f >= fw.base + 64) load_win(P, fw, f, fend);
-        emit_win(P, fw, f, acc);
+        row_scatter_sum<8, 0x140>(a, lane);    // row_mirror: lane i <-> 15 - i
+        row_scatter_sum<4, 0x141>(a, lane);    // row_half_mirror: i <-> 7 - i within 8
+        row_scatter_sum<2, 0x1B>(a, lane);     // quad_perm [3,2,1,0]
+        row_scatter_sum<1, 0xB1>(a, lane);     // quad_perm [1,0,3,2]
+        float tot = a[0] + __shfl_xor(a[0], 16, 64);
+        tot += __shfl_xor(tot, 32, 64);
+        if (r.idx >= 0 && tot != 0.0f) grad_add(P, (int)r.idx, r.b * (double)tot);
     }
 }
 

@@ -635,6 +635,13 @@ def make_taper_sine_small(seed=BASE_SEED + 16):
                            y_m=0.607, amp=0.03)
 
 
+def make_taper_sine_small37(seed=BASE_SEED + 17):
+    """The small sine taper with 37 terms: the gradient kernel reduces the
+    terms 16 at a time, so this spans two full groups and a partial one."""
+    return make_taper_sine(seed, nx=70, ny=30, nz=10, nterm=37, w_in=0.2, w_out=0.7, x_a=0.213, x_b=2.413,
+                           y_m=0.607, amp=0.03)
+
+
 def make_psgc_small(seed=BASE_SEED + 14, **kw):
     return make_psgc(seed, nside=3, nx=31, ny=29, nz=12, **kw)
 
@@ -832,6 +839,7 @@ CONFIGS = {
     "crowd3": make_crowd, "many2": make_many,
     "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
     "taper3_sine": make_taper_sine, "taper3_sine_small": make_taper_sine_small,
+    "taper3_sine_small37": make_taper_sine_small37,
     "levels2": lambda: make_levels(dim=2), "levels3": lambda: make_levels(dim=3),
     "levels2_deep": lambda: make_levels(dim=2, deep=True),
     "blazed": make_blazed, "blazed_small": make_blazed_small,
