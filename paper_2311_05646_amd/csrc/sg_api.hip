@@ -527,6 +527,7 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
     // device primitive records (primitives of the tree only, in index order)
     std::vector<DevPrim> prims;
     std::vector<GSeg> gseg;     // piecewise-linear boundaries: segment of every u-sample center
+    std::map<std::string, int32_t> cgroups;     // Fourier coefficient fields (bytes) -> first primitive
     for (int i = 0; i < d->nprim; ++i) {
         if (!used[i]) continue;
         const sg_prim_desc& p = d->prims[i];
@@ -541,6 +542,13 @@ extern "C" sg_status sg_scene_create(sg_ctx* ctx, const sg_scene_desc* d, sg_sce
             return sigma_cut(sgm.kind) / k;
         };
         r.gs0 = -1;
+        if (p.type == SG_PRIM_POLAR) {
+            std::string key(reinterpret_cast<const char*>(&p.nvert), sizeof(p.nvert));
+            key.append(reinterpret_cast<const char*>(d->fields + p.field_off + 3), 2 * p.nvert * sizeof(sg_field));
+            auto it = cgroups.find(key);
+            r.cgrp = it != cgroups.end() ? it->second : (int32_t)prims.size();
+            if (it == cgroups.end()) cgroups.emplace(std::move(key), r.cgrp);
+        }
         if (p.type == SG_PRIM_GCART) {
             // largest j in [0, M-2] with x_j <= x (0 left of the first vertex),
             // and t = (x - x_j) / (x_{j+1} - x_j) clamped to [0, 1]

@@ -703,36 +703,150 @@ __device__ __forceinline__ void polar_emit(const KParams& P, const FieldWin& w, 
 }
 
 // A wavefront's per-lane sums of the Fourier-coefficient partials over the
-// candidates it has processed, while they reference the same parameters (the
-// global shape coefficients of a lattice of scatterers): one reduction per
-// coefficient per wavefront instead of one per candidate.  kw is the first
-// such candidate's field window (its coefficient lanes are the key); n = 0:
+// candidates it has processed, while they are of one coefficient group (the
+// same coefficient fields: the global shape coefficients of a lattice of
+// scatterers): one reduction per coefficient per wavefront instead of one
+// per candidate.  The group's coefficient values (coef, one per lane) and
+// field window (kw, its coefficient lanes) are read once per group; n = 0:
 // empty.  Orders above kAccN take the per-candidate reductions.
 constexpr int kAccN = 6;
 struct PolarAcc {
     float c[kAccN], s[kAccN];
-    int n;
+    int n, grp;
+    float coef;
     FieldWin kw;
 };
 __device__ __forceinline__ void polar_acc_clear(PolarAcc& a) { a.n = 0; }
 
-// Reduces and emits the accumulated sums (then empty).
+// Reduces and emits the accumulated sums (then empty): the 2 kAccN sums of
+// every lane in one reduce-scatter, after which lane l < 2 kAccN holds sum l
+// (c_1..c_kAccN, then s_1..s_kAccN) and emits it as polar_emit would: into
+// the block's LDS slot of its coefficient when the slot holds, or can be
+// claimed for, its parameter, else to grad.
 __device__ __forceinline__ void polar_acc_flush(const KParams& P, PolarAcc& a, double* s_pacc, int* s_pkey) {
     const int N = a.n;
     if (N == 0) return;
+    const int lane = threadIdx.x & 63;
+    float v[16];
 #pragma unroll
-    for (int n = 1; n <= kAccN; ++n) {
-        if (n <= N) {
-            polar_emit(P, a.kw, a.kw.base + 2 + n, n - 1, a.c[n - 1], s_pacc, s_pkey);
-            polar_emit(P, a.kw, a.kw.base + 2 + N + n, N + n - 1, a.s[n - 1], s_pacc, s_pkey);
+    for (int k = 0; k < 16; ++k) v[k] = k < kAccN ? a.c[k] : (k < 2 * kAccN ? a.s[k - kAccN] : 0.0f);
+    row_scatter_sum<8, 0x140>(v, lane);
+    row_scatter_sum<4, 0x141>(v, lane);
+    row_scatter_sum<2, 0x1B>(v, lane);
+    row_scatter_sum<1, 0xB1>(v, lane);
+    float tot = v[0] + __shfl_xor(v[0], 16, 64);
+    tot += __shfl_xor(tot, 32, 64);
+    const int l = lane & 15;
+    const int n = l < kAccN ? l : l - kAccN;                // order - 1
+    const int slot = l < kAccN ? n : N + n;                  // position among the 2 N coefficients
+    const bool valid = lane < 2 * kAccN && n < N;
+    const int src = 3 + (valid ? slot : 0);                  // the coefficient's lane in the window
+    const int idx = __shfl(a.kw.idx, src, 64);
+    const double b = __shfl(a.kw.b, src, 64);
+    if (valid && idx >= 0 && tot != 0.0f) {
+        const double val = b * (double)tot;
+        if (P.fx) {       // deterministic mode: no LDS combining (FP64 LDS atomics add in any order)
+            grad_add(P, idx, val);
+        } else {
+            int k = s_pkey[slot];
+            if (k == -2) {
+                const int old = atomicCAS(&s_pkey[slot], -2, idx);
+                k = (old == -2) ? idx : old;
+            }
+            if (k == idx) atomicAdd(&s_pacc[slot], val);
+            else atomicAdd(grad_copy(P) + idx, val);
         }
     }
     a.n = 0;
 }
 
-template <int SIGS, bool ACC>
+// polar_partials into the running sums (order N <= kAccN): x0 y0 R0 and
+// their references come from the staged record, the coefficients from the
+// group's registers; one sample at a time, the radius recurrence keeps each
+// cos / sin (n theta) for the coefficient partials once d F / d (R - r) is
+// known, so the rotation runs once per sample.
+template <int SIGS>
+__device__ __forceinline__ void polar_partials_acc(const KParams& P, const PrimRec& cr, const float* sAc,
+                                                   const SampleLat& L, double* s_pacc, int* s_pkey, PolarAcc& acc) {
+    constexpr int Q = kBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const DevPrim& pr = cr.pr;
+    const int N = uniform_int(pr.nvert);
+    const int grp = uniform_int(pr.cgrp);
+    if (acc.n == 0 || acc.grp != grp) {
+        polar_acc_flush(P, acc, s_pacc, s_pkey);
+        load_win(P, acc.kw, pr.f0, pr.f0 + 3 + 2 * N);
+        acc.coef = lane < 2 * N ? (float)P.fval[pr.f0 + 3 + lane] : 0.0f;
+        acc.n = N;
+        acc.grp = grp;
+#pragma unroll
+        for (int n = 0; n < kAccN; ++n) acc.c[n] = acc.s[n] = 0.0f;
+    }
+    const float k0 = (float)pr.k0;
+    float an[kAccN], bn[kAccN];
+#pragma unroll
+    for (int n = 0; n < kAccN; ++n) {
+        const int l = max(min(n, N - 1), 0);
+        an[n] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc.coef), l));
+        bn[n] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc.coef), N + l));
+    }
+    const double x0 = cr.f[0], y0 = cr.f[1];
+    const float R0 = (float)cr.f[2];
+    float sx = 0.0f, sy = 0.0f, sR = 0.0f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int t = q * 64 + lane;
+        const float av = sAc[t];
+        if (__ballot(av != 0.0f) == 0) continue;
+        float c1 = 1.0f, s1 = 0.0f, rv = 0.0f, iv = 0.0f;
+        {
+            const float dx = (float)(L.uc(t) - x0), dy = (float)(L.vc(t) - y0);
+            rv = sqrtf(dx * dx + dy * dy);
+            iv = rv > 0.0f ? 1.0f / rv : 0.0f;
+            if (rv > 0.0f) {
+                c1 = dx * iv;
+                s1 = dy * iv;
+            }
+        }
+        float cs[kAccN], sn[kAccN];
+        float R = R0, dR = 0.0f, cn = 1.0f, snn = 0.0f;
+#pragma unroll
+        for (int n = 1; n <= kAccN; ++n) {
+            const float crt = cn * c1 - snn * s1;
+            snn = snn * c1 + cn * s1;
+            cn = crt;
+            cs[n - 1] = cn;
+            sn[n - 1] = snn;
+            if (n <= N) {
+                R -= an[n - 1] * cn + bn[n - 1] * snn;
+                dR += (float)n * (an[n - 1] * snn - bn[n - 1] * cn);
+            }
+        }
+        float gg = 0.0f;
+        if (av != 0.0f) {
+            gg = av * k0 * sig_d32(pr.sk0, k0 * (R - rv));     // a * d F / d (R - r)
+            if (rv > 0.0f) {
+                sx += gg * (dR * s1 * iv + c1);
+                sy += gg * (-dR * c1 * iv + s1);
+            }
+            sR += gg;
+        }
+#pragma unroll
+        for (int n = 0; n < kAccN; ++n) {
+            if (n < N) {
+                acc.c[n] -= gg * cs[n];
+                acc.s[n] -= gg * sn[n];
+            }
+        }
+    }
+    emit_ref(P, cr.fidx[0], cr.fb[0], sx);
+    emit_ref(P, cr.fidx[1], cr.fb[1], sy);
+    emit_ref(P, cr.fidx[2], cr.fb[2], sR);
+}
+
+template <int SIGS>
 __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& pr, const float* sAc,
-                                               const SampleLat& L, double* s_pacc, int* s_pkey, PolarAcc& acc) {
+                                               const SampleLat& L, double* s_pacc, int* s_pkey) {
     constexpr int Q = kBlock / 64;
     const int lane = threadIdx.x & 63;
     const int N = uniform_int(pr.nvert);
@@ -807,36 +921,6 @@ __device__ __forceinline__ void polar_partials(const KParams& P, const DevPrim& 
     for (int q = 0; q < Q; ++q) {
         cn[q] = 1.0f;
         sn[q] = 0.0f;
-    }
-    if (ACC && N <= kAccN) {
-        // into the wavefront's running sums when the coefficients reference the
-        // same parameters as the ones there (else those go out first)
-        const bool same = acc.n == N &&
-                          __ballot(lane >= 3 && lane < 3 + 2 * N && (w.idx != acc.kw.idx || w.b != acc.kw.b)) == 0;
-        if (!same) {
-            polar_acc_flush(P, acc, s_pacc, s_pkey);
-            acc.n = N;
-            acc.kw = w;
-#pragma unroll
-            for (int n = 0; n < kAccN; ++n) acc.c[n] = acc.s[n] = 0.0f;
-        }
-#pragma unroll
-        for (int n = 1; n <= kAccN; ++n) {
-            if (n <= N) {
-                float pc = 0.0f, ps = 0.0f;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const float c = cn[q] * c1[q] - sn[q] * s1[q];
-                    sn[q] = sn[q] * c1[q] + cn[q] * s1[q];
-                    cn[q] = c;
-                    pc -= g[q] * cn[q];
-                    ps -= g[q] * sn[q];
-                }
-                acc.c[n - 1] += pc;
-                acc.s[n - 1] += ps;
-            }
-        }
-        return;
     }
     for (int n = 1; n <= N; ++n) {
         float pc = 0.0f, ps = 0.0f;
@@ -1091,7 +1175,13 @@ __device__ __forceinline__ void block_partials(const KParams& P, const PrimRec& 
         if (type == SG_PRIM_POLAR) {
             // the running sums only in the Fourier feature set (the catch-all
             // kernel has no registers to spare for them)
-            polar_partials<SIGS, TYPES == (T_BOX | T_POLAR)>(P, pr, sAc, L, s_pacc, s_pkey, acc);
+            if constexpr (TYPES == (T_BOX | T_POLAR)) {
+                if (pr.nvert <= kAccN) {
+                    polar_partials_acc<SIGS>(P, cr, sAc, L, s_pacc, s_pkey, acc);
+                    return;
+                }
+            }
+            polar_partials<SIGS>(P, pr, sAc, L, s_pacc, s_pkey);
             return;
         }
     }

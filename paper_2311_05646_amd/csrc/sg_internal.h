@@ -63,7 +63,13 @@ struct DevPrim {
     int32_t fv0, fv1;      // BOX: fields of the v bounds
     int32_t sk0, sm0;      // sigma kind / k mode of argument 0 (u bound, boundary, x-range)
     int32_t sk1, sm1;      // sigma kind / k mode of argument 1 (v bound, GCART y boundary)
-    int32_t gs0;           // GCART: first entry of its segment table (component 0, u = 0); else -1
+    union {
+        int32_t gs0;       // GCART: first entry of its segment table (component 0, u = 0)
+        // POLAR: its coefficient group, the index of the first primitive whose
+        // 2 N Fourier coefficient fields are the same references (a, b, idx
+        // alike: the same values and parameters)
+        int32_t cgrp;
+    };                     // others: -1
     double k0, k1;         // k_r (LOCAL) or k (FIXED)
     double reach0, reach1; // support half-width of each argument (um), for the support boxes
     double ax, ay;         // ELLIPSE aspect
@@ -81,8 +87,9 @@ struct GSeg {
 
 // Per-call copy of a primitive as the in-plane and partials kernels read it
 // (written by k_stage): the record, its support box (u_lo, u_hi, v_lo, v_hi),
-// and for boxes and ellipses the resolved values of their in-plane fields
-// (boxes: u0 u1 v0 v1; ellipses: x0 y0 r) with the parameter index (-1:
+// and for boxes, ellipses and polar shapes the resolved values of their
+// leading fields (boxes: u0 u1 v0 v1; ellipses: x0 y0 r; Fourier radius:
+// x0 y0 R0; Polar2D: x0 y0 R delta) with the parameter index (-1:
 // constant) and scale of each.
 struct PrimRec {
     DevPrim pr;

@@ -185,8 +185,10 @@ __global__ __launch_bounds__(256) void k_stage(const StageParams sp) {
         if (lane < kPrimDw)
             reinterpret_cast<uint32_t*>(&rec->pr)[lane] = reinterpret_cast<const uint32_t*>(sp.prims + pi)[lane];
         if (lane < 4) {
-            const bool rf = pr.type == SG_PRIM_BOX || pr.type == SG_PRIM_ELLIPSE;
-            const bool live = rf && (pr.type == SG_PRIM_BOX || lane < 3);
+            // boxes u0 u1 v0 v1, ellipses x0 y0 r, Fourier radius x0 y0 R0, Polar2D x0 y0 R delta
+            const bool rf = pr.type == SG_PRIM_BOX || pr.type == SG_PRIM_ELLIPSE || pr.type == SG_PRIM_POLAR ||
+                            pr.type == SG_PRIM_POLAR2D;
+            const bool live = rf && (pr.type == SG_PRIM_BOX || pr.type == SG_PRIM_POLAR2D || lane < 3);
             rec->f[lane] = live ? kv : 0.0;
             rec->fb[lane] = live ? kb : 0.0;
             rec->fidx[lane] = live ? kidx : -1;
