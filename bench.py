@@ -464,6 +464,28 @@ def _oracle_slice(i0_i1):
     return g, time.perf_counter() - t, E2.size
 
 
+def hbm_reference(api, torch, nbytes, reps=10):
+    """A plain streaming copy (the library's sg_util_copy: 16-byte loads and
+    stores, grid-stride) of nbytes, timed with events: what one pass of
+    reads and writes of that size reaches on this GPU, beside the 8 TB/s
+    of the datasheet."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        api.util_copy(dst, src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        api.util_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"copy_bytes": nbytes, "copy_us": us, "copy_GBps": 2 * nbytes / (us * 1e-6) / 1e9,
+            "kernel": "sg_util_copy (k_copy, 4096 x 256 threads, uint4 grid-stride)"}
+
+
 def cpu_baseline(cfg, cols=25, single_chunks=24, reps=3):
     """The oracle (FP64 NumPy, not tuned) on this host: the taper split into
     x-slabs of `cols` columns (a uniform x lattice, so a slab's samples and
@@ -602,6 +624,11 @@ def main():
                                    res3["ms_per_step"])}
     del E3, A3, sc3
     torch.cuda.empty_cache()
+
+    # ---- a plain copy of the VJP's byte count, as a measured reference
+    ref = hbm_reference(api, torch, int(res3["roofline"]["algorithmic_bytes_per_launch"]) // 2 // 16 * 16)
+    ref["vjp_over_copy"] = res3["roofline"]["achieved"] / ref["copy_GBps"]
+    out["hbm_reference"] = ref
 
     # ---- the grating coupler and the blazed grating, same structure
     for name in ("c4", "c2"):
