@@ -475,6 +475,14 @@ def psgc_scene(rng, nside=40, nx=None, ny=None, nz=80, pitch=0.25, r_lo=0.06, r_
 
     if shared:
         cs, ss = coeffs()
+    if shared == "mixed":
+        # three coefficient sets over the lattice: the global set, the same
+        # parameters scaled by -1/2 with a constant offset, and a global
+        # set of order 3 of its own
+        sets = [(cs, ss), ([(0.001, -0.5, f[2]) for f in cs], [(-0.001, -0.5, f[2]) for f in ss])]
+        q = len(p)
+        p.extend(rng.normal(0.0, coef / n) for n in list(range(1, 4)) * 2)
+        sets.append(([P(q + i) for i in range(3)], [P(q + 3 + i) for i in range(3)]))
     for i in range(nside):
         for j in range(nside):
             cx = pitch / 2 + pitch * i + rng.uniform(-jitter, jitter)
@@ -483,6 +491,8 @@ def psgc_scene(rng, nside=40, nx=None, ny=None, nz=80, pitch=0.25, r_lo=0.06, r_
             r0 = P(len(p) - 1)
             if not shared:
                 cs, ss = coeffs()
+            elif shared == "mixed":
+                cs, ss = sets[(i + 2 * j) % 3]
             prims.append(polar(K(cx), K(cy), r0, cs, ss, z=zr, sig=("sigmoid", "fixed", k)))
     scene = {"name": "psgc", "dim": 3, "nodes": [X, Y, Z], "components": ("x", "y", "z"),
              "eps_bg": EPS_SIO2, "eps_fg": EPS_SI, "n_params": len(p), "prims": prims,
@@ -648,6 +658,13 @@ def make_psgc_small(seed=BASE_SEED + 14, **kw):
 
 def make_psgc_small_local(seed=BASE_SEED + 15):
     return make_psgc_small(seed, shared=False)
+
+
+def make_psgc_small_mixed(seed=BASE_SEED + 18):
+    """Three coefficient sets interleaved over a 6 x 6 lattice (16 x 16 tiles
+    meet several scatterers, so the gradient kernel's coefficient groups
+    change between a wavefront's candidates)."""
+    return make_psgc(seed, nside=6, nx=60, ny=60, nz=12, shared="mixed")
 
 
 def make_zoo(seed=BASE_SEED + 20, dim=3, root="union"):
@@ -838,6 +855,7 @@ CONFIGS = {
     "c2_small": make_c2_small, "c3_small": make_c3_small, "c4_small": make_c4_small,
     "crowd3": make_crowd, "many2": make_many,
     "psgc3": make_psgc, "psgc3_small": make_psgc_small, "psgc3_small_local": make_psgc_small_local,
+    "psgc3_small_mixed": make_psgc_small_mixed,
     "taper3_sine": make_taper_sine, "taper3_sine_small": make_taper_sine_small,
     "taper3_sine_small37": make_taper_sine_small37,
     "levels2": lambda: make_levels(dim=2), "levels3": lambda: make_levels(dim=3),

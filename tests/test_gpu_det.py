@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 # gcart bucket flushes (zoo, c4), polar coefficient slots (psgc3), dense
 # series partials (taper), the levels chain, crowded tiles
 CASES = ["c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo2_difference", "crowd3",
-         "psgc3_small", "psgc3_small_local", "taper3_sine_small", "taper3_sine_small37", "levels3"]
+         "psgc3_small", "psgc3_small_local", "psgc3_small_mixed", "taper3_sine_small", "taper3_sine_small37", "levels3"]
 GRAD_TOL = 1e-4
 ORDER_TOL = 1e-6
 

@@ -16,7 +16,7 @@ from tests.gpu_util import api, config, to_dev
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ["c3_small", "c4_small", "psgc3_small", "taper3_sine_small", "zoo3_union", "zoo2_deep", "blazed_small",
+NAMES = ["c3_small", "c4_small", "psgc3_small", "psgc3_small_mixed", "taper3_sine_small", "zoo3_union", "zoo2_deep", "blazed_small",
          "levels2", "crowd3", "many2", "polar2d_small"]
 
 

@@ -13,8 +13,9 @@ from paper_2311_05646_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 # crowd3: one tile holds more candidates than a staging round; many2: more
-# primitives than one candidate scan pass; psgc3_small(_local): Fourier-radius
-# scatterers with global (shared) or per-scatterer shape coefficients;
+# primitives than one candidate scan pass; psgc3_small(_local, _mixed):
+# Fourier-radius scatterers with global (shared), per-scatterer, or three
+# interleaved sets of shape coefficients (one of them the global set scaled);
 # taper3_sine_small(37): the taper's sine-series boundary (every parameter
 # reaches every column of it; 37 terms span three groups of the kernel's
 # 16-term reduction, the last one partial); levels2/3: the non-binary union over four material sets;
@@ -25,7 +26,7 @@ pytestmark = pytest.mark.gpu
 # shapes (alpha = 3, 4, 5, sigmoid and linear) etched into a slab, 3D and 2D
 CASES = ["c1", "c2_small", "c3_small", "c4_small", "zoo2_union", "zoo3_union", "zoo3_difference",
          "zoo2_intersection", "zoo3_intersection", "zoo2_difference", "crowd3", "many2",
-         "psgc3_small", "psgc3_small_local", "taper3_sine_small", "taper3_sine_small37", "levels2",
+         "psgc3_small", "psgc3_small_local", "psgc3_small_mixed", "taper3_sine_small", "taper3_sine_small37", "levels2",
          "levels3", "blazed_small", "zoo2_deep", "zoo3_deep", "levels2_deep", "polar2d_small", "polar2d_small2"]
 EPS_TOL = 1e-6
 GRAD_TOL = 1e-4
