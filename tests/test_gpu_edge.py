@@ -1,6 +1,8 @@
 """Degenerate inputs through the C-ABI against the oracle: shapes that miss
 the grid (no candidate in any tile), a scene without parameters, a one-cell
-grid, a one-step column, an inverted (empty) box and a zero-radius circle."""
+grid, a one-step column, an inverted (empty) box and a zero-radius circle;
+and the boundary counts of the gradient kernel's grouped reductions (sine
+series of 1, 16 and 17 terms, shared Fourier coefficients of order 1, 6, 7)."""
 import numpy as np
 import pytest
 
@@ -71,3 +73,23 @@ def test_empty_box_and_zero_radius():
              W.ellipse(W.P(2), W.P(3), W.P(4), z=(W.K(0.0), W.K(0.15)), sig=("linear", "fixed", 40.0)),
              W.box(x=(W.K(0.02), W.K(0.1)), y=(W.K(0.13), W.P(5)), z=(W.K(0.0), W.K(0.15)))]
     _check(_scene(prims, 20, 12, 6, 6), np.array([0.3, 0.12, 0.21, 0.14, 0.0, 0.23]))
+
+
+@pytest.mark.parametrize("nterm", [1, 16, 17])
+def test_series_term_counts(nterm):
+    """Sine-series boundaries whose term count is one, exactly one, or just
+    over one group of the gradient kernel's 16-term reduction."""
+    rng = np.random.Generator(np.random.PCG64(300 + nterm))
+    desc, p = W.taper_sine_scene(rng, nx=60, ny=28, nz=6, nterm=nterm, w_in=0.2, w_out=0.6, x_a=0.213,
+                                 x_b=1.313, y_m=0.357, amp=0.03)
+    _check(desc, p)
+
+
+@pytest.mark.parametrize("order", [1, 6, 7])
+def test_fourier_orders_with_shared_coefficients(order):
+    """Fourier scatterers sharing their coefficients at orders 1 and 6 (the
+    gradient kernel's per-wavefront running sums, up to order 6) and 7 (the
+    per-candidate path of the same kernel)."""
+    rng = np.random.Generator(np.random.PCG64(400 + order))
+    desc, p = W.psgc_scene(rng, nside=6, nx=60, ny=60, nz=6, order=order)
+    _check(desc, p)
