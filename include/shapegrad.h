@@ -246,8 +246,12 @@ sg_status eps_grad_vjp_sparse(sg_ctx* ctx, sg_scene* scene, const double* p, int
  * device. */
 sg_status sg_scene_sparse_reads(sg_scene* scene, int64_t* pairs);
 
-/* Reverse mode with an upstream dF/deps: grad_eps is C FP32 planes stored
- * contiguously ([C][Nz][Ny][Nx]); grad_k = sum grad_eps * d eps / d p_k. */
+/* Reverse mode with an upstream dF/deps (the chain rule of Sec. "Automatic
+ * differentiation based acceleration" through the eps map alone, for callers
+ * whose objective reaches eps by other means than eq:1's field product, e.g.
+ * an autograd graph): grad_eps is C FP32 planes stored contiguously
+ * ([C][Nz][Ny][Nx]); grad_k = sum grad_eps * d eps / d p_k.  With grad_eps =
+ * 2 omega Im(E Eadj) it equals eps_grad_vjp up to rounding. */
 sg_status eps_grad_vjp_geps(sg_ctx* ctx, sg_scene* scene, const double* p, int p_on_device,
                             const float* grad_eps, double* grad, int grad_on_device, void* stream);
 
