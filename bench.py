@@ -196,8 +196,8 @@ def fd_baseline(api, scene, p_dev, E, A, cfg, vjp_us, step_ms, reps=2):
 
 
 def time_kernels(api, scene, p_dev, E, A, omega, reps):
-    """Column-kernel times of eps_build, eps_grad_vjp and eps_grad_vjp_sparse,
-    each call repeated back to back (interleaving them adds the write-back of
+    """Column-kernel times of eps_build, eps_grad_vjp, eps_grad_vjp_sparse and
+    eps_grad_vjp_geps, each call repeated back to back (interleaving them adds the write-back of
     eps to the VJP's HBM traffic).  The sparse VJP reads the fields only where
     d eps / d p can be nonzero: its share of the samples and its rate over the
     bytes it needs are reported apart from the dense kernel's bandwidth."""
@@ -226,10 +226,20 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
     for _ in range(reps):
         api.eps_grad_vjp_sparse(scene, p_dev, E, A, omega, grad=gs)
     torch.cuda.synchronize()
+    # the eps-upstream gradient (the autograd op's backward) on dF/deps =
+    # 2 omega Im(E Eadj): the same gradient from a 4-byte plane
+    geps = ((2.0 * omega) * (E * A).imag).float().contiguous()
+    gg = torch.empty_like(g)
+    for _ in range(reps):
+        api.eps_grad_vjp_geps(scene, p_dev, geps, grad=gg)
+    torch.cuda.synchronize()
     ve, ne = scene.kernel_time("eps")
     vv, nv = scene.kernel_time("vjp")
     vs, ns = scene.kernel_time("sparse")
+    vg, ng = scene.kernel_time("geps")
     scene.set_timing(False)
+    geps_rel = float(torch.linalg.norm(gg - g) / torch.linalg.norm(g))
+    del geps
     m = scene.shape[0] * scene.shape[1] * scene.shape[2] * scene.shape[3]
     return {"vjp_us": 1e3 * vv / nv, "vjp_GBps": 16.0 * m / (vv / nv * 1e-3) / 1e9,
             "vjp_frac_of_peak": 16.0 * m / (vv / nv * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -237,7 +247,9 @@ def time_kernels(api, scene, p_dev, E, A, omega, reps):
             "sparse": {"us": 1e3 * vs / ns, "speedup_vs_dense_vjp": vv / nv / (vs / ns),
                        "samples_read": reads, "read_fraction": reads / m,
                        "GBps_of_bytes_read": 16.0 * reads / (vs / ns * 1e-3) / 1e9,
-                       "rel_l2_vs_dense": sparse_rel}}
+                       "rel_l2_vs_dense": sparse_rel},
+            "geps": {"us": 1e3 * vg / ng, "GBps": 4.0 * m / (vg / ng * 1e-3) / 1e9,
+                     "frac_of_peak": 4.0 * m / (vg / ng * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_vjp": geps_rel}}
 
 
 def time_deterministic(api, scene, p_dev, E, A, omega, reps):
