@@ -30,9 +30,11 @@ def _pair(name, det):
 
 # the first input of each sequence is larger than the second; zoo3_union has
 # p-dependent extrusion tables and the spread accumulation, psgc3_small shares
-# its shape coefficients among scatterers
+# its shape coefficients among scatterers, psgc3_small_mixed interleaves three
+# coefficient sets, taper3_sine_small37 reduces 37 sine terms in groups of 16
 @pytest.mark.parametrize("det", [False, True])
-@pytest.mark.parametrize("seq", [("zoo3_union", "c3_small"), ("c4_small", "psgc3_small")])
+@pytest.mark.parametrize("seq", [("zoo3_union", "c3_small"), ("c4_small", "psgc3_small"),
+                                 ("psgc3_small_mixed", "taper3_sine_small37")])
 def test_noalloc_equals_vjp_on_two_calls(seq, det):
     A_ = api()
     print(f"[noalloc] {seq} deterministic={det}", flush=True)
