@@ -1374,8 +1374,13 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
     __shared__ int s_pkey[(VJP && (TYPES & T_POLAR)) ? kPolarSlots : 1];
     const int tid = threadIdx.x, wave = tid >> 6;
 
-    const int seg = b % P.nseg;
-    const TileGeom G = tile_geom<MODE == MODE_EPS>(P, b / P.nseg);     // linear tiles: eps_build only
+    // block b: tile b mod ntile of segment b / ntile, so the blocks in flight
+    // read one compact window (every tile at the same column steps; the 2D
+    // grating's 16 segments per tile: VJP 30.5 -> 28.5 us against segment-
+    // fastest order)
+    const int ntile = P.ncomp * P.tiles_u * P.tiles_v;
+    const int seg = b / ntile, tile = b - seg * ntile;
+    const TileGeom G = tile_geom<MODE == MODE_EPS>(P, tile);     // linear tiles: eps_build only
     const int comp = G.comp;
     const bool act = G.act;
     const int ngw = (P.nw + kGroup - 1) / kGroup;
@@ -1559,7 +1564,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
             if constexpr (EARLY_LISTED) first_loads();
             bool listed = false;
             if (P.tlist != nullptr && !P.linear && __builtin_amdgcn_readfirstlane(P.tlist[0]) == P.tu) {
-                const int32_t* tl = P.tlist + 1 + (int64_t)(b / P.nseg) * (1 + kStageRec);
+                const int32_t* tl = P.tlist + 1 + (int64_t)tile * (1 + kStageRec);
                 const int cnt = __builtin_amdgcn_readfirstlane(tl[0]);
                 if (cnt >= 0) {
                     if (tid < cnt) s_cand[tid] = tl[1 + tid];
@@ -1606,7 +1611,7 @@ __device__ __forceinline__ void column_body(const KParams& P, int b) {
                     // the tile's candidates (s_cand holds them when they fit one staging round)
                     if (b == 0 && tid == 0) P.tlist[0] = P.linear ? -1 : P.tu;
                     if (!P.linear && seg == 0) {
-                        int32_t* tl = P.tlist + 1 + (int64_t)(b / P.nseg) * (1 + kStageRec);
+                        int32_t* tl = P.tlist + 1 + (int64_t)tile * (1 + kStageRec);
                         if (tid == 0) tl[0] = staged_all ? ncand : -1;
                         if (staged_all && tid < ncand) tl[1 + tid] = s_cand[tid];
                     }

@@ -224,7 +224,7 @@ struct KParams {
     const int32_t* chg;
     int32_t gen, nfield;
     // with the planes, each rectangular tile's candidate list: tlist[0] = the
-    // tile width the lists are for (0 or -1: none), then per tile (block / nseg) a
+    // tile width the lists are for (0 or -1: none), then per tile (block mod tiles) a
     // count (-1: more than one staging round) and kStageRec primitive indices
     int32_t* tlist;
 };
