@@ -1254,10 +1254,13 @@ __device__ __forceinline__ TileGeom tile_geom(const KParams& P, int b) {
         span_box(P, ucs, vcs, min(wf, nuv - 1), min(wf + 64, nuv) - 1, T.wulo, T.wuhi, T.wvlo, T.wvhi);
         return G;
     }
-    const int tvi = b % P.tiles_v;
-    b /= P.tiles_v;
+    // row-major tile order: consecutive blocks are side by side in u, so a
+    // range of blocks covers whole rows (taper VJP 131.1 -> 130.5 us against
+    // v first)
     const int tui = b % P.tiles_u;
-    G.comp = b / P.tiles_u;
+    b /= P.tiles_u;
+    const int tvi = b % P.tiles_v;
+    G.comp = b / P.tiles_v;
     const int TU = P.tu;
     G.u = tui * TU + (tid & (TU - 1));
     G.v = tvi * P.tv + tid / TU;
