@@ -1078,13 +1078,14 @@ extern "C" sg_status eps_build(sg_ctx* ctx, sg_scene* s, const double* p, int p_
     if ((rc = stage_p(s, p, p_on_device, st, &dp)) != SG_OK) return rc;
     StageParams sp = stage_params(s, dp);
     // eps_build writes 4 B per sample against the VJP's 16 B read: on short
-    // columns its blocks are shorter than their prologue, and a quarter more
-    // of them measured faster (blazed grating: 18.6 vs 19.4 us).
-    // Linear tiles: every wavefront stores 64 consecutive floats per step, so
+    // columns each segment repeats the tile's prologue for a quarter of the
+    // VJP's bytes, so it aims at half the VJP's blocks (blazed grating, with
+    // the blocks in segment-slowest order: 13.7 us at 384 blocks, 14.5 us at
+    // 960).  Linear tiles: every wavefront stores 64 consecutive floats per step, so
     // whole 128-byte lines leave with the non-temporal stores (a 128 x 2 tile
     // on a 600-wide grid writes 256-byte runs that straddle line boundaries;
     // measured on the taper: 71.6 -> 40.2 us)
-    KParams kp = column_params(s, 960, true);
+    KParams kp = column_params(s, 384, true);
     if (s->fcache && (rc = fcache_prepare(s, sp, kp, st)) != SG_OK) return rc;
     HIP_OK(launch_stage(sp, 1, st));
     kp.out = eps;
